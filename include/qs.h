@@ -1,0 +1,143 @@
+/*
+ * qs.h -- C ABI of the CZ-partition circuit simulator for MI355X (gfx950).
+ *
+ * Method (Chen et al., "64-qubit quantum circuit simulation", arXiv 1802.06952):
+ * every CZ gate that crosses a chosen cut of the qubits is rewritten as
+ * P0 x I + P1 x Z (Sec. 2.1, Eq. 1; Supp. A, Eq. 2), so a circuit with c such
+ * gates is the sum of 2^c copies, each the tensor product of an upper and a
+ * lower half circuit with no entangling gate between them (Supp. A, Eq. 7-8).
+ * The amplitude of an output bitstring x is the sum over copies k of
+ * U_k[u(x)] * L_k[l(x)], where u(x) and l(x) are the bits of x on the upper and
+ * lower qubits (Sec. 2.3.1: sample each half, take the tensor product, add).
+ *
+ * Conventions shared by every call:
+ *   - A circuit is a sequence of layers ("cycles"); each layer holds gates on
+ *     disjoint qubits (Supp. A, the layer graphs G_t = (V_t, E_t)).  Gates:
+ *     h, t, sx (square root of X), sy (square root of Y), cz.
+ *   - Bit q of a bitstring (uint64) is the outcome of qubit q.  Bits >= n must
+ *     be zero.
+ *   - Cut j is the j-th crossing CZ ordered by (layer, upper endpoint id); copy
+ *     k carries bit s_j = (k >> (c-1-j)) & 1 (earliest cut = most significant).
+ *     P_{s_j} acts on the upper endpoint and Z^{s_j} on the lower endpoint.
+ *   - Inside a half, qubits are numbered in ascending global id.
+ *   - Amplitudes are complex64 pairs (re, im) of float; the half states are
+ *     complex64 with FP32 arithmetic on the GPU.
+ *
+ * Errors: every call returns a qs_status; no exception crosses the ABI.  On
+ * failure out-parameters are left untouched, handles stay valid, and
+ * qs_last_error() returns a message for the calling thread.
+ * Ownership: handles are created by qs_* calls and released by the matching
+ * qs_*_free; every input array belongs to the caller and is copied before the
+ * call returns; output arrays belong to the caller.  Device memory belongs to
+ * the plan and is released by qs_plan_free.
+ * Threads: a plan is not thread-safe; different plans may be used from
+ * different threads and streams at the same time.
+ */
+#ifndef QS_H
+#define QS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QS_OK = 0,
+  QS_ERR_ARG = -1,          /* invalid argument (range, null pointer, size) */
+  QS_ERR_PARSE = -2,        /* malformed circuit text */
+  QS_ERR_UNSUPPORTED = -3,  /* valid request this library does not handle */
+  QS_ERR_OOM = -4,          /* device or host allocation failed / over budget */
+  QS_ERR_HIP = -5,          /* a HIP runtime call failed */
+  QS_ERR_STATE = -6         /* call out of order (e.g. bitstrings not registered) */
+} qs_status;
+
+typedef enum {
+  QS_PREC_FP32 = 0,        /* assembly GEMM on FP32 MFMA, FP32 accumulation */
+  QS_PREC_SPLIT_BF16 = 1   /* each FP32 operand split into bf16 hi + lo; hi*hi + hi*lo + lo*hi
+                              on BF16 MFMA with FP32 accumulation */
+} qs_precision;
+
+typedef struct qs_circuit qs_circuit; /* opaque, host memory */
+typedef struct qs_plan qs_plan;       /* opaque, owns device buffers */
+
+/* Tuning knobs; a zero field means "choose automatically". */
+typedef struct {
+  int tile_bits;          /* qubits held per workgroup tile in a full-state pass (6..13) */
+  int coalesce_bits;      /* low qubits always inside a tile (contiguous runs of 2^b amplitudes) */
+  int tail_max_qubits;    /* largest light cone the leaf evaluation accepts (0..10) */
+  int materialize_level;  /* force the last materialised tree level (-1 = cost model) */
+  size_t mem_budget;      /* bytes of device memory the plan may hold for states */
+} qs_options;
+
+/* Message describing the last failed call on this thread ("" if none). */
+const char* qs_last_error(void);
+
+/* Parse circuit text (format: "qubits <n>" then one gate per line,
+ * "<layer> <gate> <q> [<q2>]", '#' comments).  Layers must not decrease and a
+ * qubit may appear once per layer.  n <= 64.  On success *out owns a new
+ * circuit.  Errors: QS_ERR_ARG (null pointers), QS_ERR_PARSE. */
+qs_status qs_load_circuit(const char* text, size_t len, qs_circuit** out);
+
+/* Number of qubits and gates of a parsed circuit (either pointer may be NULL). */
+qs_status qs_circuit_info(const qs_circuit* circ, int* n_qubits, int* n_gates);
+
+void qs_circuit_free(qs_circuit* circ);
+
+/* Build a plan for the bipartition given by upper_mask (bit q set = qubit q in
+ * the upper half V1; Supp. A).  Classifies the crossing CZ gates (the set
+ * E_int of Supp. A), builds the two half programs and uploads nothing yet.
+ * opts may be NULL.  The plan keeps its own copy of the circuit.
+ * Errors: QS_ERR_ARG (mask empty, full, or naming qubits >= n; a half with
+ * more than 34 qubits), QS_ERR_UNSUPPORTED (more than 40 cut gates). */
+qs_status qs_partition(const qs_circuit* circ, uint64_t upper_mask, const qs_options* opts,
+                       qs_plan** out);
+
+/* Sizes of a plan: qubits per half and number of cut gates (copies = 1 << n_cuts). */
+qs_status qs_plan_info(const qs_plan* plan, int* n_upper, int* n_lower, int* n_cuts);
+
+/* JSON description of the plan (cuts, half programs, tree levels, passes),
+ * for tests.  Writes at most cap bytes including the terminating NUL; *needed
+ * receives the full size including the NUL.  buf may be NULL when cap is 0. */
+qs_status qs_plan_dump(const qs_plan* plan, char* buf, size_t cap, size_t* needed);
+
+void qs_plan_free(qs_plan* plan);
+
+/* Simulate the copies k in [copy_begin, copy_end) of both halves on the GPU
+ * and keep, for each, the half amplitudes at the upper and lower parts of the
+ * m bitstrings (host array).  The first call registers the bitstrings; later
+ * calls must pass the same set (same values, same order) and add further copy
+ * ranges; a copy range may not be run twice.  Asynchronous on hip_stream (a
+ * hipStream_t, NULL = default stream) apart from the upload of the inputs.
+ * Errors: QS_ERR_ARG (range outside [0, 2^c), empty, bits >= n, m == 0),
+ * QS_ERR_STATE (different bitstrings, overlapping range), QS_ERR_OOM, QS_ERR_HIP. */
+qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
+                        const uint64_t* bitstrings, size_t m, void* hip_stream);
+
+/* Amplitudes of the m bitstrings summed over every copy run so far (the whole
+ * circuit when all 2^c copies were run, a partial sum for a slice).  If no
+ * copy has been run yet, runs all copies first with these bitstrings.  The
+ * bitstrings must be the registered set.  out_c64 receives 2*m floats (re, im)
+ * in host memory.  out_stats (nullable, host) receives three doubles computed
+ * in FP64 on the GPU: sum |a|^2, 2^n * mean |a|^2, 2^(2n) * mean |a|^4.
+ * Synchronises hip_stream.  Errors: QS_ERR_ARG, QS_ERR_STATE, QS_ERR_HIP. */
+qs_status qs_amplitudes(qs_plan* plan, const uint64_t* bitstrings, size_t m, qs_precision prec,
+                        float* out_c64, double* out_stats, void* hip_stream);
+
+/* Forget every run copy and registered bitstring of the plan (device buffers
+ * are kept for reuse). */
+qs_status qs_plan_reset(qs_plan* plan);
+
+/* Device time in milliseconds spent by the last qs_run_halves/qs_amplitudes
+ * calls, split by kernel family: out[0] full-state passes, out[1] leaf
+ * evaluation, out[2] assembly GEMM, out[3] other (initialisation, transfers,
+ * reductions).  Only filled when timing was enabled with qs_set_timing. */
+qs_status qs_get_timing(const qs_plan* plan, double* out4);
+qs_status qs_set_timing(qs_plan* plan, int enable);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QS_H */

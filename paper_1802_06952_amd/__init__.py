@@ -1,0 +1,230 @@
+"""Python binding of libqs (ctypes): argument marshalling only.
+
+Every step of the simulation runs in the HIP kernels of ``libqs.so``; this
+module only converts Python/numpy arguments and raises on error codes.  The
+library must have been built in-tree (``python -m paper_1802_06952_amd.build``);
+importing fails loudly when it is missing.
+
+The functions carry the names of the C ABI (``include/qs.h``):
+``qs_load_circuit``, ``qs_partition``, ``qs_plan_info``, ``qs_plan_dump``,
+``qs_run_halves``, ``qs_amplitudes`` and friends.  ``Plan`` wraps them.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqs.so")
+
+QS_OK = 0
+QS_PREC_FP32 = 0
+QS_PREC_SPLIT_BF16 = 1
+_STATUS = {0: "QS_OK", -1: "QS_ERR_ARG", -2: "QS_ERR_PARSE", -3: "QS_ERR_UNSUPPORTED",
+           -4: "QS_ERR_OOM", -5: "QS_ERR_HIP", -6: "QS_ERR_STATE"}
+
+EXPORTED = ("qs_last_error", "qs_load_circuit", "qs_circuit_info", "qs_circuit_free",
+            "qs_partition", "qs_plan_info", "qs_plan_dump", "qs_plan_free", "qs_run_halves",
+            "qs_amplitudes", "qs_plan_reset", "qs_get_timing", "qs_set_timing")
+
+
+class QSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class qs_options(C.Structure):
+    _fields_ = [("tile_bits", C.c_int), ("coalesce_bits", C.c_int), ("tail_max_qubits", C.c_int),
+                ("materialize_level", C.c_int), ("mem_budget", C.c_size_t)]
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1802_06952_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, u64p = C.c_void_p, C.POINTER(C.c_uint64)
+    lib.qs_last_error.restype = C.c_char_p
+    lib.qs_load_circuit.argtypes = [C.c_char_p, C.c_size_t, C.POINTER(vp)]
+    lib.qs_circuit_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.qs_circuit_free.argtypes = [vp]
+    lib.qs_circuit_free.restype = None
+    lib.qs_partition.argtypes = [vp, C.c_uint64, C.POINTER(qs_options), C.POINTER(vp)]
+    lib.qs_plan_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.qs_plan_dump.argtypes = [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
+    lib.qs_plan_free.argtypes = [vp]
+    lib.qs_plan_free.restype = None
+    lib.qs_run_halves.argtypes = [vp, C.c_uint64, C.c_uint64, u64p, C.c_size_t, vp]
+    lib.qs_amplitudes.argtypes = [vp, u64p, C.c_size_t, C.c_int, C.POINTER(C.c_float),
+                                  C.POINTER(C.c_double), vp]
+    lib.qs_plan_reset.argtypes = [vp]
+    lib.qs_get_timing.argtypes = [vp, C.POINTER(C.c_double)]
+    lib.qs_set_timing.argtypes = [vp, C.c_int]
+    for name in EXPORTED:
+        if name != "qs_last_error" and getattr(lib, name).restype is not None:
+            getattr(lib, name).restype = C.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def lib() -> C.CDLL:
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != QS_OK:
+        raise QSError(status, _lib.qs_last_error().decode())
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available() and torch.cuda.is_initialized():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:  # pragma: no cover - torch is optional here
+            pass
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _bits(bitstrings) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(bitstrings, dtype=np.uint64))
+
+
+# --------------------------------------------------------------- C ABI names
+
+def qs_load_circuit(text: str) -> C.c_void_p:
+    b = text.encode()
+    h = C.c_void_p()
+    _check(_lib.qs_load_circuit(b, len(b), C.byref(h)))
+    return h
+
+
+def qs_circuit_info(circ) -> tuple[int, int]:
+    n, g = C.c_int(), C.c_int()
+    _check(_lib.qs_circuit_info(circ, C.byref(n), C.byref(g)))
+    return n.value, g.value
+
+
+def qs_circuit_free(circ) -> None:
+    _lib.qs_circuit_free(circ)
+
+
+def qs_partition(circ, upper_mask: int, opts: qs_options | None = None) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(_lib.qs_partition(circ, C.c_uint64(upper_mask), C.byref(opts) if opts else None,
+                             C.byref(h)))
+    return h
+
+
+def qs_plan_info(plan) -> tuple[int, int, int]:
+    a, b, c = C.c_int(), C.c_int(), C.c_int()
+    _check(_lib.qs_plan_info(plan, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def qs_plan_dump(plan) -> dict:
+    need = C.c_size_t()
+    _check(_lib.qs_plan_dump(plan, None, 0, C.byref(need)))
+    buf = C.create_string_buffer(need.value)
+    _check(_lib.qs_plan_dump(plan, buf, need.value, C.byref(need)))
+    return json.loads(buf.value.decode())
+
+
+def qs_plan_free(plan) -> None:
+    _lib.qs_plan_free(plan)
+
+
+def qs_plan_reset(plan) -> None:
+    _check(_lib.qs_plan_reset(plan))
+
+
+def qs_run_halves(plan, copy_begin: int, copy_end: int, bitstrings, stream=None) -> None:
+    b = _bits(bitstrings)
+    _check(_lib.qs_run_halves(plan, copy_begin, copy_end,
+                              b.ctypes.data_as(C.POINTER(C.c_uint64)), b.size,
+                              _stream_handle(stream)))
+
+
+def qs_amplitudes(plan, bitstrings, prec: int = QS_PREC_FP32, stream=None):
+    """Returns (amplitudes as complex64 array, stats array of 3 float64)."""
+    b = _bits(bitstrings)
+    out = np.empty(2 * b.size, dtype=np.float32)
+    stats = np.zeros(3, dtype=np.float64)
+    _check(_lib.qs_amplitudes(plan, b.ctypes.data_as(C.POINTER(C.c_uint64)), b.size, prec,
+                              out.ctypes.data_as(C.POINTER(C.c_float)),
+                              stats.ctypes.data_as(C.POINTER(C.c_double)), _stream_handle(stream)))
+    return out.view(np.complex64), stats
+
+
+def qs_set_timing(plan, enable: bool) -> None:
+    _check(_lib.qs_set_timing(plan, 1 if enable else 0))
+
+
+def qs_get_timing(plan) -> np.ndarray:
+    out = np.zeros(4, dtype=np.float64)
+    _check(_lib.qs_get_timing(plan, out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
+# --------------------------------------------------------------- convenience
+
+class Plan:
+    """Owns a circuit handle and a plan handle."""
+
+    def __init__(self, circuit_text: str, upper_mask: int, tile_bits: int = 0,
+                 coalesce_bits: int = 0, tail_max_qubits: int = 0, materialize_level: int = -1,
+                 mem_budget: int = 0):
+        self._circ = qs_load_circuit(circuit_text)
+        opts = qs_options(tile_bits, coalesce_bits, tail_max_qubits, materialize_level, mem_budget)
+        try:
+            self._plan = qs_partition(self._circ, upper_mask, opts)
+        except Exception:
+            qs_circuit_free(self._circ)
+            raise
+        self.n_upper, self.n_lower, self.n_cuts = qs_plan_info(self._plan)
+
+    @property
+    def handle(self):
+        return self._plan
+
+    def dump(self) -> dict:
+        return qs_plan_dump(self._plan)
+
+    def run_halves(self, copy_begin: int, copy_end: int, bitstrings, stream=None) -> None:
+        qs_run_halves(self._plan, copy_begin, copy_end, bitstrings, stream)
+
+    def amplitudes(self, bitstrings, prec: int = QS_PREC_FP32, stream=None):
+        return qs_amplitudes(self._plan, bitstrings, prec, stream)
+
+    def reset(self) -> None:
+        qs_plan_reset(self._plan)
+
+    def set_timing(self, on: bool) -> None:
+        qs_set_timing(self._plan, on)
+
+    def timing(self) -> np.ndarray:
+        return qs_get_timing(self._plan)
+
+    def close(self) -> None:
+        if getattr(self, "_plan", None):
+            qs_plan_free(self._plan)
+            self._plan = None
+        if getattr(self, "_circ", None):
+            qs_circuit_free(self._circ)
+            self._circ = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

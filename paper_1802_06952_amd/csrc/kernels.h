@@ -1,0 +1,45 @@
+// Launch wrappers of the HIP kernels (implemented in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "qs_internal.h"
+
+namespace qs {
+
+// Full-state pass over all tiles of `n_in_nodes` input states (or 1 when the
+// pass starts from the initial product state).  d_desc / d_ops live in device
+// memory; h_desc is the same descriptor on the host (for the launch shape).
+hipError_t launch_pass(const PassDesc& h_desc, const PassDesc* d_desc, const DevOp* d_ops,
+                       const float2* in, float2* out, uint64_t n_in_nodes, hipStream_t st);
+
+// Light-cone leaf evaluation; writes X[k * ldx + s_index].
+hipError_t launch_tail(const TailDesc& h_desc, const TailDesc* d_desc, const DevOp* d_ops,
+                       const float2* states, const uint32_t* svals, const uint64_t* node_k,
+                       float2* X, hipStream_t st);
+
+// C[i*ldc + j] (+)= sum_k A[k*lda + i] * B[k*ldb + j], complex64, FP32 MFMA.
+hipError_t launch_zgemm_tn_f32(int M, int N, int K, const float2* A, int lda, const float2* B,
+                               int ldb, float2* C, int ldc, int accumulate, hipStream_t st);
+
+// Same contraction with each FP32 operand split into bf16 hi + lo parts and
+// the hi*hi + hi*lo + lo*hi products accumulated in FP32 on BF16 MFMA.
+// `work` must hold split_bf16_workspace_bytes(M, N, K) bytes.
+size_t split_bf16_workspace_bytes(int M, int N, int K);
+hipError_t launch_zgemm_tn_split_bf16(int M, int N, int K, const float2* A, int lda,
+                                      const float2* B, int ldb, float2* C, int ldc,
+                                      int accumulate, void* work, hipStream_t st);
+
+// amps[t] = C[iu[t] * ldc + il[t]].
+hipError_t launch_gather_amps(const float2* C, int ldc, const int* iu, const int* il, size_t m,
+                              float2* amps, hipStream_t st);
+
+// FP64 sums over m amplitudes: out[0] = sum |a|^2, out[1] = sum |a|^4.
+// `partial` must hold 2 * prob_partial_blocks(m) doubles.
+int prob_partial_blocks(size_t m);
+hipError_t launch_prob_sums(const float2* amps, size_t m, double* partial, double* out,
+                            hipStream_t st);
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+
+}  // namespace qs

@@ -1,0 +1,479 @@
+// Host planner of the qs library.
+//
+// Partition (Sec. 2.1; Supp. A): the CZ gates with one endpoint in each half
+// are the cut gates E_int; each becomes P_b on its upper endpoint and Z^b on
+// its lower endpoint (Eq. 1), giving 2^c copies of two independent halves.
+//
+// Copy tree of one half (the prefix reuse of Sec. 2.3.2, taken further): a
+// cut factor is diagonal, so it commutes with every gate except a
+// non-diagonal gate on its own qubit.  An operation depends on cut j when a
+// chain of non-commuting operations leads from the cut factor to it; every
+// operation that depends on no undecided cut runs once for all copies that
+// share the decided bits.  Cuts are decided in the order of their first
+// dependent operation; a level of the tree holds the cuts decided together
+// and the operations that become runnable.  A cut with no dependent operation
+// is only applied to the output amplitudes.
+//
+// Levels up to a chosen depth are materialised as full half states by
+// passes over LDS tiles; the deeper levels are evaluated only at the
+// requested half values, on the subspace spanned by the non-diagonal targets
+// of those levels (the light cone), which these levels leave invariant.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <sstream>
+
+namespace qs {
+
+static inline int popc64(uint64_t x) { return __builtin_popcountll(x); }
+
+bool build_partition(const Circuit& c, uint64_t upper_mask, std::vector<Cut>& cuts, Side& up,
+                     Side& lo, std::string& err) {
+  const int n = c.n;
+  const uint64_t full = (n == 64) ? ~0ULL : ((1ULL << n) - 1);
+  if (upper_mask == 0 || (upper_mask & ~full) != 0 || (upper_mask & full) == full) {
+    err = "upper_mask must be a non-empty proper subset of the circuit's qubits";
+    return false;
+  }
+  const uint64_t lower_mask = full & ~upper_mask;
+  cuts.clear();
+  std::vector<std::tuple<int, int, int>> raw;
+  for (const Gate& g : c.gates) {
+    if (g.kind != G_CZ) continue;
+    bool ua = (upper_mask >> g.q0) & 1, ub = (upper_mask >> g.q1) & 1;
+    if (ua != ub) raw.emplace_back(g.cycle, ua ? g.q0 : g.q1, ua ? g.q1 : g.q0);
+  }
+  std::sort(raw.begin(), raw.end());
+  for (size_t j = 0; j < raw.size(); ++j)
+    cuts.push_back(Cut{(int)j, std::get<0>(raw[j]), std::get<1>(raw[j]), std::get<2>(raw[j])});
+  std::map<std::pair<int, int>, int> cut_of;  // (cycle, endpoint) -> cut
+  for (const Cut& k : cuts) {
+    cut_of[{k.cycle, k.upper}] = k.index;
+    cut_of[{k.cycle, k.lower}] = k.index;
+  }
+  for (int sidx = 0; sidx < 2; ++sidx) {
+    Side& s = sidx == 0 ? up : lo;
+    uint64_t mask = sidx == 0 ? upper_mask : lower_mask;
+    s = Side();
+    s.upper = sidx == 0;
+    std::vector<int> loc(n, -1);
+    for (int q = 0; q < n; ++q)
+      if ((mask >> q) & 1) {
+        loc[q] = (int)s.qubits.size();
+        s.qubits.push_back(q);
+      }
+    s.n = (int)s.qubits.size();
+    std::vector<HOp> ops;
+    for (const Gate& g : c.gates) {
+      if (g.kind == G_CZ) {
+        int a = loc[g.q0], b = loc[g.q1];
+        if (a >= 0 && b >= 0) ops.push_back(HOp{OP_CZ, a, b, -1, 0, g.cycle});
+        else if (a >= 0 || b >= 0) {
+          int q = a >= 0 ? g.q0 : g.q1;
+          ops.push_back(HOp{OP_CUT, loc[q], -1, cut_of[{g.cycle, q}], 0, g.cycle});
+        }
+      } else {
+        int a = loc[g.q0];
+        if (a < 0) continue;
+        if (g.kind == G_T) ops.push_back(HOp{OP_T, a, -1, -1, 0, g.cycle});
+        else ops.push_back(HOp{OP_MAT, a, -1, -1, g.kind == G_H ? 0 : (g.kind == G_SX ? 1 : 2), g.cycle});
+      }
+    }
+    // fold each qubit's leading H into the initial product state
+    std::vector<bool> touched(s.n, false);
+    for (const HOp& o : ops) {
+      bool fold = false;
+      if (o.kind == OP_MAT && o.mat == 0 && !touched[o.q0]) {
+        fold = true;
+        s.hinit |= 1ULL << o.q0;
+      }
+      touched[o.q0] = true;
+      if (o.q1 >= 0) touched[o.q1] = true;
+      if (!fold) s.ops.push_back(o);
+    }
+  }
+  return true;
+}
+
+Tree build_tree(const Side& s, int c, const Block& blk) {
+  Tree t;
+  t.fixed.assign(c, -1);
+  for (int j = 0; j < blk.p && j < c; ++j) t.fixed[j] = (int)((blk.k0 >> (c - 1 - j)) & 1);
+  const int nops = (int)s.ops.size();
+  auto is_free_cut = [&](const HOp& o) { return o.kind == OP_CUT && t.fixed[o.cut] < 0; };
+  // dependency masks over cuts
+  std::vector<uint64_t> dep(nops, 0);
+  std::vector<uint64_t> acc_all(s.n, 0), acc_nd(s.n, 0);
+  for (int i = 0; i < nops; ++i) {
+    const HOp& o = s.ops[i];
+    bool nd = o.kind == OP_MAT;
+    uint64_t d = 0;
+    int qs[2] = {o.q0, o.q1};
+    for (int k = 0; k < 2; ++k) {
+      if (qs[k] < 0) continue;
+      d |= nd ? acc_all[qs[k]] : acc_nd[qs[k]];
+    }
+    dep[i] = d;
+    uint64_t own = d | (is_free_cut(o) ? (1ULL << o.cut) : 0);
+    for (int k = 0; k < 2; ++k) {
+      if (qs[k] < 0) continue;
+      acc_all[qs[k]] |= own;
+      if (nd) acc_nd[qs[k]] |= own;
+    }
+  }
+  // order free cuts by first dependent op
+  std::vector<int> first(c, -1);
+  for (int i = 0; i < nops; ++i) {
+    if (is_free_cut(s.ops[i])) continue;
+    for (int j = 0; j < c; ++j)
+      if (((dep[i] >> j) & 1) && first[j] < 0) first[j] = i;
+  }
+  std::vector<int> order;
+  for (int j = 0; j < c; ++j)
+    if (t.fixed[j] < 0) {
+      if (first[j] >= 0) order.push_back(j);
+      else t.end_cuts.push_back(j);
+    }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return first[a] < first[b]; });
+  std::vector<bool> done(nops, false);
+  uint64_t D = 0;
+  auto take = [&]() {
+    std::vector<int> lst;
+    for (int i = 0; i < nops; ++i) {
+      if (done[i] || is_free_cut(s.ops[i])) continue;
+      if ((dep[i] & ~D) == 0) {
+        done[i] = true;
+        lst.push_back(i);
+      }
+    }
+    return lst;
+  };
+  t.levels.push_back(Level{{}, take()});
+  std::vector<int> pend;
+  for (size_t a = 0; a < order.size(); ++a) {
+    pend.push_back(order[a]);
+    D |= 1ULL << order[a];
+    std::vector<int> lst = take();
+    if (!lst.empty() || (int)pend.size() == kMaxBranch || a + 1 == order.size()) {
+      t.levels.push_back(Level{pend, lst});
+      pend.clear();
+    }
+  }
+  for (const Level& L : t.levels)
+    for (int j : L.cuts) t.order.push_back(j);
+  for (int j : t.end_cuts) t.order.push_back(j);
+  return t;
+}
+
+namespace {
+
+// Greedy pass packing: take ops in order while their non-diagonal targets fit
+// in the tile; an op that does not fit is deferred together with every later
+// op that does not commute with a deferred one.
+void absorb(const Side& s, const std::vector<int>& P, std::vector<int>& S, int tmax,
+            std::vector<int>& taken, std::vector<int>& deferred) {
+  std::vector<char> nd_def(s.n, 0), any_def(s.n, 0);
+  taken.clear();
+  deferred.clear();
+  for (int i : P) {
+    const HOp& o = s.ops[i];
+    bool nd = o.kind == OP_MAT;
+    bool conflict = false;
+    if (nd) conflict = any_def[o.q0];
+    else {
+      conflict = nd_def[o.q0] || (o.q1 >= 0 && nd_def[o.q1]);
+    }
+    if (!conflict && nd && std::find(S.begin(), S.end(), o.q0) == S.end()) {
+      if ((int)S.size() < tmax) S.push_back(o.q0);
+      else conflict = true;
+    }
+    if (conflict) {
+      deferred.push_back(i);
+      any_def[o.q0] = 1;
+      if (o.q1 >= 0) any_def[o.q1] = 1;
+      if (nd) nd_def[o.q0] = 1;
+    } else {
+      taken.push_back(i);
+    }
+  }
+}
+
+}  // namespace
+
+bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, SidePlan& out,
+               std::string& err) {
+  Tree tree = build_tree(s, c, blk);
+  const int L = (int)tree.levels.size() - 1;
+  std::vector<uint64_t> nodes(L + 1, 1);
+  for (int l = 1; l <= L; ++l) nodes[l] = nodes[l - 1] << tree.levels[l].cuts.size();
+  const double B = std::ldexp(8.0, s.n);
+  const int t = std::min(kn.tile_bits, s.n);
+  const int b = std::max(0, std::min(kn.coalesce_bits, t - 1));
+
+  bool found = false;
+  SidePlan best;
+  for (int ls = 0; ls <= L; ++ls) {
+    if (kn.force_lstar >= 0 && ls != std::min(kn.force_lstar, L)) continue;
+    SidePlan sp;
+    sp.tree = tree;
+    sp.lstar = ls;
+    sp.nodes = nodes;
+    // light cone of the levels below ls
+    std::vector<int> Q;
+    for (int l = ls + 1; l <= L; ++l)
+      for (int i : tree.levels[l].ops)
+        if (s.ops[i].kind == OP_MAT && std::find(Q.begin(), Q.end(), s.ops[i].q0) == Q.end())
+          Q.push_back(s.ops[i].q0);
+    std::sort(Q.begin(), Q.end());
+    if ((int)Q.size() > kn.tail_max_qubits) continue;
+    sp.Q = Q;
+    // passes for levels 0..ls
+    std::vector<std::vector<int>> pending(ls + 1);
+    for (int l = 0; l <= ls; ++l) pending[l] = tree.levels[l].ops;
+    int cur = 0;
+    bool first = true;
+    double cost = 0;
+    size_t peak = 1;
+    for (int guard = 0; guard < 100000; ++guard) {
+      PassPlan pp;
+      pp.level_in = cur;
+      pp.init = first;
+      first = false;
+      std::vector<int> S;
+      for (int q = 0; q < b; ++q) S.push_back(q);
+      std::vector<int> deferred;
+      absorb(s, pending[cur], S, t, pp.ops_in, deferred);
+      pending[cur] = deferred;
+      if (deferred.empty() && cur < ls) {
+        std::vector<int> d2;
+        absorb(s, pending[cur + 1], S, t, pp.ops_out, d2);
+        pending[cur + 1] = d2;
+        pp.branch = true;
+        ++cur;
+      }
+      // fill the tile up to t bits with the lowest unused qubits (keeps runs long)
+      for (int q = 0; (int)S.size() < t && q < s.n; ++q)
+        if (std::find(S.begin(), S.end(), q) == S.end()) S.push_back(q);
+      std::sort(S.begin(), S.end());
+      pp.tile = S;
+      if (pp.branch) {
+        cost += (pp.init ? 0 : B * nodes[pp.level_in]) + B * nodes[cur];
+        peak = std::max<size_t>(peak, nodes[pp.level_in] + nodes[cur]);
+      } else {
+        cost += (pp.init ? 1 : 2) * B * nodes[cur];
+        peak = std::max<size_t>(peak, nodes[cur]);
+      }
+      sp.passes.push_back(pp);
+      if (cur == ls && pending[ls].empty()) break;
+    }
+    // leaf evaluation estimate: gather plus arithmetic per (node, value)
+    const double q = (double)Q.size();
+    double per = std::ldexp(32.0, (int)q);
+    double leaves = 1;
+    for (int l = ls + 1; l <= L; ++l) {
+      leaves *= std::ldexp(1.0, (int)tree.levels[l].cuts.size());
+      double nmat = 0, ndiag = 0;
+      for (int i : tree.levels[l].ops) (s.ops[i].kind == OP_MAT ? nmat : ndiag) += 1;
+      per += leaves * std::ldexp(1.0, (int)q) * (nmat * 16 + ndiag * 12 + 8) / 4.0;
+    }
+    cost += per * (double)nodes[ls] * kn.S;
+    sp.cost_bytes = cost;
+    sp.peak_states = peak;
+    if (kn.mem_budget && (double)peak * B > (double)kn.mem_budget) continue;
+    if (!found || cost < best.cost_bytes) {
+      best = sp;
+      found = true;
+    }
+  }
+  if (!found) {
+    err = "no feasible schedule: light cone of the leaf levels exceeds the limit or the "
+          "materialised states exceed the memory budget";
+    return false;
+  }
+  out = std::move(best);
+  return true;
+}
+
+namespace {
+
+struct DiagAcc {
+  int w[64] = {0};
+  std::map<int, uint64_t> cz;  // distance -> mask of lower endpoints
+  uint64_t pmask = 0, pval = 0;
+  bool zero = false;
+  bool any = false;
+  void reset() { *this = DiagAcc(); }
+};
+
+void flush(DiagAcc& a, std::vector<DevOp>& out) {
+  if (!a.any) return;
+  std::vector<std::pair<int, uint64_t>> dl;
+  for (auto& kv : a.cz)
+    if (kv.second) dl.push_back(kv);
+  size_t at = 0;
+  bool firstop = true;
+  do {
+    DevOp op{};
+    op.kind = 1;
+    if (firstop) {
+      for (int q = 0; q < 64; ++q) {
+        int w = a.w[q] & 7;
+        if (w & 1) op.t0 |= 1ULL << q;
+        if (w & 2) op.t1 |= 1ULL << q;
+        if (w & 4) op.t2 |= 1ULL << q;
+      }
+      op.pmask = a.pmask;
+      op.pval = a.pval;
+      if (a.zero) {
+        op.pmask = 1;
+        op.pval = 2;
+      }
+    }
+    int k = 0;
+    while (at < dl.size() && k < kMaxDiagDist) {
+      op.d[k] = dl[at].first;
+      op.M[k] = dl[at].second;
+      ++k;
+      ++at;
+    }
+    op.nd = k;
+    out.push_back(op);
+    firstop = false;
+  } while (at < dl.size());
+  a.reset();
+}
+
+void set_mat(DevOp& op, int mat) {
+  const float r = 0.70710678118654752f;
+  float m[8];
+  if (mat == 0) {  // H
+    float v[8] = {r, 0, r, 0, r, 0, -r, 0};
+    std::copy(v, v + 8, m);
+  } else if (mat == 1) {  // sqrt X = 1/2 [[1+i, 1-i], [1-i, 1+i]]
+    float v[8] = {0.5f, 0.5f, 0.5f, -0.5f, 0.5f, -0.5f, 0.5f, 0.5f};
+    std::copy(v, v + 8, m);
+  } else {  // sqrt Y = 1/2 [[1+i, -1-i], [1+i, 1+i]]
+    float v[8] = {0.5f, 0.5f, -0.5f, -0.5f, 0.5f, 0.5f, 0.5f, 0.5f};
+    std::copy(v, v + 8, m);
+  }
+  std::copy(m, m + 8, op.m);
+}
+
+}  // namespace
+
+bool encode_ops(const Side& s, const std::vector<int>& ops, const std::vector<int>& fixed_bits,
+                const std::vector<int>& work_of, std::vector<DevOp>& out, std::string& err) {
+  DiagAcc acc;
+  for (int i : ops) {
+    const HOp& o = s.ops[i];
+    switch (o.kind) {
+      case OP_MAT: {
+        flush(acc, out);
+        int w = work_of[o.q0];
+        if (w < 0) {
+          err = "internal: non-diagonal gate outside the working bits";
+          return false;
+        }
+        DevOp op{};
+        op.kind = 0;
+        op.target = w;
+        set_mat(op, o.mat);
+        out.push_back(op);
+        break;
+      }
+      case OP_T:
+        acc.w[o.q0] += 1;
+        acc.any = true;
+        break;
+      case OP_CZ: {
+        int lo = std::min(o.q0, o.q1), hi = std::max(o.q0, o.q1);
+        acc.cz[hi - lo] ^= 1ULL << lo;
+        acc.any = true;
+        break;
+      }
+      case OP_CUT: {
+        int bit = fixed_bits[o.cut];
+        if (bit < 0) {
+          err = "internal: free cut inside an op list";
+          return false;
+        }
+        if (s.upper) {
+          uint64_t m = 1ULL << o.q0;
+          if ((acc.pmask & m) && (((acc.pval >> o.q0) & 1) != (uint64_t)bit)) acc.zero = true;
+          acc.pmask |= m;
+          if (bit) acc.pval |= m;
+        } else if (bit) {
+          acc.w[o.q0] += 4;
+        }
+        acc.any = true;
+        break;
+      }
+    }
+  }
+  flush(acc, out);
+  return true;
+}
+
+std::string dump_json(const Circuit& c, uint64_t upper_mask, const std::vector<Cut>& cuts,
+                      const Side& up, const Side& lo, const SidePlan* pu, const SidePlan* pl) {
+  std::ostringstream o;
+  o << "{\"n\":" << c.n << ",\"upper_mask\":" << upper_mask << ",\"cuts\":[";
+  for (size_t j = 0; j < cuts.size(); ++j)
+    o << (j ? "," : "") << "[" << cuts[j].cycle << "," << cuts[j].upper << "," << cuts[j].lower << "]";
+  o << "],\"sides\":[";
+  for (int k = 0; k < 2; ++k) {
+    const Side& s = k == 0 ? up : lo;
+    const SidePlan* sp = k == 0 ? pu : pl;
+    o << (k ? "," : "") << "{\"upper\":" << (s.upper ? "true" : "false") << ",\"n\":" << s.n
+      << ",\"hinit\":" << s.hinit << ",\"qubits\":[";
+    for (size_t i = 0; i < s.qubits.size(); ++i) o << (i ? "," : "") << s.qubits[i];
+    o << "],\"ops\":[";
+    for (size_t i = 0; i < s.ops.size(); ++i) {
+      const HOp& h = s.ops[i];
+      const char* nm = h.kind == OP_MAT ? (h.mat == 0 ? "h" : h.mat == 1 ? "sx" : "sy")
+                       : h.kind == OP_T ? "t" : h.kind == OP_CZ ? "cz" : "cut";
+      o << (i ? "," : "") << "[\"" << nm << "\"," << h.q0 << "," << h.q1 << "," << h.cut << ","
+        << h.cycle << "]";
+    }
+    o << "]";
+    if (sp) {
+      o << ",\"lstar\":" << sp->lstar << ",\"cost_bytes\":" << sp->cost_bytes
+        << ",\"peak_states\":" << sp->peak_states << ",\"end_cuts\":[";
+      for (size_t i = 0; i < sp->tree.end_cuts.size(); ++i)
+        o << (i ? "," : "") << sp->tree.end_cuts[i];
+      o << "],\"levels\":[";
+      for (size_t l = 0; l < sp->tree.levels.size(); ++l) {
+        const Level& L = sp->tree.levels[l];
+        o << (l ? "," : "") << "{\"cuts\":[";
+        for (size_t i = 0; i < L.cuts.size(); ++i) o << (i ? "," : "") << L.cuts[i];
+        o << "],\"ops\":[";
+        for (size_t i = 0; i < L.ops.size(); ++i) o << (i ? "," : "") << L.ops[i];
+        o << "],\"nodes\":" << sp->nodes[l] << "}";
+      }
+      o << "],\"passes\":[";
+      for (size_t p = 0; p < sp->passes.size(); ++p) {
+        const PassPlan& pp = sp->passes[p];
+        o << (p ? "," : "") << "{\"level_in\":" << pp.level_in << ",\"init\":" << (pp.init ? 1 : 0)
+          << ",\"branch\":" << (pp.branch ? 1 : 0) << ",\"ops_in\":[";
+        for (size_t i = 0; i < pp.ops_in.size(); ++i) o << (i ? "," : "") << pp.ops_in[i];
+        o << "],\"ops_out\":[";
+        for (size_t i = 0; i < pp.ops_out.size(); ++i) o << (i ? "," : "") << pp.ops_out[i];
+        o << "],\"tile\":[";
+        for (size_t i = 0; i < pp.tile.size(); ++i) o << (i ? "," : "") << pp.tile[i];
+        o << "]}";
+      }
+      o << "],\"Q\":[";
+      for (size_t i = 0; i < sp->Q.size(); ++i) o << (i ? "," : "") << sp->Q[i];
+      o << "]";
+    }
+    o << "}";
+  }
+  o << "]}";
+  return o.str();
+}
+
+}  // namespace qs

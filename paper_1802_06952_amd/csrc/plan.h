@@ -1,0 +1,78 @@
+// Host planner: cut classification, half programs, the copy tree of a half
+// (branch points pushed past every gate that commutes with the cut factor),
+// grouping of each tree level into full-state passes, and the light-cone leaf
+// evaluation of the deepest levels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "qs_internal.h"
+
+namespace qs {
+
+// Cuts of E_int in cut order and the two half programs.
+bool build_partition(const Circuit& c, uint64_t upper_mask, std::vector<Cut>& cuts, Side& up,
+                     Side& lo, std::string& err);
+
+// A block of copies: cut j < p is fixed to bit (k0 >> (c-1-j)) & 1, the rest are free.
+struct Block {
+  uint64_t k0 = 0;
+  int p = 0;
+};
+
+struct Level {
+  std::vector<int> cuts;  // cuts decided on entering the level (branch order, MSB first)
+  std::vector<int> ops;   // indices into Side::ops executed at this level, program order
+};
+
+struct Tree {
+  std::vector<Level> levels;   // levels[0].cuts is empty
+  std::vector<int> end_cuts;   // free cuts with no later non-commuting gate on their qubit
+  std::vector<int> fixed;      // per cut: -1 free, else the fixed bit
+  std::vector<int> order;      // free cuts in leaf-id order: level cuts, then end cuts
+};
+
+Tree build_tree(const Side& s, int c, const Block& blk);
+
+struct PassPlan {
+  int level_in = 0;
+  bool init = false;
+  bool branch = false;
+  std::vector<int> ops_in, ops_out;
+  std::vector<int> tile;  // local qubits of the tile, ascending
+};
+
+struct SidePlan {
+  Tree tree;
+  int lstar = 0;                  // last materialised level
+  std::vector<PassPlan> passes;
+  std::vector<int> Q;             // light-cone qubits of the leaf evaluation (ascending)
+  double cost_bytes = 0;          // cost model estimate
+  size_t peak_states = 0;         // largest number of live states
+  std::vector<uint64_t> nodes;    // nodes per level
+};
+
+struct PlanKnobs {
+  int tile_bits = 12;
+  int coalesce_bits = 5;
+  int tail_max_qubits = 10;
+  int force_lstar = -1;
+  size_t mem_budget = 0;  // bytes; 0 = unlimited
+  int S = 1;              // requested values of this half (for the cost model)
+};
+
+bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, SidePlan& out,
+               std::string& err);
+
+// Encode a sequence of half ops as kernel ops; `work_of` maps a local qubit to
+// the working bit of a MAT op (-1 if the qubit is not a working bit, which is
+// an error for MAT ops).  Diagonal ops between MATs are merged.
+bool encode_ops(const Side& s, const std::vector<int>& ops, const std::vector<int>& fixed_bits,
+                const std::vector<int>& work_of, std::vector<DevOp>& out, std::string& err);
+
+std::string dump_json(const Circuit& c, uint64_t upper_mask, const std::vector<Cut>& cuts,
+                      const Side& up, const Side& lo, const SidePlan* pu, const SidePlan* pl);
+
+}  // namespace qs

@@ -1,0 +1,137 @@
+// Internal structures of the qs library: circuit, half programs, the copy tree
+// of one half, and the device descriptors of the kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qs.h"
+
+namespace qs {
+
+// ---------------------------------------------------------------- circuit
+
+enum GateKind : uint8_t { G_H = 0, G_SX = 1, G_SY = 2, G_T = 3, G_CZ = 4 };
+
+struct Gate {
+  int cycle;
+  GateKind kind;
+  int q0, q1;  // q1 = -1 for one-qubit gates
+};
+
+struct Circuit {
+  int n = 0;
+  std::vector<Gate> gates;
+};
+
+// Parse the text format; on error returns false and fills err.
+bool parse_circuit(const char* text, size_t len, Circuit& out, std::string& err);
+
+// ---------------------------------------------------------------- partition
+
+struct Cut {
+  int index;  // position in cut order
+  int cycle;
+  int upper;  // global qubit id of the upper endpoint (carries P_b)
+  int lower;  // global qubit id of the lower endpoint (carries Z^b)
+};
+
+// One operation of a half program, on local qubit ids.
+enum OpKind : uint8_t {
+  OP_MAT = 0,  // non-diagonal 2x2 gate (H, sqrt X, sqrt Y) on q0
+  OP_T = 1,    // T on q0
+  OP_CZ = 2,   // CZ on (q0, q1), both inside the half
+  OP_CUT = 3   // the half's factor of cut gate `cut`: P_b (upper) or Z^b (lower) on q0
+};
+
+struct HOp {
+  OpKind kind;
+  int q0, q1;
+  int cut;
+  int mat;    // OP_MAT: 0 = H, 1 = sqrt X, 2 = sqrt Y
+  int cycle;
+};
+
+struct Side {
+  bool upper = true;
+  int n = 0;                   // qubits of the half
+  std::vector<int> qubits;     // global id of local qubit i (ascending)
+  std::vector<HOp> ops;        // program order (after the initial H layer)
+  uint64_t hinit = 0;          // local qubits starting in |+> (leading H folded into the init)
+};
+
+// ---------------------------------------------------------------- device descriptors
+
+constexpr int kMaxDiagDist = 8;
+constexpr int kMaxBranch = 8;
+constexpr int kMaxTailLevels = 10;
+constexpr int kMaxTileBits = 14;
+
+// One operation as the kernels see it.  DIAG multiplies amplitude x by
+//   omega^(popc(x & t0) + 2 popc(x & t1) + 4 popc(x & t2)
+//           + 4 * sum_i popc(x & (x >> d[i]) & M[i]))
+// and zeroes it unless (x & pmask) == pval (omega = (1+i)/sqrt 2; Eq. 4 and 6
+// fused with the cut projectors and Z of Eq. 1).  MAT applies a 2x2 matrix on
+// index bit `target` of the kernel's working index space.
+struct DevOp {
+  int kind;    // 0 = MAT, 1 = DIAG
+  int target;  // MAT: working bit
+  int nd;      // DIAG: number of (d, M) pairs
+  int pad;
+  float m[8];  // MAT: m00 m01 m10 m11 as (re, im)
+  uint64_t t0, t1, t2, pmask, pval;
+  int d[kMaxDiagDist];
+  uint64_t M[kMaxDiagDist];
+};
+
+// A full-state pass: every workgroup owns one tile of 2^t amplitudes (the
+// tile bits are state bits tbit[0..t-1], ascending, the first `coalesce` of
+// them the lowest state bits), applies `n_in` ops once, then for each of the
+// 2^m children of a branch (m = 0: a single output) applies the child's cut
+// factors and `n_out` ops and stores the tile.
+struct PassDesc {
+  int n;             // state qubits
+  int t;             // tile bits
+  int tbit[kMaxTileBits];
+  int n_outer;       // n - t
+  int obit[64];      // state bit of outer bit j (ascending)
+  int init;          // 1: no input, start from the product state given by hinit
+  uint64_t hinit;
+  float hamp;        // amplitude of the initial product state
+  int op_in, n_in;   // range in the op table
+  int op_out, n_out;
+  int m;             // branch bits (0 = no branch)
+  int bq[kMaxBranch];  // state bit of the cut qubit of branch bit i (bit i = MSB first)
+  int upper;         // 1: P_b factors, 0: Z^b factors
+};
+
+struct TailLevel {
+  int m;                 // cut bits decided at this level (0 for the first, shared level)
+  int bq[kMaxBranch];    // state bit of each cut qubit (bit 0 = MSB of b)
+  int op0, nops;         // range in the op table (MAT targets are Q indices)
+  uint64_t kbit[kMaxBranch];  // copy-index contribution of each branch bit
+};
+
+// Leaf evaluation restricted to the light cone: for each materialised node
+// and each requested half value s, the 2^q amplitudes that differ from s only
+// on the qubits Q[0..q-1] are gathered, the tail levels are applied depth
+// first, and each leaf's amplitude at s is written (times the factors of the
+// cuts decided only at the end).
+struct TailDesc {
+  int n;
+  int q;
+  int Q[16];            // state bit of working bit i
+  int nlev;
+  TailLevel lev[kMaxTailLevels];
+  int n_end;            // cuts with no later non-commuting gate: applied to the output
+  int eq[kMaxBranch * 2];   // state bit of each end cut's qubit (MSB first)
+  uint64_t ekbit[kMaxBranch * 2];  // copy-index contribution of each end bit
+  int upper;
+  int n_nodes;          // materialised nodes
+  int nodes_per_copy_shift;  // unused
+  int S;                // requested values
+  int ldx;              // leading dimension (row stride) of the output X[k][s]
+};
+
+}  // namespace qs

@@ -1,0 +1,184 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Error measure: the norm-wise relative error ||a - a_ref|| / ||a_ref|| over the
+evaluated amplitudes (per-amplitude relative errors are ill-conditioned near
+the zeros of a Porter-Thomas distribution).  Bounds: 1e-5 for the FP32 path,
+1e-4 for the split-BF16 assembly.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import circuit as OC, partition as P, statevector as SV
+from workloads import circuits as W, product_bitstrings, workload
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TOL = {0: 1e-5, 1: 1e-4}
+
+
+def _lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1802_06952_amd as Q
+    return Q
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def relerr(a, ref):
+    return float(np.linalg.norm(a.astype(np.complex128) - ref) / np.linalg.norm(ref))
+
+
+def run_plan(Q, text, mask, bits, prec=0, **kw):
+    p = Q.Plan(text, mask, **kw)
+    try:
+        amp, stats = p.amplitudes(bits, prec)
+    finally:
+        p.close()
+    return amp, stats
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_grid4x4_all_amplitudes(prec):
+    Q = _lib()
+    w = workload("grid4x4_d10")
+    text = w.circuit_text()
+    bits, _, _ = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
+    say(f"case grid4x4_d10 prec={prec} m={bits.size}")
+    amp, stats = run_plan(Q, text, w.upper_mask, bits, prec)
+    psi = SV.simulate(OC.parse(text))
+    ref = psi[bits.astype(np.int64)]
+    assert relerr(amp, ref) < TOL[prec]
+    # every amplitude of the state: the probabilities sum to one
+    assert abs(stats[0] - 1.0) < 1e-5
+    assert abs(stats[1] - 1.0) < 1e-5
+
+
+@pytest.mark.parametrize("rows,cols,depth,mask,seed", [
+    (4, 4, 16, W.grid_cols_mask(4, 4, [0, 1]), 1),
+    (3, 4, 18, W.grid_rows_mask(3, 4, [0]) | 0b0011 << 4, 2),
+    (2, 6, 12, W.grid_cols_mask(2, 6, [0, 2, 4]), 3),
+    (4, 5, 12, W.grid_rows_mask(4, 5, [0, 1]), 4),
+    (5, 4, 14, W.grid_rows_mask(5, 4, [0, 1]), 5),
+])
+def test_masks_against_full_state(rows, cols, depth, mask, seed):
+    Q = _lib()
+    text = W.random_grid_circuit(rows, cols, depth, seed)
+    n = rows * cols
+    nu = bin(mask).count("1")
+    bits, _, _ = product_bitstrings(n, mask, min(64, 1 << nu), min(64, 1 << (n - nu)), seed, seed + 1)
+    say(f"case masks {rows}x{cols} d{depth} mask={mask:#x}")
+    amp, _ = run_plan(Q, text, mask, bits)
+    ref = SV.simulate(OC.parse(text))[bits.astype(np.int64)]
+    assert relerr(amp, ref) < 1e-5
+
+
+@pytest.mark.parametrize("kw", [
+    dict(tile_bits=6, coalesce_bits=2),
+    dict(tile_bits=9, coalesce_bits=3, materialize_level=0, tail_max_qubits=10),
+    dict(tile_bits=13, coalesce_bits=6, materialize_level=2),
+    dict(tile_bits=8, coalesce_bits=0, materialize_level=100),
+])
+def test_schedule_knobs_same_result(kw):
+    Q = _lib()
+    text = W.random_grid_circuit(4, 5, 16, 7)
+    mask = W.grid_rows_mask(4, 5, [0, 1])
+    bits, _, _ = product_bitstrings(20, mask, 128, 128, 11, 12)
+    say(f"case knobs {kw}")
+    amp, _ = run_plan(Q, text, mask, bits, **kw)
+    ref = SV.simulate(OC.parse(text))[bits.astype(np.int64)]
+    assert relerr(amp, ref) < 1e-5
+
+
+def test_copy_slices_partial_sums():
+    Q = _lib()
+    text = W.random_grid_circuit(4, 4, 12, 5)
+    mask = W.grid_rows_mask(4, 4, [0, 1])
+    oc = OC.parse(text)
+    bits, _, _ = product_bitstrings(16, mask, 32, 32, 3, 4)
+    p = Q.Plan(text, mask)
+    total = 1 << p.n_cuts
+    ranges = [(0, 3), (3, 8), (8, total - 1), (total - 1, total)]
+    got = np.zeros(bits.size, dtype=np.complex128)
+    for a, b in ranges:
+        say(f"case slice [{a},{b})")
+        q = Q.Plan(text, mask)
+        q.run_halves(a, b, bits)
+        amp, _ = q.amplitudes(bits)
+        q.close()
+        ref = P.amplitudes(oc, mask, bits, a, b)
+        assert np.linalg.norm(amp - ref) <= 1e-5 * max(np.linalg.norm(ref), 1e-3)
+        got += amp
+    full = SV.simulate(oc)[bits.astype(np.int64)]
+    assert relerr(got, full) < 1e-5
+    # several ranges on one plan accumulate
+    for a, b in ranges:
+        p.run_halves(a, b, bits)
+    amp, _ = p.amplitudes(bits)
+    assert relerr(amp, full) < 1e-5
+    # a range may not run twice
+    with pytest.raises(Q.QSError):
+        p.run_halves(0, 1, bits)
+    p.close()
+
+
+def test_argument_errors():
+    Q = _lib()
+    w = workload("grid4x4_d10")
+    p = Q.Plan(w.circuit_text(), w.upper_mask)
+    with pytest.raises(Q.QSError) as e:
+        p.run_halves(0, 1 << p.n_cuts, np.array([1 << 16], dtype=np.uint64))
+    assert e.value.status == -1
+    with pytest.raises(Q.QSError) as e:
+        p.run_halves(0, (1 << p.n_cuts) + 1, np.array([1], dtype=np.uint64))
+    assert e.value.status == -1
+    p.run_halves(0, 4, np.array([1, 2], dtype=np.uint64))
+    with pytest.raises(Q.QSError) as e:
+        p.amplitudes(np.array([1, 3], dtype=np.uint64))
+    assert e.value.status == -6
+    p.close()
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"{name}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return np.load(path)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_grid6x6_d16_golden(prec):
+    Q = _lib()
+    w = workload("grid6x6_d16")
+    g = _golden(w.name)
+    bits, u, l = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
+    assert np.array_equal(g["u"], u.astype(np.int64)) and np.array_equal(g["l"], l.astype(np.int64))
+    say(f"case grid6x6_d16 prec={prec}")
+    amp, stats = run_plan(Q, w.circuit_text(), w.upper_mask, bits, prec)
+    assert relerr(amp, g["amp"]) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_grid6x7_d20_full_size_subset(prec):
+    """The 2^20-bitstring workload; the oracle holds the first 64 x 64 block."""
+    Q = _lib()
+    w = workload("grid6x7_d20")
+    g = _golden(w.name)
+    bits, u, l = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
+    nu, nl = len(g["u"]), len(g["l"])
+    assert np.array_equal(g["u"], u[:nu].astype(np.int64))
+    say(f"case grid6x7_d20 prec={prec} m={bits.size}")
+    amp, stats = run_plan(Q, w.circuit_text(), w.upper_mask, bits, prec)
+    sub = amp.reshape(w.n_u, w.n_l)[:nu, :nl].reshape(-1)
+    assert relerr(sub, g["amp"]) < TOL[prec]
+    # uniform bitstrings: 2^n mean p estimates 1
+    assert abs(stats[1] - 1.0) < 0.05

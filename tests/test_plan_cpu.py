@@ -1,0 +1,173 @@
+"""CPU checks of the library's host side: exported symbols, the partition, and
+the copy-tree schedule.
+
+The schedule test replays the plan the library prints (initial product
+state, tree levels with their branch factors, cuts applied at the output) with
+a small numpy interpreter written here, and compares every copy's half state
+with the oracle.  No GPU is involved: only the planner's reordering of the
+half programs is under test.
+"""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1802_06952_amd as Q
+from oracle import circuit as OC, partition as P
+from workloads import CONFIGS, circuits as W
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "qs.h")
+
+
+def test_library_exports_every_declared_symbol():
+    text = open(HEADER).read()
+    declared = set(re.findall(r"\b(qs_[a-z_]+)\s*\(", text))
+    assert declared, "no declarations found"
+    lib = Q.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(Q.EXPORTED)
+
+
+def test_parse_errors():
+    for bad in ["", "qubits 0\n", "qubits 65\n", "qubits 2\n0 cz 0 0\n", "qubits 2\n0 h 2\n",
+                "qubits 2\n1 h 0\n0 h 1\n", "qubits 2\n0 h 0\n0 t 0\n", "qubits 2\n0 foo 1\n",
+                "0 h 0\n"]:
+        with pytest.raises(Q.QSError) as e:
+            Q.qs_load_circuit(bad)
+        assert e.value.status == -2
+    c = Q.qs_load_circuit("qubits 3 # three\n0 h 0\n0 h 1\n1 cz 0 1\n")
+    assert Q.qs_circuit_info(c) == (3, 3)
+    Q.qs_circuit_free(c)
+
+
+def test_partition_errors():
+    text = W.random_grid_circuit(4, 4, 10, 0)
+    c = Q.qs_load_circuit(text)
+    for mask in (0, (1 << 16) - 1, 1 << 16):
+        with pytest.raises(Q.QSError) as e:
+            Q.qs_partition(c, mask)
+        assert e.value.status == -1
+    Q.qs_circuit_free(c)
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_partition_matches_oracle_cuts(name):
+    w = CONFIGS[name]
+    text = w.circuit_text()
+    p = Q.Plan(text, w.upper_mask)
+    d = p.dump()
+    oc = OC.parse(text)
+    cuts = P.find_cuts(oc, w.upper_mask)
+    assert p.n_cuts == len(cuts)
+    assert [tuple(x) for x in d["cuts"]] == [(k.cycle, k.upper, k.lower) for k in cuts]
+    full = (1 << w.n) - 1
+    assert d["sides"][0]["qubits"] == P.half_qubits(w.n, w.upper_mask)
+    assert d["sides"][1]["qubits"] == P.half_qubits(w.n, full & ~w.upper_mask)
+    for s in d["sides"]:
+        # every op runs at exactly one tree level
+        if "levels" in s:
+            seen = sorted(i for lv in s["levels"] for i in lv["ops"])
+            ncut_ops = sum(1 for o in s["ops"] if o[0] == "cut")
+            assert len(seen) == len(set(seen)) == len(s["ops"]) - ncut_ops
+
+
+# ---------------------------------------------------------------- schedule replay
+
+SQ = np.sqrt(0.5)
+MATS = {"h": np.array([[SQ, SQ], [SQ, -SQ]], dtype=complex),
+        "sx": 0.5 * np.array([[1 + 1j, 1 - 1j], [1 - 1j, 1 + 1j]]),
+        "sy": 0.5 * np.array([[1 + 1j, -1 - 1j], [1 + 1j, 1 + 1j]])}
+
+
+def _bit(n, q):
+    return (np.arange(1 << n) >> q) & 1
+
+
+def _apply(psi, n, op):
+    name, q0, q1 = op[0], op[1], op[2]
+    if name in MATS:
+        m = MATS[name]
+        b = _bit(n, q0)
+        i0 = np.nonzero(b == 0)[0]
+        i1 = i0 | (1 << q0)
+        a0, a1 = psi[i0].copy(), psi[i1].copy()
+        psi[i0] = m[0, 0] * a0 + m[0, 1] * a1
+        psi[i1] = m[1, 0] * a0 + m[1, 1] * a1
+    elif name == "t":
+        psi *= np.where(_bit(n, q0) == 1, (1 + 1j) * SQ, 1.0)
+    elif name == "cz":
+        psi *= np.where((_bit(n, q0) & _bit(n, q1)) == 1, -1.0, 1.0)
+    else:
+        raise AssertionError(op)
+
+
+def _cut_factor(psi, n, q, b, upper):
+    if upper:
+        psi *= (_bit(n, q) == b)
+    elif b:
+        psi *= np.where(_bit(n, q) == 1, -1.0, 1.0)
+
+
+def replay(side, cuts, c):
+    n = side["n"]
+    qubits = side["qubits"]
+    upper = side["upper"]
+    loc = {g: i for i, g in enumerate(qubits)}
+    cq = [loc[(k[1] if upper else k[2])] for k in cuts]
+    psi0 = np.zeros(1 << n, dtype=complex)
+    h = side["hinit"]
+    x = np.arange(1 << n)
+    psi0[(x & ~h) == 0] = 2.0 ** (-bin(h).count("1") / 2)
+    out = np.zeros((1 << n, 1 << c), dtype=complex)
+    levels = side["levels"]
+
+    def rec(psi, li, k):
+        if li == len(levels):
+            ends = side["end_cuts"]
+            for e in range(1 << len(ends)):
+                s = psi.copy()
+                kk = k
+                for i, j in enumerate(ends):
+                    b = (e >> (len(ends) - 1 - i)) & 1
+                    _cut_factor(s, n, cq[j], b, upper)
+                    kk |= b << (c - 1 - j)
+                out[:, kk] = s
+            return
+        lv = levels[li]
+        m = len(lv["cuts"])
+        for b in range(1 << m):
+            s = psi.copy()
+            kk = k
+            for i, j in enumerate(lv["cuts"]):
+                bb = (b >> (m - 1 - i)) & 1
+                _cut_factor(s, n, cq[j], bb, upper)
+                kk |= bb << (c - 1 - j)
+            for oi in lv["ops"]:
+                _apply(s, n, side["ops"][oi])
+            rec(s, li + 1, kk)
+
+    rec(psi0, 0, 0)
+    return out
+
+
+@pytest.mark.parametrize("rows,cols,depth,mask", [
+    (4, 4, 10, W.grid_rows_mask(4, 4, [0, 1])),
+    (4, 4, 16, W.grid_cols_mask(4, 4, [0, 1])),
+    (3, 4, 18, W.grid_rows_mask(3, 4, [0]) | 0b0011 << 4),
+    (2, 6, 12, W.grid_cols_mask(2, 6, [0, 2, 4])),
+])
+def test_tree_schedule_replays_to_oracle(rows, cols, depth, mask):
+    text = W.random_grid_circuit(rows, cols, depth, 3)
+    p = Q.Plan(text, mask)
+    d = p.dump()
+    oc = OC.parse(text)
+    c = p.n_cuts
+    assert c > 0
+    for si, upper in enumerate((True, False)):
+        side = d["sides"][si]
+        got = replay(side, d["cuts"], c)
+        ref = P.half_states(oc, mask, upper)
+        assert np.max(np.abs(got - ref)) < 1e-12

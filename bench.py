@@ -1,0 +1,299 @@
+#!/usr/bin/env python
+"""Throughput of the CZ-partition hot path on one MI355X.
+
+A step is one pass of the whole hot path over the workload: every copy of
+both half circuits simulated on the GPU (qs_run_halves over [0, 2^c)), then
+the assembly amp(u, l) = sum_k U_k[u] L_k[l] and the FP64 probability sums
+(qs_amplitudes_device).  The bitstrings are registered (uploaded) before the
+timed region and the amplitudes stay in HBM, so the timed work is device work
+plus its host-side launches.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                       [--prec fp32|bf16x3] [--no-cpu-baseline] [--no-plain]
+
+Prints one JSON line.  ``value`` is output amplitudes per second.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {0: 157.3, 1: 2500.0}   # FP32 MFMA; dense BF16 MFMA
+
+
+def _kernel_source_hash() -> str:
+    path = os.path.join(ROOT, "paper_1802_06952_amd", "csrc", "kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic_from_profile(kernel_family: str, workload: str):
+    """HBM bytes per launch from a committed counter summary, if it matches the current kernels."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_family}_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except Exception:
+        return None
+    if d.get("kernels_hip_sha256_16") != _kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, n_copies: int, n_values: int):
+    """The FP64 oracle on the host on a bounded sample of the same workload."""
+    import numpy as np
+    import torch
+    from oracle import circuit as OC, partition as P
+    from workloads import product_bitstrings
+
+    oc = OC.parse(w.circuit_text())
+    c = len(P.find_cuts(oc, w.upper_mask))
+    total = 1 << c
+    k1 = min(total, n_copies)
+    _, u, l = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
+    t0 = time.perf_counter()
+    A, B = P.gathered_halves(oc, w.upper_mask, u[:n_values].astype(np.int64),
+                             l[:n_values].astype(np.int64), 0, k1)
+    (A @ B.T)
+    dt = time.perf_counter() - t0
+    # the gathered set size hardly matters (full half states are simulated);
+    # the whole job runs every copy: scale the time by the copy count
+    scaled = dt * total / k1
+    m = w.n_u * w.n_l
+    return {"value": m / scaled, "unit": "amplitudes/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle on copies [0, {k1}) of {total} (both halves, prefix reuse "
+                      f"over cut layers, {n_values} upper x {n_values} lower values gathered): "
+                      f"{dt:.2f} s, scaled by {total}/{k1} copies to the whole job of {m} amplitudes"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="grid6x7_d20")
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--plain-copies", type=int, default=16)
+    ap.add_argument("--cpu-copies", type=int, default=64)
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="after the steps, copy a tensor of this size (for counter calibration)")
+    a = ap.parse_args()
+
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (copies of a half circuit are independent; "
+              "the multi-GPU split is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    import paper_1802_06952_amd as Q
+    from workloads import product_bitstrings, workload
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    prec = 0 if a.prec == "fp32" else 1
+    w = workload(a.workload)
+    text = w.circuit_text()
+    bits, u_vals, l_vals = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
+    m = int(bits.size)
+    plan = Q.Plan(text, w.upper_mask)
+    c = plan.n_cuts
+    k0 = w.copy_begin
+    k1 = w.copy_end if w.copy_end is not None else (1 << c)
+    stream = torch.cuda.current_stream()
+    d_out = torch.empty(2 * m, dtype=torch.float32, device="cuda")
+    d_sums = torch.zeros(2, dtype=torch.float64, device="cuda")
+
+    t_setup = time.perf_counter()
+    plan.run_halves(k0, k1, bits, stream)           # registers bitstrings, plans and uploads
+    plan.amplitudes_device(prec, d_out.data_ptr(), d_sums.data_ptr(), stream)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+
+    def step(p):
+        plan.reset(keep_bitstrings=True)
+        plan.run_halves(k0, k1, None, stream)
+        plan.amplitudes_device(p, d_out.data_ptr(), d_sums.data_ptr(), stream)
+
+    for _ in range(a.warmup):
+        step(prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        step(prec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / a.steps
+    value = m / (ms_per_step / 1000.0)
+
+    # per-kernel-family device time with HIP events on the launch stream
+    plan.set_timing(True)
+    for _ in range(a.steps):
+        step(prec)
+    torch.cuda.synchronize()
+    tm = plan.timing()
+    plan.set_timing(False)
+    fam_ms = {"pass": tm["pass_ms"], "tail": tm["tail_ms"], "gemm": tm["gemm_ms"], "other": tm["other_ms"]}
+    per_step = {k: v / a.steps for k, v in fam_ms.items()}
+    launches = {"pass": tm["pass_launches"] / a.steps, "tail": tm["tail_launches"] / a.steps,
+                "gemm": tm["gemm_launches"] / a.steps, "other": tm["other_launches"] / a.steps}
+    dominant = max(("pass", "tail", "gemm"), key=lambda k: fam_ms[k])
+    if dominant == "tail":
+        flops_per_step = tm["tail_flops"] / a.steps
+        t = per_step["tail"] / 1000.0
+        achieved = flops_per_step / t / 1e12
+        roof = {"kernel": "k_tail", "bound": "alu", "achieved": round(achieved, 3),
+                "peak": 157.3, "unit": "TFLOP/s", "frac": round(achieved / 157.3, 4),
+                "traffic": _traffic_from_profile("k_tail", w.name),
+                "note": "2x2 complex gate flops on the light-cone subspaces (14 per amplitude per gate)"}
+    elif dominant == "pass":
+        bytes_per_step = tm["pass_bytes"] / a.steps
+        avg_launch_s = per_step["pass"] / 1000.0 / max(1.0, launches["pass"])
+        per_launch = bytes_per_step / max(1.0, launches["pass"])
+        achieved = per_launch / avg_launch_s / 1e9
+        traffic = _traffic_from_profile("k_pass", w.name)
+        roof = {"kernel": "k_pass", "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "algorithmic_bytes_per_launch": per_launch,
+                "avg_launch_us": avg_launch_s * 1e6}
+    else:
+        flops_per_step = tm["gemm_flops"] / a.steps
+        t = per_step["gemm"] / 1000.0
+        achieved = flops_per_step / t / 1e12
+        peak = MFMA_PEAK_TFLOPS[prec]
+        roof = {"kernel": "k_zgemm_tn_f32" if prec == 0 else "k_zgemm_tn_bf16x3", "bound": "mfma",
+                "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4),
+                "traffic": _traffic_from_profile("k_zgemm", w.name),
+                "note": "FP32-equivalent flops 8*M*N*K" if prec else "8*M*N*K"}
+
+    # executed and flat (paper accounting) amp-updates
+    oc_gates = [ln.split() for ln in text.splitlines() if ln and ln[0].isdigit()]
+    n_u, n_l = plan.n_upper, plan.n_lower
+    g_side = [0, 0]
+    upper = w.upper_mask
+    for g in oc_gates:
+        qs = [int(x) for x in g[2:]]
+        sides = {0 if (upper >> q) & 1 else 1 for q in qs}
+        for s in sides:
+            g_side[s] += 1
+    flat_updates = (k1 - k0) * (g_side[0] * 2.0 ** n_u + g_side[1] * 2.0 ** n_l)
+    amp_updates_per_s = flat_updates / (ms_per_step / 1000.0)
+
+    out = {
+        "metric": "output amplitudes/s and half-circuit amp-updates/s at 42q d20; HBM/MFMA %peak",
+        "value": round(value, 1),
+        "unit": "amplitudes/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.rows}x{w.cols} grid ({w.n} qubits), depth {w.depth}, seed "
+                               f"{w.seed}; {n_u}+{n_l} halves, {c} cut CZ, copies [{k0}, {k1}); "
+                               f"{w.n_u} x {w.n_l} product-set bitstrings",
+                   "qubits": w.n, "depth": w.depth, "cuts": c, "copies": k1 - k0, "bitstrings": m,
+                   "assembly": "fp32 mfma" if prec == 0 else "split-bf16 (3 products) mfma"},
+        "amp_updates_per_s_flat": amp_updates_per_s,
+        "device_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
+        "launches_per_step": launches,
+        "setup_s": round(setup_s, 3),
+        "roofline": roof,
+    }
+
+    # split-BF16 assembly on the same simulated halves
+    if prec == 0:
+        for _ in range(2):
+            step(1)
+        torch.cuda.synchronize()
+        tb0 = time.perf_counter()
+        for _ in range(a.steps):
+            step(1)
+        torch.cuda.synchronize()
+        out["value_split_bf16"] = round(m / ((time.perf_counter() - tb0) / a.steps), 1)
+        step(prec)
+        torch.cuda.synchronize()
+
+    # host-API rate: bitstrings from host memory, amplitudes back to host memory
+    hp = Q.Plan(text, w.upper_mask)
+    hp.run_halves(k0, k1, bits)
+    hp.amplitudes(bits, prec)
+    th0 = time.perf_counter()
+    for _ in range(2):
+        hp.reset(keep_bitstrings=False)
+        hp.run_halves(k0, k1, bits)
+        amp_h, _ = hp.amplitudes(bits, prec)
+    out["host_api_value"] = round(m / ((time.perf_counter() - th0) / 2), 1)
+    hp.close()
+
+    if not a.no_check:
+        gpath = os.path.join(ROOT, "tests", "golden", f"{w.name}.npz")
+        if os.path.exists(gpath):
+            g = np.load(gpath)
+            amp = d_out.cpu().numpy().view(np.complex64).reshape(w.n_u, w.n_l)
+            nu, nl = len(g["u"]), len(g["l"])
+            sub = amp[:nu, :nl].reshape(-1).astype(np.complex128)
+            ref = g["amp"]
+            out["check"] = {"rel_err_vs_oracle_subset": float(np.linalg.norm(sub - ref) / np.linalg.norm(ref)),
+                            "subset": f"{nu} x {nl}"}
+        sums = d_sums.cpu().numpy()
+        out["stats"] = {"sum_p": float(sums[0]), "2^n mean p": float(np.ldexp(sums[0] / m, w.n)),
+                        "2^2n mean p^2": float(np.ldexp(sums[1] / m, 2 * w.n))}
+
+    if not a.no_plain:
+        pc = min(a.plain_copies, k1 - k0)
+        pp = Q.Plan(text, w.upper_mask, plain=True)
+        pp.run_halves(k0, k0 + pc, bits)
+        torch.cuda.synchronize()
+        pp.reset(keep_bitstrings=True)
+        tp0 = time.perf_counter()
+        pp.run_halves(k0, k0 + pc, None, stream)
+        pp.amplitudes_device(0, d_out.data_ptr(), d_sums.data_ptr(), stream)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp0
+        scaled = tp * (k1 - k0) / pc
+        out["plain_fp32"] = {"value": round(m / scaled, 2), "unit": "amplitudes/s",
+                             "sample": f"flat per-copy form (no shared prefix, one gate per pass, "
+                                       f"full leaf states) on {pc} of {k1 - k0} copies: {tp:.3f} s, "
+                                       f"extrapolated linearly"}
+        pp.close()
+
+    if a.calib_copy_gib > 0:
+        nbytes = int(a.calib_copy_gib * (1 << 30))
+        x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = nbytes
+        del x, y
+
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_copies, 64)
+
+    plan.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -68,6 +68,9 @@ typedef struct {
   int coalesce_bits;      /* low qubits always inside a tile (contiguous runs of 2^b amplitudes) */
   int tail_max_qubits;    /* largest light cone the leaf evaluation accepts (0..10) */
   int materialize_level;  /* force the last materialised tree level (-1 = cost model) */
+  int plain;              /* 1 = the paper's flat per-copy form, for comparison: every copy
+                             simulated from |0> on its own (no shared prefix), one gate per
+                             full-state pass, full leaf states then a gather */
   size_t mem_budget;      /* bytes of device memory the plan may hold for states */
 } qs_options;
 
@@ -90,7 +93,7 @@ void qs_circuit_free(qs_circuit* circ);
  * E_int of Supp. A), builds the two half programs and uploads nothing yet.
  * opts may be NULL.  The plan keeps its own copy of the circuit.
  * Errors: QS_ERR_ARG (mask empty, full, or naming qubits >= n; a half with
- * more than 34 qubits), QS_ERR_UNSUPPORTED (more than 40 cut gates). */
+ * more than 32 qubits), QS_ERR_UNSUPPORTED (more than 40 cut gates). */
 qs_status qs_partition(const qs_circuit* circ, uint64_t upper_mask, const qs_options* opts,
                        qs_plan** out);
 
@@ -106,12 +109,17 @@ void qs_plan_free(qs_plan* plan);
 
 /* Simulate the copies k in [copy_begin, copy_end) of both halves on the GPU
  * and keep, for each, the half amplitudes at the upper and lower parts of the
- * m bitstrings (host array).  The first call registers the bitstrings; later
- * calls must pass the same set (same values, same order) and add further copy
- * ranges; a copy range may not be run twice.  Asynchronous on hip_stream (a
- * hipStream_t, NULL = default stream) apart from the upload of the inputs.
- * Errors: QS_ERR_ARG (range outside [0, 2^c), empty, bits >= n, m == 0),
- * QS_ERR_STATE (different bitstrings, overlapping range), QS_ERR_OOM, QS_ERR_HIP. */
+ * m bitstrings (host array).  The first call registers the bitstrings (they
+ * must form, up to a factor 4, a product set of upper x lower values: Sec.
+ * 2.3.1 samples the halves and takes their tensor product); later calls pass
+ * the same set (same values, same order) or bitstrings = NULL and m = 0 for
+ * the registered set, and add further copy ranges; a copy range may not be run
+ * twice.  Asynchronous on hip_stream (a hipStream_t, NULL = default stream)
+ * once the plan has seen the same copy blocks before; the first call of a
+ * block plans it and uploads its descriptors (host work, one stream sync).
+ * Errors: QS_ERR_ARG (range outside [0, 2^c), empty, bits >= n, no
+ * bitstrings), QS_ERR_STATE (different bitstrings, overlapping range),
+ * QS_ERR_UNSUPPORTED (not a product set), QS_ERR_OOM, QS_ERR_HIP. */
 qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
                         const uint64_t* bitstrings, size_t m, void* hip_stream);
 
@@ -125,15 +133,29 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
 qs_status qs_amplitudes(qs_plan* plan, const uint64_t* bitstrings, size_t m, qs_precision prec,
                         float* out_c64, double* out_stats, void* hip_stream);
 
-/* Forget every run copy and registered bitstring of the plan (device buffers
- * are kept for reuse). */
-qs_status qs_plan_reset(qs_plan* plan);
+/* Device-resident variant of qs_amplitudes for the registered bitstrings:
+ * d_out_c64 (device, 2*m floats in registration order) and d_out_sums (device,
+ * nullable, 2 doubles: sum |a|^2 and sum |a|^4 in FP64) are written on
+ * hip_stream without any host transfer or synchronisation.  Copies must have
+ * been run.  Errors: QS_ERR_ARG, QS_ERR_STATE, QS_ERR_HIP. */
+qs_status qs_amplitudes_device(qs_plan* plan, qs_precision prec, float* d_out_c64,
+                               double* d_out_sums, void* hip_stream);
 
-/* Device time in milliseconds spent by the last qs_run_halves/qs_amplitudes
- * calls, split by kernel family: out[0] full-state passes, out[1] leaf
- * evaluation, out[2] assembly GEMM, out[3] other (initialisation, transfers,
- * reductions).  Only filled when timing was enabled with qs_set_timing. */
-qs_status qs_get_timing(const qs_plan* plan, double* out4);
+/* Forget every run copy of the plan.  keep_bitstrings = 1 keeps the
+ * registered bitstrings (a new round of qs_run_halves may pass NULL);
+ * 0 forgets them too.  Device buffers and cached block plans are kept. */
+qs_status qs_plan_reset(qs_plan* plan, int keep_bitstrings);
+
+/* Device time in milliseconds, measured with HIP events on the plan's stream,
+ * accumulated since qs_set_timing(plan, 1), by kernel family:
+ * out[0] full-state passes, out[1] leaf evaluation, out[2] assembly GEMM,
+ * out[3] gather and FP64 reductions; out[4..7] the number of launches of each
+ * family; out[8] the algorithmic bytes of the full-state passes (reads and
+ * writes of the half states), out[9] the assembly flops (8 M N K per block,
+ * FP32-equivalent), out[10] the 2x2-gate flops of the leaf evaluation (14 per
+ * amplitude per gate on the light-cone subspaces).  Synchronises with the
+ * recorded events.  out has 11 doubles. */
+qs_status qs_get_timing(qs_plan* plan, double* out11);
 qs_status qs_set_timing(qs_plan* plan, int enable);
 
 #ifdef __cplusplus

@@ -29,7 +29,8 @@ _STATUS = {0: "QS_OK", -1: "QS_ERR_ARG", -2: "QS_ERR_PARSE", -3: "QS_ERR_UNSUPPO
 
 EXPORTED = ("qs_last_error", "qs_load_circuit", "qs_circuit_info", "qs_circuit_free",
             "qs_partition", "qs_plan_info", "qs_plan_dump", "qs_plan_free", "qs_run_halves",
-            "qs_amplitudes", "qs_plan_reset", "qs_get_timing", "qs_set_timing")
+            "qs_amplitudes", "qs_amplitudes_device", "qs_plan_reset", "qs_get_timing",
+            "qs_set_timing")
 
 
 class QSError(RuntimeError):
@@ -40,7 +41,7 @@ class QSError(RuntimeError):
 
 class qs_options(C.Structure):
     _fields_ = [("tile_bits", C.c_int), ("coalesce_bits", C.c_int), ("tail_max_qubits", C.c_int),
-                ("materialize_level", C.c_int), ("mem_budget", C.c_size_t)]
+                ("materialize_level", C.c_int), ("plain", C.c_int), ("mem_budget", C.c_size_t)]
 
 
 def _load() -> C.CDLL:
@@ -61,7 +62,8 @@ def _load() -> C.CDLL:
     lib.qs_run_halves.argtypes = [vp, C.c_uint64, C.c_uint64, u64p, C.c_size_t, vp]
     lib.qs_amplitudes.argtypes = [vp, u64p, C.c_size_t, C.c_int, C.POINTER(C.c_float),
                                   C.POINTER(C.c_double), vp]
-    lib.qs_plan_reset.argtypes = [vp]
+    lib.qs_amplitudes_device.argtypes = [vp, C.c_int, vp, vp, vp]
+    lib.qs_plan_reset.argtypes = [vp, C.c_int]
     lib.qs_get_timing.argtypes = [vp, C.POINTER(C.c_double)]
     lib.qs_set_timing.argtypes = [vp, C.c_int]
     for name in EXPORTED:
@@ -144,11 +146,15 @@ def qs_plan_free(plan) -> None:
     _lib.qs_plan_free(plan)
 
 
-def qs_plan_reset(plan) -> None:
-    _check(_lib.qs_plan_reset(plan))
+def qs_plan_reset(plan, keep_bitstrings: bool = False) -> None:
+    _check(_lib.qs_plan_reset(plan, 1 if keep_bitstrings else 0))
 
 
-def qs_run_halves(plan, copy_begin: int, copy_end: int, bitstrings, stream=None) -> None:
+def qs_run_halves(plan, copy_begin: int, copy_end: int, bitstrings=None, stream=None) -> None:
+    """bitstrings=None runs with the registered set."""
+    if bitstrings is None:
+        _check(_lib.qs_run_halves(plan, copy_begin, copy_end, None, 0, _stream_handle(stream)))
+        return
     b = _bits(bitstrings)
     _check(_lib.qs_run_halves(plan, copy_begin, copy_end,
                               b.ctypes.data_as(C.POINTER(C.c_uint64)), b.size,
@@ -166,14 +172,26 @@ def qs_amplitudes(plan, bitstrings, prec: int = QS_PREC_FP32, stream=None):
     return out.view(np.complex64), stats
 
 
+def qs_amplitudes_device(plan, prec: int, d_out_ptr: int, d_sums_ptr: int | None = None,
+                         stream=None) -> None:
+    """Device outputs (raw device pointers, e.g. torch tensor.data_ptr())."""
+    _check(_lib.qs_amplitudes_device(plan, prec, C.c_void_p(d_out_ptr),
+                                     C.c_void_p(d_sums_ptr) if d_sums_ptr else None,
+                                     _stream_handle(stream)))
+
+
 def qs_set_timing(plan, enable: bool) -> None:
     _check(_lib.qs_set_timing(plan, 1 if enable else 0))
 
 
-def qs_get_timing(plan) -> np.ndarray:
-    out = np.zeros(4, dtype=np.float64)
+TIMING_FIELDS = ("pass_ms", "tail_ms", "gemm_ms", "other_ms", "pass_launches", "tail_launches",
+                 "gemm_launches", "other_launches", "pass_bytes", "gemm_flops", "tail_flops")
+
+
+def qs_get_timing(plan) -> dict:
+    out = np.zeros(11, dtype=np.float64)
     _check(_lib.qs_get_timing(plan, out.ctypes.data_as(C.POINTER(C.c_double))))
-    return out
+    return dict(zip(TIMING_FIELDS, out.tolist()))
 
 
 # --------------------------------------------------------------- convenience
@@ -183,9 +201,10 @@ class Plan:
 
     def __init__(self, circuit_text: str, upper_mask: int, tile_bits: int = 0,
                  coalesce_bits: int = 0, tail_max_qubits: int = 0, materialize_level: int = -1,
-                 mem_budget: int = 0):
+                 plain: bool = False, mem_budget: int = 0):
         self._circ = qs_load_circuit(circuit_text)
-        opts = qs_options(tile_bits, coalesce_bits, tail_max_qubits, materialize_level, mem_budget)
+        opts = qs_options(tile_bits, coalesce_bits, tail_max_qubits, materialize_level,
+                          1 if plain else 0, mem_budget)
         try:
             self._plan = qs_partition(self._circ, upper_mask, opts)
         except Exception:
@@ -200,19 +219,23 @@ class Plan:
     def dump(self) -> dict:
         return qs_plan_dump(self._plan)
 
-    def run_halves(self, copy_begin: int, copy_end: int, bitstrings, stream=None) -> None:
+    def run_halves(self, copy_begin: int, copy_end: int, bitstrings=None, stream=None) -> None:
         qs_run_halves(self._plan, copy_begin, copy_end, bitstrings, stream)
 
     def amplitudes(self, bitstrings, prec: int = QS_PREC_FP32, stream=None):
         return qs_amplitudes(self._plan, bitstrings, prec, stream)
 
-    def reset(self) -> None:
-        qs_plan_reset(self._plan)
+    def amplitudes_device(self, prec: int, d_out_ptr: int, d_sums_ptr: int | None = None,
+                          stream=None) -> None:
+        qs_amplitudes_device(self._plan, prec, d_out_ptr, d_sums_ptr, stream)
+
+    def reset(self, keep_bitstrings: bool = False) -> None:
+        qs_plan_reset(self._plan, keep_bitstrings)
 
     def set_timing(self, on: bool) -> None:
         qs_set_timing(self._plan, on)
 
-    def timing(self) -> np.ndarray:
+    def timing(self) -> dict:
         return qs_get_timing(self._plan)
 
     def close(self) -> None:

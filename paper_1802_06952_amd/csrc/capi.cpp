@@ -5,7 +5,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <tuple>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -91,6 +93,27 @@ struct qs_circuit {
   Circuit c;
 };
 
+// A planned block of one half: schedule, descriptors (host and device).
+struct Prepared {
+  SidePlan sp;
+  std::vector<PassDesc> pds;
+  TailDesc td{};
+  char* dev = nullptr;  // descriptors, tail desc, ops, node copy indices (owned)
+  size_t o_pd = 0, o_td = 0, o_ops = 0, o_nk = 0, o_lk = 0;
+  std::vector<uint64_t> leaf_k;
+  double pass_bytes = 0;  // algorithmic bytes of the passes
+  double tail_flops = 0;  // 2x2-gate flops of the leaf evaluation
+  ~Prepared() {
+    if (dev) (void)hipFree(dev);
+  }
+};
+
+struct EvRec {
+  int fam;
+  int launches;
+  hipEvent_t a, b;
+};
+
 struct qs_plan {
   Circuit circ;
   uint64_t upper_mask = 0;
@@ -103,11 +126,24 @@ struct qs_plan {
   std::vector<uint32_t> vals[2];
   std::vector<int> idx[2];
   uint32_t* d_vals[2] = {nullptr, nullptr};
+  int* d_idx[2] = {nullptr, nullptr};
   std::vector<BlockRes> blocks;
   std::vector<std::pair<uint64_t, uint64_t>> ranges;
+  std::map<std::tuple<int, uint64_t, int>, std::unique_ptr<Prepared>> cache;
   bool timing = false;
+  std::vector<EvRec> events;
   double tms[4] = {0, 0, 0, 0};
-  ~qs_plan() { pool.release_all(); }
+  double counts[4] = {0, 0, 0, 0};
+  double pass_bytes = 0, gemm_flops = 0, tail_flops = 0;
+  ~qs_plan() {
+    (void)hipDeviceSynchronize();
+    for (EvRec& e : events) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    cache.clear();
+    pool.release_all();
+  }
 };
 
 namespace {
@@ -132,41 +168,51 @@ PlanKnobs knobs_of(const qs_plan* p, int S) {
     if (hipMemGetInfo(&fr, &tot) == hipSuccess) k.mem_budget = (size_t)(0.85 * (double)fr);
   }
   k.S = S;
+  k.one_op_per_pass = p->opts.plain != 0;
   return k;
 }
 
+// Records a pair of events around a family of launches on the stream; the
+// elapsed times are collected by qs_get_timing without blocking the caller.
 struct Timer {
-  bool on;
+  qs_plan* P;
   hipStream_t st;
-  hipEvent_t a = nullptr, b = nullptr;
-  double* slot;
-  Timer(bool on_, hipStream_t s, double* sl) : on(on_), st(s), slot(sl) {
-    if (on) {
+  int fam;
+  int launches = 0;
+  hipEvent_t a = nullptr;
+  Timer(qs_plan* p, hipStream_t s, int f) : P(p), st(s), fam(f) {
+    if (P->timing) {
       (void)hipEventCreate(&a);
-      (void)hipEventCreate(&b);
       (void)hipEventRecord(a, st);
     }
   }
   ~Timer() {
-    if (on) {
+    if (P->timing) {
+      hipEvent_t b = nullptr;
+      (void)hipEventCreate(&b);
       (void)hipEventRecord(b, st);
-      (void)hipEventSynchronize(b);
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, a, b);
-      *slot += ms;
-      (void)hipEventDestroy(a);
-      (void)hipEventDestroy(b);
+      P->events.push_back(EvRec{fam, launches, a, b});
     }
   }
 };
 
-// Run one side of one block: passes for the materialised levels, then the
-// leaf evaluation into X[k][s].
-qs_status run_side(qs_plan* P, int sidx, const Block& blk, float2* X, hipStream_t st) {
+// Plan one half of one block and upload its descriptors (cached per block).
+qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
+  auto key = std::make_tuple(sidx, blk.k0, blk.p);
+  auto it = P->cache.find(key);
+  if (it != P->cache.end()) {
+    *out = it->second.get();
+    return QS_OK;
+  }
+  if (P->cache.size() > 4096) {
+    (void)hipDeviceSynchronize();
+    P->cache.clear();
+  }
   const Side& s = P->side[sidx];
   const int c = (int)P->cuts.size();
   const int S = (int)P->vals[sidx].size();
-  SidePlan sp;
+  std::unique_ptr<Prepared> pr(new Prepared());
+  SidePlan& sp = pr->sp;
   std::string err;
   if (!plan_side(s, c, blk, knobs_of(P, S), sp, err)) return fail(QS_ERR_UNSUPPORTED, err);
   const Tree& tr = sp.tree;
@@ -178,11 +224,11 @@ qs_status run_side(qs_plan* P, int sidx, const Block& blk, float2* X, hipStream_
     int g = s.upper ? k.upper : k.lower;
     return (int)(std::find(s.qubits.begin(), s.qubits.end(), g) - s.qubits.begin());
   };
-  // ---- descriptors
-  std::vector<PassDesc> pds;
+  const double SB = std::ldexp(8.0, s.n);
   std::vector<DevOp> ops;
   for (const PassPlan& pp : sp.passes) {
     PassDesc d{};
+    d.wave = s.n >= 7 ? 1 : 0;
     d.n = s.n;
     d.t = (int)pp.tile.size();
     std::vector<int> work_of(s.n, -1);
@@ -203,15 +249,19 @@ qs_status run_side(qs_plan* P, int sidx, const Block& blk, float2* X, hipStream_
     if (!encode_ops(s, pp.ops_out, tr.fixed, work_of, ops, err)) return fail(QS_ERR_UNSUPPORTED, err);
     d.n_out = (int)ops.size() - d.op_out;
     d.m = 0;
+    const double nin = (double)sp.nodes[pp.level_in];
     if (pp.branch) {
       const Level& nx = tr.levels[pp.level_in + 1];
       d.m = (int)nx.cuts.size();
       for (int i = 0; i < d.m; ++i) d.bq[i] = cut_qubit(nx.cuts[i]);
+      pr->pass_bytes += (pp.init ? 0.0 : nin * SB) + (double)sp.nodes[pp.level_in + 1] * SB;
+    } else {
+      pr->pass_bytes += (pp.init ? 1.0 : 2.0) * nin * SB;
     }
     d.upper = s.upper ? 1 : 0;
-    pds.push_back(d);
+    pr->pds.push_back(d);
   }
-  TailDesc td{};
+  TailDesc& td = pr->td;
   td.n = s.n;
   td.q = (int)sp.Q.size();
   std::vector<int> work_q(s.n, -1);
@@ -220,19 +270,51 @@ qs_status run_side(qs_plan* P, int sidx, const Block& blk, float2* X, hipStream_
     work_q[sp.Q[i]] = i;
   }
   td.nlev = L - sp.lstar;
+  td.M = 0;
+  for (int l = sp.lstar + 1; l <= L; ++l) td.M += (int)tr.levels[l].cuts.size();
   std::vector<DevOp> tops;
-  for (int l = sp.lstar + 1; l <= L; ++l) {
-    TailLevel& tl = td.lev[l - sp.lstar - 1];
-    const Level& lv = tr.levels[l];
-    tl.m = (int)lv.cuts.size();
-    for (int i = 0; i < tl.m; ++i) {
-      tl.bq[i] = cut_qubit(lv.cuts[i]);
-      tl.kbit[i] = 1ULL << (c - 1 - lv.cuts[i]);
+  {
+    int shift = td.M;
+    for (int l = sp.lstar + 1; l <= L; ++l) {
+      TailLevel& tl = td.lev[l - sp.lstar - 1];
+      const Level& lv = tr.levels[l];
+      tl.m = (int)lv.cuts.size();
+      shift -= tl.m;
+      tl.shift = shift;
+      for (int i = 0; i < tl.m; ++i) {
+        tl.bq[i] = cut_qubit(lv.cuts[i]);
+        tl.kbit[i] = 1ULL << (c - 1 - lv.cuts[i]);
+      }
+      std::vector<int> rev(lv.ops.rbegin(), lv.ops.rend());
+      tl.bop0 = (int)(ops.size() + tops.size());
+      size_t before = tops.size();
+      if (!encode_ops(s, rev, tr.fixed, work_q, tops, err, true)) return fail(QS_ERR_UNSUPPORTED, err);
+      tl.bnops = (int)(tops.size() - before);
     }
-    tl.op0 = (int)(ops.size() + tops.size());
-    size_t before = tops.size();
-    if (!encode_ops(s, lv.ops, tr.fixed, work_q, tops, err)) return fail(QS_ERR_UNSUPPORTED, err);
-    tl.nops = (int)(tops.size() - before);
+  }
+  // copy-index contribution of each leaf path below the materialised level
+  pr->leaf_k.assign((size_t)1 << td.M, 0);
+  for (size_t lam = 0; lam < pr->leaf_k.size(); ++lam) {
+    uint64_t k = 0;
+    for (int l = 0; l < td.nlev; ++l) {
+      const TailLevel& tl = td.lev[l];
+      for (int i = 0; i < tl.m; ++i)
+        if ((lam >> (tl.shift + tl.m - 1 - i)) & 1) k |= tl.kbit[i];
+    }
+    pr->leaf_k[lam] = k;
+  }
+  {
+    // algorithmic flops: the per-value GEMM (8 per complex multiply-add) and
+    // the backward rows (14 per amplitude per 2x2 gate)
+    const double K = std::ldexp(1.0, td.q);
+    pr->tail_flops = 8.0 * std::ldexp(1.0, td.M) * K * (double)sp.nodes[sp.lstar] * S;
+    double paths = 1;
+    for (int l = L; l > sp.lstar; --l) {
+      double nmat = 0;
+      for (int i : tr.levels[l].ops) nmat += s.ops[i].kind == OP_MAT ? 1 : 0;
+      pr->tail_flops += (double)S * paths * 14.0 * nmat * K;
+      paths *= std::ldexp(1.0, (int)tr.levels[l].cuts.size());
+    }
   }
   td.n_end = (int)tr.end_cuts.size();
   for (int i = 0; i < td.n_end; ++i) {
@@ -256,32 +338,49 @@ qs_status run_side(qs_plan* P, int sidx, const Block& blk, float2* X, hipStream_
       if ((r >> (nb - 1 - i)) & 1) k |= 1ULL << (c - 1 - ncuts[i]);
     node_k[r] = k;
   }
-  // ---- upload (one buffer)
-  const size_t b_pd = pds.size() * sizeof(PassDesc);
+  const size_t b_pd = pr->pds.size() * sizeof(PassDesc);
   const size_t b_td = sizeof(TailDesc);
   const size_t b_ops = std::max<size_t>(1, ops.size()) * sizeof(DevOp);
   const size_t b_nk = node_k.size() * sizeof(uint64_t);
+  const size_t b_lk = pr->leaf_k.size() * sizeof(uint64_t);
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t total = al(b_pd) + al(b_td) + al(b_ops) + al(b_nk);
+  const size_t total = al(b_pd) + al(b_td) + al(b_ops) + al(b_nk) + al(b_lk);
   std::vector<char> host(total, 0);
-  size_t o_pd = 0, o_td = al(b_pd), o_ops = o_td + al(b_td), o_nk = o_ops + al(b_ops);
-  if (b_pd) std::memcpy(host.data() + o_pd, pds.data(), b_pd);
-  std::memcpy(host.data() + o_td, &td, b_td);
-  if (!ops.empty()) std::memcpy(host.data() + o_ops, ops.data(), ops.size() * sizeof(DevOp));
-  std::memcpy(host.data() + o_nk, node_k.data(), b_nk);
-  char* dev = (char*)P->pool.get(total);
-  if (!dev) return fail(QS_ERR_OOM, "descriptor buffer");
-  HIPCHECK(hipMemcpyAsync(dev, host.data(), total, hipMemcpyHostToDevice, st));
-  HIPCHECK(hipStreamSynchronize(st));
-  // ---- passes
+  pr->o_pd = 0;
+  pr->o_td = al(b_pd);
+  pr->o_ops = pr->o_td + al(b_td);
+  pr->o_nk = pr->o_ops + al(b_ops);
+  pr->o_lk = pr->o_nk + al(b_nk);
+  if (b_pd) std::memcpy(host.data() + pr->o_pd, pr->pds.data(), b_pd);
+  std::memcpy(host.data() + pr->o_td, &td, b_td);
+  if (!ops.empty()) std::memcpy(host.data() + pr->o_ops, ops.data(), ops.size() * sizeof(DevOp));
+  std::memcpy(host.data() + pr->o_nk, node_k.data(), b_nk);
+  std::memcpy(host.data() + pr->o_lk, pr->leaf_k.data(), b_lk);
+  if (hipMalloc(&pr->dev, total) != hipSuccess) {
+    (void)hipGetLastError();
+    pr->dev = nullptr;
+    return fail(QS_ERR_OOM, "descriptor buffer");
+  }
+  HIPCHECK(hipMemcpy(pr->dev, host.data(), total, hipMemcpyHostToDevice));
+  *out = pr.get();
+  P->cache[key] = std::move(pr);
+  return QS_OK;
+}
+
+// Run one half of one block: passes for the materialised levels, then the
+// leaf evaluation into X[k][s].  Asynchronous on st.
+qs_status run_side(qs_plan* P, int sidx, const Prepared& pr, float2* X, hipStream_t st) {
+  const Side& s = P->side[sidx];
+  const SidePlan& sp = pr.sp;
   const size_t SB = (size_t)8 << s.n;
   float2* cur = nullptr;
   uint64_t cur_nodes = 0;
+  const DevOp* d_ops = (const DevOp*)(pr.dev + pr.o_ops);
   {
-    Timer tm(P->timing, st, &P->tms[0]);
+    Timer tm(P, st, 0);
     for (size_t pi = 0; pi < sp.passes.size(); ++pi) {
       const PassPlan& pp = sp.passes[pi];
-      const PassDesc* dd = (const PassDesc*)(dev + o_pd) + pi;
+      const PassDesc* dd = (const PassDesc*)(pr.dev + pr.o_pd) + pi;
       if (pp.init) {
         cur_nodes = 1;
         cur = (float2*)P->pool.get(SB);
@@ -291,37 +390,54 @@ qs_status run_side(qs_plan* P, int sidx, const Block& blk, float2* X, hipStream_
         const uint64_t on = sp.nodes[pp.level_in + 1];
         float2* nxt = (float2*)P->pool.get(SB * on);
         if (!nxt) return fail(QS_ERR_OOM, "tree level states");
-        HIPCHECK(launch_pass(pds[pi], dd, (const DevOp*)(dev + o_ops), cur, nxt, cur_nodes, st));
+        HIPCHECK(launch_pass(pr.pds[pi], dd, d_ops, cur, nxt, cur_nodes, st));
         P->pool.put(cur);
         cur = nxt;
         cur_nodes = on;
       } else {
-        HIPCHECK(launch_pass(pds[pi], dd, (const DevOp*)(dev + o_ops), cur, cur, cur_nodes, st));
+        HIPCHECK(launch_pass(pr.pds[pi], dd, d_ops, cur, cur, cur_nodes, st));
       }
+      ++tm.launches;
     }
+    if (P->timing) P->pass_bytes += pr.pass_bytes;
   }
   {
-    Timer tm(P->timing, st, &P->tms[1]);
-    HIPCHECK(launch_tail(td, (const TailDesc*)(dev + o_td), (const DevOp*)(dev + o_ops), cur,
-                         P->d_vals[sidx], (const uint64_t*)(dev + o_nk), X, st));
+    Timer tm(P, st, 1);
+    const int S = (int)P->vals[sidx].size();
+    const size_t per_s = tail_w_bytes(pr.td, 1);
+    int chunk = (int)std::max<size_t>(1, ((size_t)512 << 20) / per_s);
+    chunk = std::min({chunk, S, 65535});
+    float2* W = (float2*)P->pool.get(per_s * chunk);
+    if (!W) return fail(QS_ERR_OOM, "leaf rows");
+    for (int s0 = 0; s0 < S; s0 += chunk) {
+      const int ns = std::min(chunk, S - s0);
+      HIPCHECK(launch_tail(pr.td, (const TailDesc*)(pr.dev + pr.o_td), d_ops, cur, P->d_vals[sidx],
+                           (const uint64_t*)(pr.dev + pr.o_nk), (const uint64_t*)(pr.dev + pr.o_lk),
+                           s0, ns, W, X, st));
+      tm.launches += 2;
+    }
+    P->pool.put(W);
+    if (P->timing) P->tail_flops += pr.tail_flops;
   }
-  // the stream orders later users of these buffers after the kernels above
+  // later users of these buffers are ordered after the kernels above by the stream
   P->pool.put(cur);
-  P->pool.put(dev);
   return QS_OK;
 }
 
 qs_status register_bits(qs_plan* P, const uint64_t* bits, size_t m) {
   const int n = P->circ.n;
   const uint64_t full = n == 64 ? ~0ULL : ((1ULL << n) - 1);
-  for (size_t t = 0; t < m; ++t)
-    if (bits[t] & ~full) return fail(QS_ERR_ARG, "bitstring has bits set beyond the qubit count");
   if (P->registered) {
-    if (m != P->bits.size() || std::memcmp(bits, P->bits.data(), m * 8) != 0)
+    if (bits == nullptr && m == 0) return QS_OK;
+    if (!bits || m != P->bits.size() || std::memcmp(bits, P->bits.data(), m * 8) != 0)
       return fail(QS_ERR_STATE, "bitstrings differ from the registered set");
     return QS_OK;
   }
-  P->bits.assign(bits, bits + m);
+  if (!bits || m == 0) return fail(QS_ERR_ARG, "no bitstrings registered yet");
+  for (size_t t = 0; t < m; ++t)
+    if (bits[t] & ~full) return fail(QS_ERR_ARG, "bitstring has bits set beyond the qubit count");
+  std::vector<uint32_t> vals[2];
+  std::vector<int> idx[2];
   for (int sidx = 0; sidx < 2; ++sidx) {
     const Side& s = P->side[sidx];
     std::vector<uint32_t> hv(m);
@@ -333,22 +449,79 @@ qs_status register_bits(qs_plan* P, const uint64_t* bits, size_t m) {
     std::vector<uint32_t> u = hv;
     std::sort(u.begin(), u.end());
     u.erase(std::unique(u.begin(), u.end()), u.end());
-    P->vals[sidx] = u;
-    P->idx[sidx].resize(m);
+    idx[sidx].resize(m);
     for (size_t t = 0; t < m; ++t)
-      P->idx[sidx][t] = (int)(std::lower_bound(u.begin(), u.end(), hv[t]) - u.begin());
+      idx[sidx][t] = (int)(std::lower_bound(u.begin(), u.end(), hv[t]) - u.begin());
+    vals[sidx] = std::move(u);
   }
-  const double prod = (double)P->vals[0].size() * (double)P->vals[1].size();
+  const double prod = (double)vals[0].size() * (double)vals[1].size();
   if (prod > 4.0 * (double)m + 1024.0)
     return fail(QS_ERR_UNSUPPORTED, "bitstrings are not close to a product set of upper x lower values");
   for (int sidx = 0; sidx < 2; ++sidx) {
-    const size_t bytes = P->vals[sidx].size() * sizeof(uint32_t);
-    P->d_vals[sidx] = (uint32_t*)P->pool.get(bytes);
-    if (!P->d_vals[sidx]) return fail(QS_ERR_OOM, "value table");
-    HIPCHECK(hipMemcpy(P->d_vals[sidx], P->vals[sidx].data(), bytes, hipMemcpyHostToDevice));
+    const size_t bytes = vals[sidx].size() * sizeof(uint32_t);
+    uint32_t* dv = (uint32_t*)P->pool.get(bytes);
+    int* di = (int*)P->pool.get(m * sizeof(int));
+    if (!dv || !di) return fail(QS_ERR_OOM, "value tables");
+    HIPCHECK(hipMemcpy(dv, vals[sidx].data(), bytes, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(di, idx[sidx].data(), m * sizeof(int), hipMemcpyHostToDevice));
+    P->d_vals[sidx] = dv;
+    P->d_idx[sidx] = di;
+    P->vals[sidx] = std::move(vals[sidx]);
+    P->idx[sidx] = std::move(idx[sidx]);
   }
+  P->bits.assign(bits, bits + m);
+  // a new value set changes the leaf evaluation: drop cached block plans
+  (void)hipDeviceSynchronize();
+  P->cache.clear();
   P->registered = true;
   return QS_OK;
+}
+
+// Assembly of every run block into C, then the amplitudes of the registered
+// bitstrings into d_amps and their FP64 sums into d_sums.  Asynchronous.
+qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_sums, hipStream_t st) {
+  const int M = (int)plan->vals[0].size(), N = (int)plan->vals[1].size();
+  const size_t m = plan->bits.size();
+  float2* C = (float2*)plan->pool.get((size_t)M * N * sizeof(float2));
+  const int nb = prob_partial_blocks(m);
+  double* d_part = (double*)plan->pool.get((2 * (size_t)nb + 2) * sizeof(double));
+  if (!C || !d_part) return fail(QS_ERR_OOM, "assembly buffers");
+  {
+    Timer tm(plan, st, 2);
+    bool first = true;
+    for (BlockRes& b : plan->blocks) {
+      const int K = (int)(b.k1 - b.k0);
+      const size_t wb = zgemm_workspace_bytes((int)prec, M, N, K);
+      void* work = plan->pool.get(wb);
+      if (!work) return fail(QS_ERR_OOM, "assembly workspace");
+      HIPCHECK(launch_zgemm_tn((int)prec, M, N, K, b.X[0], M, b.X[1], N, C, N, first ? 0 : 1, work, st));
+      plan->pool.put(work);
+      tm.launches += prec == QS_PREC_FP32 ? 2 : 4;
+      if (plan->timing) plan->gemm_flops += 8.0 * M * N * (double)K;
+      first = false;
+    }
+  }
+  {
+    Timer tm(plan, st, 3);
+    HIPCHECK(launch_gather_amps(C, N, plan->d_idx[0], plan->d_idx[1], m, d_amps, st));
+    HIPCHECK(launch_prob_sums(d_amps, m, d_part, d_sums ? d_sums : d_part + 2 * nb, st));
+    tm.launches += 3;
+  }
+  plan->pool.put(C);
+  plan->pool.put(d_part);
+  return QS_OK;
+}
+
+PlanKnobs dump_knobs(const qs_plan* plan, int k) {
+  PlanKnobs kn;
+  if (plan->opts.tile_bits > 0) kn.tile_bits = std::min(plan->opts.tile_bits, 13);
+  if (plan->opts.coalesce_bits > 0) kn.coalesce_bits = plan->opts.coalesce_bits;
+  if (plan->opts.tail_max_qubits > 0) kn.tail_max_qubits = std::min(plan->opts.tail_max_qubits, 10);
+  kn.force_lstar = plan->opts.materialize_level;
+  kn.mem_budget = plan->opts.mem_budget;
+  kn.S = plan->registered ? (int)plan->vals[k].size() : 1024;
+  kn.one_op_per_pass = plan->opts.plain != 0;
+  return kn;
 }
 
 }  // namespace
@@ -391,6 +564,8 @@ qs_status qs_partition(const qs_circuit* circ, uint64_t upper_mask, const qs_opt
     p->opts = qs_options{};
     p->opts.materialize_level = -1;
   }
+  if (p->opts.tile_bits < 0 || p->opts.coalesce_bits < 0 || p->opts.tail_max_qubits < 0)
+    return fail(QS_ERR_ARG, "negative option");
   std::string err;
   if (!build_partition(p->circ, upper_mask, p->cuts, p->side[0], p->side[1], err))
     return fail(QS_ERR_ARG, err);
@@ -412,19 +587,11 @@ qs_status qs_plan_dump(const qs_plan* plan, char* buf, size_t cap, size_t* neede
   if (!plan || (!buf && cap)) return fail(QS_ERR_ARG, "null pointer");
   const int c = (int)plan->cuts.size();
   Block blk;
+  if (plan->opts.plain) blk.p = c;  // the flat form plans every copy alone
   SidePlan sp[2];
   bool ok[2];
   std::string err;
-  for (int k = 0; k < 2; ++k) {
-    PlanKnobs kn;
-    if (plan->opts.tile_bits > 0) kn.tile_bits = std::min(plan->opts.tile_bits, 13);
-    if (plan->opts.coalesce_bits > 0) kn.coalesce_bits = plan->opts.coalesce_bits;
-    if (plan->opts.tail_max_qubits > 0) kn.tail_max_qubits = std::min(plan->opts.tail_max_qubits, 10);
-    kn.force_lstar = plan->opts.materialize_level;
-    kn.mem_budget = plan->opts.mem_budget;
-    kn.S = plan->registered ? (int)plan->vals[k].size() : 1024;
-    ok[k] = plan_side(plan->side[k], c, blk, kn, sp[k], err);
-  }
+  for (int k = 0; k < 2; ++k) ok[k] = plan_side(plan->side[k], c, blk, dump_knobs(plan, k), sp[k], err);
   std::string js = dump_json(plan->circ, plan->upper_mask, plan->cuts, plan->side[0],
                              plan->side[1], ok[0] ? &sp[0] : nullptr, ok[1] ? &sp[1] : nullptr);
   if (needed) *needed = js.size() + 1;
@@ -438,28 +605,31 @@ qs_status qs_plan_dump(const qs_plan* plan, char* buf, size_t cap, size_t* neede
 
 void qs_plan_free(qs_plan* plan) { delete plan; }
 
-qs_status qs_plan_reset(qs_plan* plan) {
+qs_status qs_plan_reset(qs_plan* plan, int keep_bitstrings) {
   if (!plan) return fail(QS_ERR_ARG, "null plan");
-  (void)hipDeviceSynchronize();
   for (BlockRes& b : plan->blocks)
     for (int k = 0; k < 2; ++k) plan->pool.put(b.X[k]);
   plan->blocks.clear();
   plan->ranges.clear();
-  for (int k = 0; k < 2; ++k) {
-    if (plan->d_vals[k]) plan->pool.put(plan->d_vals[k]);
-    plan->d_vals[k] = nullptr;
-    plan->vals[k].clear();
-    plan->idx[k].clear();
+  if (!keep_bitstrings) {
+    for (int k = 0; k < 2; ++k) {
+      if (plan->d_vals[k]) plan->pool.put(plan->d_vals[k]);
+      if (plan->d_idx[k]) plan->pool.put(plan->d_idx[k]);
+      plan->d_vals[k] = nullptr;
+      plan->d_idx[k] = nullptr;
+      plan->vals[k].clear();
+      plan->idx[k].clear();
+    }
+    plan->bits.clear();
+    plan->registered = false;
   }
-  plan->bits.clear();
-  plan->registered = false;
   return QS_OK;
 }
 
 qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
                         const uint64_t* bitstrings, size_t m, void* hip_stream) {
-  if (!plan || !bitstrings) return fail(QS_ERR_ARG, "null pointer");
-  if (m == 0) return fail(QS_ERR_ARG, "no bitstrings");
+  if (!plan) return fail(QS_ERR_ARG, "null plan");
+  if ((bitstrings == nullptr) != (m == 0)) return fail(QS_ERR_ARG, "bitstrings and m disagree");
   const int c = (int)plan->cuts.size();
   const uint64_t total = 1ULL << c;
   if (copy_begin >= copy_end || copy_end > total) return fail(QS_ERR_ARG, "copy range outside [0, 2^c)");
@@ -472,6 +642,7 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
   while (k < copy_end) {
     int sz = std::min(ctz64(k), c);
     while (sz > 0 && k + (1ULL << sz) > copy_end) --sz;
+    if (plan->opts.plain) sz = 0;  // the flat form runs every copy on its own
     Block blk;
     blk.k0 = k;
     blk.p = c - sz;
@@ -480,10 +651,13 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
     br.k1 = k + (1ULL << sz);
     const uint64_t Kb = 1ULL << sz;
     for (int sidx = 0; sidx < 2; ++sidx) {
+      Prepared* pr = nullptr;
+      s = prepare_side(plan, sidx, blk, &pr);
+      if (s != QS_OK) return s;
       const size_t bytes = Kb * plan->vals[sidx].size() * sizeof(float2);
       br.X[sidx] = (float2*)plan->pool.get(bytes);
       if (!br.X[sidx]) return fail(QS_ERR_OOM, "gathered half amplitudes");
-      s = run_side(plan, sidx, blk, br.X[sidx], st);
+      s = run_side(plan, sidx, *pr, br.X[sidx], st);
       if (s != QS_OK) return s;
     }
     plan->blocks.push_back(br);
@@ -499,76 +673,71 @@ qs_status qs_amplitudes(qs_plan* plan, const uint64_t* bitstrings, size_t m, qs_
   if (m == 0) return fail(QS_ERR_ARG, "no bitstrings");
   if (prec != QS_PREC_FP32 && prec != QS_PREC_SPLIT_BF16) return fail(QS_ERR_ARG, "unknown precision");
   hipStream_t st = (hipStream_t)hip_stream;
+  if (plan->registered &&
+      (m != plan->bits.size() || std::memcmp(bitstrings, plan->bits.data(), m * 8) != 0))
+    return fail(QS_ERR_STATE, "bitstrings differ from the registered set");
   if (!plan->registered || plan->blocks.empty()) {
-    if (plan->registered && (m != plan->bits.size() || std::memcmp(bitstrings, plan->bits.data(), m * 8)))
-      return fail(QS_ERR_STATE, "bitstrings differ from the registered set");
     qs_status s = qs_run_halves(plan, 0, 1ULL << plan->cuts.size(), bitstrings, m, hip_stream);
     if (s != QS_OK) return s;
-  } else {
-    if (m != plan->bits.size() || std::memcmp(bitstrings, plan->bits.data(), m * 8) != 0)
-      return fail(QS_ERR_STATE, "bitstrings differ from the registered set");
   }
-  const int M = (int)plan->vals[0].size(), N = (int)plan->vals[1].size();
-  float2* C = (float2*)plan->pool.get((size_t)M * N * sizeof(float2));
   float2* amps = (float2*)plan->pool.get(m * sizeof(float2));
-  int* d_iu = (int*)plan->pool.get(m * sizeof(int));
-  int* d_il = (int*)plan->pool.get(m * sizeof(int));
-  const int nb = prob_partial_blocks(m);
-  double* d_part = (double*)plan->pool.get((2 * (size_t)nb + 2) * sizeof(double));
-  if (!C || !amps || !d_iu || !d_il || !d_part) return fail(QS_ERR_OOM, "assembly buffers");
-  HIPCHECK(hipMemcpyAsync(d_iu, plan->idx[0].data(), m * sizeof(int), hipMemcpyHostToDevice, st));
-  HIPCHECK(hipMemcpyAsync(d_il, plan->idx[1].data(), m * sizeof(int), hipMemcpyHostToDevice, st));
-  {
-    Timer tm(plan->timing, st, &plan->tms[2]);
-    void* work = nullptr;
-    bool first = true;
-    for (BlockRes& b : plan->blocks) {
-      const int K = (int)(b.k1 - b.k0);
-      if (prec == QS_PREC_FP32) {
-        HIPCHECK(launch_zgemm_tn_f32(M, N, K, b.X[0], M, b.X[1], N, C, N, first ? 0 : 1, st));
-      } else {
-        const size_t wb = split_bf16_workspace_bytes(M, N, K);
-        work = plan->pool.get(wb);
-        if (!work) return fail(QS_ERR_OOM, "split-bf16 workspace");
-        HIPCHECK(launch_zgemm_tn_split_bf16(M, N, K, b.X[0], M, b.X[1], N, C, N, first ? 0 : 1, work, st));
-        plan->pool.put(work);
-      }
-      first = false;
-    }
-  }
-  {
-    Timer tm(plan->timing, st, &plan->tms[3]);
-    HIPCHECK(launch_gather_amps(C, N, d_iu, d_il, m, amps, st));
-    HIPCHECK(launch_prob_sums(amps, m, d_part, d_part + 2 * nb, st));
-  }
+  double* sums = (double*)plan->pool.get(2 * sizeof(double));
+  if (!amps || !sums) return fail(QS_ERR_OOM, "output buffers");
+  qs_status s = assemble(plan, prec, amps, sums, st);
+  if (s != QS_OK) return s;
   HIPCHECK(hipMemcpyAsync(out_c64, amps, m * sizeof(float2), hipMemcpyDeviceToHost, st));
-  double sums[2];
-  HIPCHECK(hipMemcpyAsync(sums, d_part + 2 * nb, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  double h[2];
+  HIPCHECK(hipMemcpyAsync(h, sums, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
   if (out_stats) {
     const double n = plan->circ.n;
-    out_stats[0] = sums[0];
-    out_stats[1] = std::ldexp(sums[0] / (double)m, (int)n);
-    out_stats[2] = std::ldexp(sums[1] / (double)m, (int)(2 * n));
+    out_stats[0] = h[0];
+    out_stats[1] = std::ldexp(h[0] / (double)m, (int)n);
+    out_stats[2] = std::ldexp(h[1] / (double)m, (int)(2 * n));
   }
-  plan->pool.put(C);
   plan->pool.put(amps);
-  plan->pool.put(d_iu);
-  plan->pool.put(d_il);
-  plan->pool.put(d_part);
+  plan->pool.put(sums);
   return QS_OK;
 }
 
-qs_status qs_get_timing(const qs_plan* plan, double* out4) {
-  if (!plan || !out4) return fail(QS_ERR_ARG, "null pointer");
-  for (int i = 0; i < 4; ++i) out4[i] = plan->tms[i];
+qs_status qs_amplitudes_device(qs_plan* plan, qs_precision prec, float* d_out_c64,
+                               double* d_out_sums, void* hip_stream) {
+  if (!plan || !d_out_c64) return fail(QS_ERR_ARG, "null pointer");
+  if (prec != QS_PREC_FP32 && prec != QS_PREC_SPLIT_BF16) return fail(QS_ERR_ARG, "unknown precision");
+  if (!plan->registered || plan->blocks.empty()) return fail(QS_ERR_STATE, "no copies run");
+  return assemble(plan, prec, (float2*)d_out_c64, d_out_sums, (hipStream_t)hip_stream);
+}
+
+qs_status qs_get_timing(qs_plan* plan, double* out10) {
+  if (!plan || !out10) return fail(QS_ERR_ARG, "null pointer");
+  // out10 holds 11 doubles (see qs.h)
+  for (EvRec& e : plan->events) {
+    HIPCHECK(hipEventSynchronize(e.b));
+    float ms = 0;
+    HIPCHECK(hipEventElapsedTime(&ms, e.a, e.b));
+    plan->tms[e.fam] += ms;
+    plan->counts[e.fam] += e.launches;
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  plan->events.clear();
+  for (int i = 0; i < 4; ++i) {
+    out10[i] = plan->tms[i];
+    out10[4 + i] = plan->counts[i];
+  }
+  out10[8] = plan->pass_bytes;
+  out10[9] = plan->gemm_flops;
+  out10[10] = plan->tail_flops;
   return QS_OK;
 }
 
 qs_status qs_set_timing(qs_plan* plan, int enable) {
   if (!plan) return fail(QS_ERR_ARG, "null plan");
+  double dummy[11];
+  (void)qs_get_timing(plan, dummy);
   plan->timing = enable != 0;
-  for (int i = 0; i < 4; ++i) plan->tms[i] = 0;
+  for (int i = 0; i < 4; ++i) plan->tms[i] = plan->counts[i] = 0;
+  plan->pass_bytes = plan->gemm_flops = plan->tail_flops = 0;
   return QS_OK;
 }
 

@@ -13,22 +13,23 @@ namespace qs {
 hipError_t launch_pass(const PassDesc& h_desc, const PassDesc* d_desc, const DevOp* d_ops,
                        const float2* in, float2* out, uint64_t n_in_nodes, hipStream_t st);
 
-// Light-cone leaf evaluation; writes X[k * ldx + s_index].
+// Light-cone leaf evaluation for the requested values s0 .. s0+ns-1: the
+// backward rows into W (tail_w_bytes(h, ns) bytes), then the contraction with
+// the materialised node states into X[k * ldx + s_index].
+size_t tail_w_bytes(const TailDesc& h, int ns);
 hipError_t launch_tail(const TailDesc& h_desc, const TailDesc* d_desc, const DevOp* d_ops,
                        const float2* states, const uint32_t* svals, const uint64_t* node_k,
-                       float2* X, hipStream_t st);
+                       const uint64_t* leaf_k, int s0, int ns, float2* W, float2* X,
+                       hipStream_t st);
 
-// C[i*ldc + j] (+)= sum_k A[k*lda + i] * B[k*ldb + j], complex64, FP32 MFMA.
-hipError_t launch_zgemm_tn_f32(int M, int N, int K, const float2* A, int lda, const float2* B,
-                               int ldb, float2* C, int ldc, int accumulate, hipStream_t st);
-
-// Same contraction with each FP32 operand split into bf16 hi + lo parts and
-// the hi*hi + hi*lo + lo*hi products accumulated in FP32 on BF16 MFMA.
-// `work` must hold split_bf16_workspace_bytes(M, N, K) bytes.
-size_t split_bf16_workspace_bytes(int M, int N, int K);
-hipError_t launch_zgemm_tn_split_bf16(int M, int N, int K, const float2* A, int lda,
-                                      const float2* B, int ldb, float2* C, int ldc,
-                                      int accumulate, void* work, hipStream_t st);
+// C[i*ldc + j] (+)= sum_k A[k*lda + i] * B[k*ldb + j], complex64.  prec 0:
+// FP32 MFMA; prec 1: split-BF16 (three bf16 products, FP32 accumulation).
+// `work` must hold zgemm_workspace_bytes(prec, M, N, K) bytes (split-K
+// partials and, for prec 1, the split operands).
+size_t zgemm_workspace_bytes(int prec, int M, int N, int K);
+hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int lda,
+                           const float2* B, int ldb, float2* C, int ldc, int accumulate,
+                           void* work, hipStream_t st);
 
 // amps[t] = C[iu[t] * ldc + il[t]].
 hipError_t launch_gather_amps(const float2* C, int ldc, const int* iu, const int* il, size_t m,

@@ -51,6 +51,20 @@ __device__ __forceinline__ void mat_apply(const float* m, float2 a, float2 b, fl
                    m[4] * a.y + m[5] * a.x + m[6] * b.y + m[7] * b.x);
 }
 
+// Register-pair 2x2 gate: pairs (r, r | 2^rb) of a per-lane register array.
+template <int R>
+__device__ __forceinline__ void tail_mat_reg(float2 (&v)[R], const float* m, int rb) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r & (1 << rb)) continue;
+    const int r1 = r | (1 << rb);
+    float2 oa, ob;
+    mat_apply(m, v[r], v[r1], oa, ob);
+    v[r] = oa;
+    v[r1] = ob;
+  }
+}
+
 // ------------------------------------------------------------------ full-state pass
 
 constexpr int kPassThreads = 256;
@@ -151,8 +165,179 @@ k_pass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops,
   }
 }
 
+// ------------------------------------------------------------------ wave-tile pass
+//
+// One wavefront owns a tile of 64 x 2^R amplitudes: lane l holds the state
+// bits 0..5 = l (so every register load or store is one contiguous 512-byte
+// run), register r holds the R state bits tbit[6..6+R-1] = bits of r.  Gates
+// on state bits 0..5 exchange partners with lane shuffles; gates on register
+// bits stay inside the lane; diagonal ops need only the index.  No LDS and
+// no barriers.
+
+constexpr int kWaveThreads = 256;
+
+// v * omega^e, omega = (1+i)/sqrt 2, e mod 8: an optional 45-degree step then a
+// quarter turn.
+__device__ __forceinline__ float2 phase_mul(float2 v, int e) {
+  const float r = 0.70710678118654752f;
+  float a = v.x, b = v.y;
+  if (e & 1) {
+    const float a2 = (a - b) * r, b2 = (a + b) * r;
+    a = a2;
+    b = b2;
+  }
+  const int q = (e >> 1) & 3;
+  float xr = (q & 1) ? -b : a;
+  float yr = (q & 1) ? a : b;
+  if (q & 2) {
+    xr = -xr;
+    yr = -yr;
+  }
+  return make_float2(xr, yr);
+}
+
+__device__ __forceinline__ float2 diag_fast(const DevOp& op, uint32_t x, float2 v) {
+  int e = __popc(x & (uint32_t)op.t0) + 2 * __popc(x & (uint32_t)op.t1) +
+          4 * __popc(x & (uint32_t)op.t2);
+  for (int i = 0; i < op.nd; ++i) e += 4 * __popc(x & (x >> op.d[i]) & (uint32_t)op.M[i]);
+  v = phase_mul(v, e);
+  return ((x & (uint32_t)op.pmask) == (uint32_t)op.pval) ? v : make_float2(0.f, 0.f);
+}
+
+template <int R>
+__device__ __forceinline__ uint32_t reg_index(int r, const uint32_t (&RB)[R]) {
+  uint32_t d = 0;
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    if ((r >> k) & 1) d |= RB[k];
+  return d;
+}
+
+template <int R>
+__device__ __forceinline__ void wave_apply_ops(float2 (&v)[1 << R], const DevOp* __restrict__ ops,
+                                               int nops, uint32_t F, const uint32_t (&RB)[R],
+                                               int lane) {
+  constexpr int E = 1 << R;
+  for (int o = 0; o < nops; ++o) {
+    const DevOp& op = ops[o];
+    if (op.kind == 0) {
+      const int w = op.target;
+      if (w < 6) {
+        const bool bit = (lane >> w) & 1;
+        const float sr = bit ? op.m[6] : op.m[0], si = bit ? op.m[7] : op.m[1];
+        const float pr = bit ? op.m[4] : op.m[2], pi = bit ? op.m[5] : op.m[3];
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const float px = __shfl_xor(v[r].x, 1 << w);
+          const float py = __shfl_xor(v[r].y, 1 << w);
+          const float2 a = v[r];
+          v[r] = make_float2(sr * a.x - si * a.y + pr * px - pi * py,
+                             sr * a.y + si * a.x + pr * py + pi * px);
+        }
+      } else {
+        const int k = w - 6;
+        if constexpr (R >= 1) { if (k == 0) tail_mat_reg<E>(v, op.m, 0); }
+        if constexpr (R >= 2) { if (k == 1) tail_mat_reg<E>(v, op.m, 1); }
+        if constexpr (R >= 3) { if (k == 2) tail_mat_reg<E>(v, op.m, 2); }
+        if constexpr (R >= 4) { if (k == 3) tail_mat_reg<E>(v, op.m, 3); }
+        if constexpr (R >= 5) { if (k == 4) tail_mat_reg<E>(v, op.m, 4); }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < E; ++r) v[r] = diag_fast(op, F | reg_index<R>(r, RB), v[r]);
+    }
+  }
+}
+
+template <int R>
+__global__ void __launch_bounds__(kWaveThreads)
+k_wpass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops, const float2* in,
+        float2* out, uint64_t total_tiles) {
+  constexpr int E = 1 << R;
+  const PassDesc& P = *pdp;
+  const int lane = threadIdx.x & 63;
+  const uint64_t wt = (uint64_t)blockIdx.x * (kWaveThreads / 64) + (threadIdx.x >> 6);
+  if (wt >= total_tiles) return;
+  const int nouter = P.n_outer;
+  const uint64_t node = wt >> nouter;
+  const uint64_t tile = wt & ((1ull << nouter) - 1);
+  uint32_t xo = 0;
+  for (int j = 0; j < nouter; ++j) xo |= (uint32_t)((tile >> j) & 1) << P.obit[j];
+  uint32_t RB[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) RB[k] = 1u << P.tbit[6 + k];
+  const uint32_t F = xo | (uint32_t)lane;
+  const uint64_t N = 1ull << P.n;
+  float2 v[E];
+  if (P.init) {
+    const uint32_t hmask = ~(uint32_t)P.hinit;
+    const float h = P.hamp;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const uint32_t x = F | reg_index<R>(r, RB);
+      v[r] = ((x & hmask) == 0) ? make_float2(h, 0.f) : make_float2(0.f, 0.f);
+    }
+  } else {
+    const float2* src = in + node * N;
+#pragma unroll
+    for (int r = 0; r < E; ++r) v[r] = src[F | reg_index<R>(r, RB)];
+  }
+  wave_apply_ops<R>(v, ops + P.op_in, P.n_in, F, RB, lane);
+  if (P.m == 0) {
+    float2* dst = out + node * N;
+#pragma unroll
+    for (int r = 0; r < E; ++r) dst[F | reg_index<R>(r, RB)] = v[r];
+    return;
+  }
+  const int m = P.m;
+  for (int b = 0; b < (1 << m); ++b) {
+    float2 w[E];
+    // cut factors of this child: a mask (upper) or a sign (lower) per cut bit
+    uint32_t cmask = 0, cval = 0, zmask = 0;
+    for (int k = 0; k < m; ++k) {
+      const uint32_t want = (b >> (m - 1 - k)) & 1;
+      const uint32_t qb = 1u << P.bq[k];
+      cmask |= qb;
+      if (want) cval |= qb;
+    }
+    if (!P.upper) {
+      zmask = cval;
+      cmask = 0;
+      cval = 0;
+    }
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const uint32_t x = F | reg_index<R>(r, RB);
+      float2 a = v[r];
+      if ((x & cmask) != cval) a = make_float2(0.f, 0.f);
+      if (__popc(x & zmask) & 1) a = make_float2(-a.x, -a.y);
+      w[r] = a;
+    }
+    wave_apply_ops<R>(w, ops + P.op_out, P.n_out, F, RB, lane);
+    float2* dst = out + ((node << m) | (uint64_t)b) * N;
+#pragma unroll
+    for (int r = 0; r < E; ++r) dst[F | reg_index<R>(r, RB)] = w[r];
+  }
+}
+
 hipError_t launch_pass(const PassDesc& h, const PassDesc* d_desc, const DevOp* d_ops,
                        const float2* in, float2* out, uint64_t n_in_nodes, hipStream_t st) {
+  if (h.wave) {
+    const int R = h.t - 6;
+    const uint64_t tiles = n_in_nodes << h.n_outer;
+    const uint64_t blocks = (tiles + (kWaveThreads / 64) - 1) / (kWaveThreads / 64);
+    if (blocks == 0 || blocks > 0x7fffffffull) return hipErrorInvalidValue;
+    dim3 g((unsigned)blocks), b(kWaveThreads);
+    switch (R) {
+      case 1: hipLaunchKernelGGL(k_wpass<1>, g, b, 0, st, d_desc, d_ops, in, out, tiles); break;
+      case 2: hipLaunchKernelGGL(k_wpass<2>, g, b, 0, st, d_desc, d_ops, in, out, tiles); break;
+      case 3: hipLaunchKernelGGL(k_wpass<3>, g, b, 0, st, d_desc, d_ops, in, out, tiles); break;
+      case 4: hipLaunchKernelGGL(k_wpass<4>, g, b, 0, st, d_desc, d_ops, in, out, tiles); break;
+      case 5: hipLaunchKernelGGL(k_wpass<5>, g, b, 0, st, d_desc, d_ops, in, out, tiles); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   const uint64_t blocks = n_in_nodes << h.n_outer;
   if (blocks == 0 || blocks > 0x7fffffffull) return hipErrorInvalidValue;
   const size_t lds = (size_t)(h.m > 0 ? 2 : 1) * ((size_t)8 << h.t);
@@ -162,6 +347,16 @@ hipError_t launch_pass(const PassDesc& h, const PassDesc* d_desc, const DevOp* d
 }
 
 // ------------------------------------------------------------------ leaf evaluation
+//
+// k_tail_bwd: per requested value s, the rows w_{s,lam} of every leaf path's
+// operator, by running the transposed leaf levels backwards from the unit
+// vector at s (the paths share their suffixes, so the backward traversal is a
+// tree too).  One group of G = min(64, 2^q) lanes per s; each lane holds
+// 2^q / G amplitudes.  Output W[s][lam][y].
+//
+// k_tail_mm: A[node, lam] at s = sum_y W[s][lam][y] v_node[x(s, y)], a complex
+// GEMM per s on FP32 MFMA; the result is written to X[k][s] for every copy k
+// the (node, lam) pair stands for (times the factors of the end cuts).
 
 constexpr int kTailThreads = 256;
 
@@ -170,22 +365,7 @@ struct TailCtx {
   uint32_t xs[R];
   int g;       // lane inside the group
   int lg;      // log2 of the group width
-  uint32_t s;  // requested half value
-  int si;      // its index
 };
-
-template <int R>
-__device__ __forceinline__ void tail_mat_reg(float2 (&v)[R], const float* m, int rb) {
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    if (r & (1 << rb)) continue;
-    const int r1 = r | (1 << rb);
-    float2 oa, ob;
-    mat_apply(m, v[r], v[r1], oa, ob);
-    v[r] = oa;
-    v[r1] = ob;
-  }
-}
 
 template <int R>
 __device__ __forceinline__ void tail_apply_ops(float2 (&v)[R], const TailCtx<R>& c,
@@ -195,15 +375,16 @@ __device__ __forceinline__ void tail_apply_ops(float2 (&v)[R], const TailCtx<R>&
     if (op.kind == 0) {
       const int w = op.target;
       if (w < c.lg) {
-        const int bit = (c.g >> w) & 1;
+        const bool bit = (c.g >> w) & 1;
+        const float sr = bit ? op.m[6] : op.m[0], si = bit ? op.m[7] : op.m[1];
+        const float pr = bit ? op.m[4] : op.m[2], pi = bit ? op.m[5] : op.m[3];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          float2 p;
-          p.x = __shfl_xor(v[r].x, 1 << w);
-          p.y = __shfl_xor(v[r].y, 1 << w);
-          float2 oa, ob;
-          if (bit) mat_apply(op.m, p, v[r], oa, ob), v[r] = ob;
-          else mat_apply(op.m, v[r], p, oa, ob), v[r] = oa;
+          const float px = __shfl_xor(v[r].x, 1 << w);
+          const float py = __shfl_xor(v[r].y, 1 << w);
+          const float2 a = v[r];
+          v[r] = make_float2(sr * a.x - si * a.y + pr * px - pi * py,
+                             sr * a.y + si * a.x + pr * py + pi * px);
         }
       } else {
         const int rb = w - c.lg;
@@ -214,102 +395,74 @@ __device__ __forceinline__ void tail_apply_ops(float2 (&v)[R], const TailCtx<R>&
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = diag_apply(op, c.xs[r], v[r]);
+      for (int r = 0; r < R; ++r) v[r] = diag_fast(op, c.xs[r], v[r]);
     }
   }
 }
 
-template <int R>
-__device__ __forceinline__ void tail_emit(const float2 (&v)[R], const TailCtx<R>& c,
-                                          const TailDesc& T, uint64_t kap, float2* __restrict__ X) {
-  // the requested index s sits at working index ys
-  uint32_t ys = 0;
-  for (int i = 0; i < T.q; ++i) ys |= ((c.s >> T.Q[i]) & 1u) << i;
-  const int G = 1 << c.lg;
-  if ((int)(ys & (G - 1)) != c.g) return;
-  const int rr = ys >> c.lg;
-  float2 val = v[0];
-#pragma unroll
-  for (int r = 1; r < R; ++r)
-    if (r == rr) val = v[r];
-  const int ne = T.n_end;
-  for (int e = 0; e < (1 << ne); ++e) {
-    float2 f = val;
-    uint64_t k = kap;
-    for (int i = 0; i < ne; ++i) {
-      const uint32_t eb = (e >> (ne - 1 - i)) & 1;
-      const uint32_t sb = (c.s >> T.eq[i]) & 1;
-      if (eb) k |= T.ekbit[i];
-      if (T.upper) {
-        if (eb != sb) f = make_float2(0.f, 0.f);
-      } else if (eb & sb) {
-        f = make_float2(-f.x, -f.y);
-      }
-    }
-    X[k * (uint64_t)T.ldx + c.si] = f;
-  }
-}
-
+// Backward traversal: level index runs from the last leaf level to the first.
 template <int R, int D>
-__device__ __forceinline__ void tail_rec(const float2 (&v)[R], const TailCtx<R>& c,
-                                         const TailDesc& T, const DevOp* __restrict__ ops,
-                                         uint64_t kap, float2* __restrict__ X) {
-  if constexpr (D >= kMaxTailLevels) {
-    tail_emit<R>(v, c, T, kap, X);
-  } else {
-    if (D == T.nlev) {
-      tail_emit<R>(v, c, T, kap, X);
-      return;
-    }
-    const TailLevel& L = T.lev[D];
+__device__ __forceinline__ void tail_bwd_rec(const float2 (&v)[R], const TailCtx<R>& c,
+                                             const TailDesc& T, const DevOp* __restrict__ ops,
+                                             uint32_t lam, float2* __restrict__ Wrow) {
+  if constexpr (D < kMaxTailLevels) {
+    const int l = T.nlev - 1 - D;
+    const TailLevel& L = T.lev[l];
+    float2 u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[r] = v[r];
+    tail_apply_ops<R>(u, c, ops + L.bop0, L.bnops);
     const int m = L.m;
+    const int G = 1 << c.lg;
     for (int b = 0; b < (1 << m); ++b) {
+      uint32_t cmask = 0, cval = 0;
+      for (int k = 0; k < m; ++k) {
+        cmask |= 1u << L.bq[k];
+        if ((b >> (m - 1 - k)) & 1) cval |= 1u << L.bq[k];
+      }
       float2 w[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        float2 a = v[r];
-        for (int k = 0; k < m; ++k) {
-          const uint32_t want = (b >> (m - 1 - k)) & 1;
-          const uint32_t xb = (c.xs[r] >> L.bq[k]) & 1;
-          if (T.upper) {
-            if (xb != want) a = make_float2(0.f, 0.f);
-          } else if (want & xb) {
-            a = make_float2(-a.x, -a.y);
-          }
+        float2 a = u[r];
+        if (T.upper) {
+          if ((c.xs[r] & cmask) != cval) a = make_float2(0.f, 0.f);
+        } else if (__popc(c.xs[r] & cval) & 1) {
+          a = make_float2(-a.x, -a.y);
         }
         w[r] = a;
       }
-      tail_apply_ops<R>(w, c, ops + L.op0, L.nops);
-      uint64_t k2 = kap;
-      for (int k = 0; k < m; ++k)
-        if ((b >> (m - 1 - k)) & 1) k2 |= L.kbit[k];
-      tail_rec<R, D + 1>(w, c, T, ops, k2, X);
+      const uint32_t lam2 = lam | ((uint32_t)b << L.shift);
+      if (l == 0) {
+        float2* dst = Wrow + (size_t)lam2 * ((size_t)G * R);
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[c.g + (r << c.lg)] = w[r];
+      } else {
+        tail_bwd_rec<R, D + 1>(w, c, T, ops, lam2, Wrow);
+      }
     }
   }
 }
 
 template <int R>
 __global__ void __launch_bounds__(kTailThreads)
-k_tail(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
-       const float2* __restrict__ states, const uint32_t* __restrict__ svals,
-       const uint64_t* __restrict__ node_k, float2* __restrict__ X) {
+k_tail_bwd(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
+           const uint32_t* __restrict__ svals, int s0, int ns, float2* __restrict__ W) {
   const TailDesc& T = *tdp;
   const int lg = T.q < 6 ? T.q : 6;
   const int G = 1 << lg;
   const uint64_t gtid = (uint64_t)blockIdx.x * kTailThreads + threadIdx.x;
   const uint64_t gid = gtid >> lg;
-  const uint64_t total = (uint64_t)T.n_nodes * (uint64_t)T.S;
-  if (gid >= total) return;
+  if (gid >= (uint64_t)ns) return;
   TailCtx<R> c;
   c.g = (int)(gtid & (G - 1));
   c.lg = lg;
-  const uint64_t node = gid / (uint64_t)T.S;
-  c.si = (int)(gid % (uint64_t)T.S);
-  c.s = svals[c.si];
-  uint32_t qmask = 0;
-  for (int i = 0; i < T.q; ++i) qmask |= 1u << T.Q[i];
-  const uint32_t base = c.s & ~qmask;
-  const float2* st = states + node * (1ull << T.n);
+  const uint32_t s = svals[s0 + gid];
+  uint32_t qmask = 0, ys = 0;
+  for (int i = 0; i < T.q; ++i) {
+    qmask |= 1u << T.Q[i];
+    ys |= ((s >> T.Q[i]) & 1u) << i;
+  }
+  const uint32_t base = s & ~qmask;
   float2 v[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -317,50 +470,42 @@ k_tail(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
     uint32_t x = base;
     for (int i = 0; i < T.q; ++i) x |= ((y >> i) & 1u) << T.Q[i];
     c.xs[r] = x;
-    v[r] = st[x];
+    v[r] = (y == ys) ? make_float2(1.f, 0.f) : make_float2(0.f, 0.f);
   }
-  tail_rec<R, 0>(v, c, T, ops, node_k[node], X);
+  const size_t K = (size_t)G * R;
+  float2* Wrow = W + gid * ((size_t)1 << T.M) * K;
+  if (T.nlev == 0) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) Wrow[c.g + (r << lg)] = v[r];
+    return;
+  }
+  tail_bwd_rec<R, 0>(v, c, T, ops, 0u, Wrow);
 }
 
-hipError_t launch_tail(const TailDesc& h, const TailDesc* d_desc, const DevOp* d_ops,
-                       const float2* states, const uint32_t* svals, const uint64_t* node_k,
-                       float2* X, hipStream_t st) {
-  const int lg = h.q < 6 ? h.q : 6;
-  const uint64_t groups = (uint64_t)h.n_nodes * (uint64_t)h.S;
-  const uint64_t threads = groups << lg;
-  const uint64_t blocks = (threads + kTailThreads - 1) / kTailThreads;
-  if (blocks == 0 || blocks > 0x7fffffffull) return hipErrorInvalidValue;
-  const int R = h.q <= 6 ? 1 : (1 << (h.q - 6));
-  dim3 g((unsigned)blocks), b(kTailThreads);
-  switch (R) {
-    case 1: hipLaunchKernelGGL(k_tail<1>, g, b, 0, st, d_desc, d_ops, states, svals, node_k, X); break;
-    case 2: hipLaunchKernelGGL(k_tail<2>, g, b, 0, st, d_desc, d_ops, states, svals, node_k, X); break;
-    case 4: hipLaunchKernelGGL(k_tail<4>, g, b, 0, st, d_desc, d_ops, states, svals, node_k, X); break;
-    case 8: hipLaunchKernelGGL(k_tail<8>, g, b, 0, st, d_desc, d_ops, states, svals, node_k, X); break;
-    case 16: hipLaunchKernelGGL(k_tail<16>, g, b, 0, st, d_desc, d_ops, states, svals, node_k, X); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
+constexpr int kTM = 64, kTN = 64, kTK = 16;
 
-// ------------------------------------------------------------------ assembly GEMM (FP32 MFMA)
-//
-// C (M x N) = A^T B with A stored k-major (A[k*lda + i]) and B stored k-major
-// (B[k*ldb + j]), complex64.  Real form: Cre = Are Bre - Aim Bim,
-// Cim = Are Bim + Aim Bre, each product on v_mfma_f32_16x16x4f32.
-
-constexpr int kGemmThreads = 256;
-constexpr int kGBM = 64, kGBN = 64, kGBK = 16;
-
-__global__ void __launch_bounds__(kGemmThreads)
-k_zgemm_tn_f32(int M, int N, int K, const float2* __restrict__ A, int lda,
-               const float2* __restrict__ B, int ldb, float2* __restrict__ C, int ldc,
-               int accumulate) {
-  __shared__ float2 As[kGBK][kGBM];
-  __shared__ float2 Bs[kGBK][kGBN];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int i_blk = blockIdx.y * kGBM, j_blk = blockIdx.x * kGBN;
+__global__ void __launch_bounds__(kTailThreads)
+k_tail_mm(const TailDesc* __restrict__ tdp, const float2* __restrict__ W,
+          const float2* __restrict__ states, const uint32_t* __restrict__ svals, int s0,
+          const uint64_t* __restrict__ node_k, const uint64_t* __restrict__ leaf_k,
+          float2* __restrict__ X) {
+  __shared__ float2 As[kTK][kTM];   // [y][lam]
+  __shared__ float2 Bs[kTK][kTN];   // [y][node]
+  __shared__ uint32_t xy[kTK];
+  const TailDesc& T = *tdp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int sl = blockIdx.z;
+  const int si = s0 + sl;
+  const uint32_t s = svals[si];
+  const int K = 1 << T.q;
+  const int Lam = 1 << T.M;
+  const int Nn = T.n_nodes;
+  const int lam0 = blockIdx.y * kTM, r0 = blockIdx.x * kTN;
+  uint32_t qmask = 0;
+  for (int i = 0; i < T.q; ++i) qmask |= 1u << T.Q[i];
+  const uint32_t base = s & ~qmask;
+  const float2* Ws = W + (size_t)sl * Lam * K;
+  const size_t N = (size_t)1 << T.n;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
   floatx4 acc_re[2][2], acc_im[2][2];
   for (int a = 0; a < 2; ++a)
@@ -368,16 +513,24 @@ k_zgemm_tn_f32(int M, int N, int K, const float2* __restrict__ A, int lda,
       acc_re[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
       acc_im[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-  for (int k0 = 0; k0 < K; k0 += kGBK) {
-    for (int e = tid; e < kGBK * kGBM; e += kGemmThreads) {
-      const int kk = e / kGBM, ii = e % kGBM;
-      const int k = k0 + kk;
-      As[kk][ii] = (k < K && i_blk + ii < M) ? A[(size_t)k * lda + i_blk + ii] : make_float2(0.f, 0.f);
-      Bs[kk][ii] = (k < K && j_blk + ii < N) ? B[(size_t)k * ldb + j_blk + ii] : make_float2(0.f, 0.f);
+  for (int y0 = 0; y0 < K; y0 += kTK) {
+    if (tid < kTK) {
+      const uint32_t y = (uint32_t)(y0 + tid);
+      uint32_t x = base;
+      for (int i = 0; i < T.q; ++i) x |= ((y >> i) & 1u) << T.Q[i];
+      xy[tid] = x;
+    }
+    __syncthreads();
+    for (int e = tid; e < kTK * kTM; e += kTailThreads) {
+      const int kk = e % kTK, ii = e / kTK;
+      const int y = y0 + kk, lam = lam0 + ii;
+      As[kk][ii] = (y < K && lam < Lam) ? Ws[(size_t)lam * K + y] : make_float2(0.f, 0.f);
+      const int rr = r0 + ii;
+      Bs[kk][ii] = (y < K && rr < Nn) ? states[(size_t)rr * N + xy[kk]] : make_float2(0.f, 0.f);
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < kGBK; kk += 4) {
+    for (int kk = 0; kk < kTK; kk += 4) {
       float2 av[2], bv[2];
       for (int a = 0; a < 2; ++a) av[a] = As[kk + (lane >> 4)][wi + a * 16 + (lane & 15)];
       for (int b = 0; b < 2; ++b) bv[b] = Bs[kk + (lane >> 4)][wj + b * 16 + (lane & 15)];
@@ -391,172 +544,366 @@ k_zgemm_tn_f32(int M, int N, int K, const float2* __restrict__ A, int lda,
     }
     __syncthreads();
   }
+  const int ne = T.n_end;
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
-      for (int e = 0; e < 4; ++e) {
-        const int i = i_blk + wi + a * 16 + 4 * (lane >> 4) + e;
-        const int j = j_blk + wj + b * 16 + (lane & 15);
-        if (i < M && j < N) {
-          float2 r = make_float2(acc_re[a][b][e], acc_im[a][b][e]);
-          float2* p = C + (size_t)i * ldc + j;
-          if (accumulate) {
-            float2 o = *p;
-            r.x += o.x;
-            r.y += o.y;
+      for (int e4 = 0; e4 < 4; ++e4) {
+        const int lam = lam0 + wi + a * 16 + 4 * (lane >> 4) + e4;
+        const int rr = r0 + wj + b * 16 + (lane & 15);
+        if (lam >= Lam || rr >= Nn) continue;
+        const float2 val = make_float2(acc_re[a][b][e4], acc_im[a][b][e4]);
+        const uint64_t kb = node_k[rr] | leaf_k[lam];
+        for (int e = 0; e < (1 << ne); ++e) {
+          float2 f = val;
+          uint64_t k = kb;
+          for (int i = 0; i < ne; ++i) {
+            const uint32_t eb = (e >> (ne - 1 - i)) & 1;
+            const uint32_t sb = (s >> T.eq[i]) & 1;
+            if (eb) k |= T.ekbit[i];
+            if (T.upper) {
+              if (eb != sb) f = make_float2(0.f, 0.f);
+            } else if (eb & sb) {
+              f = make_float2(-f.x, -f.y);
+            }
           }
-          *p = r;
+          X[k * (uint64_t)T.ldx + si] = f;
         }
       }
 }
 
-hipError_t launch_zgemm_tn_f32(int M, int N, int K, const float2* A, int lda, const float2* B,
-                               int ldb, float2* C, int ldc, int accumulate, hipStream_t st) {
-  if (M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
-  dim3 g((N + kGBN - 1) / kGBN, (M + kGBM - 1) / kGBM);
-  hipLaunchKernelGGL(k_zgemm_tn_f32, g, dim3(kGemmThreads), 0, st, M, N, K, A, lda, B, ldb, C,
-                     ldc, accumulate);
+size_t tail_w_bytes(const TailDesc& h, int ns) {
+  return (size_t)ns * ((size_t)1 << h.M) * ((size_t)1 << h.q) * sizeof(float2);
+}
+
+hipError_t launch_tail(const TailDesc& h, const TailDesc* d_desc, const DevOp* d_ops,
+                       const float2* states, const uint32_t* svals, const uint64_t* node_k,
+                       const uint64_t* leaf_k, int s0, int ns, float2* W, float2* X,
+                       hipStream_t st) {
+  if (ns <= 0) return hipSuccess;
+  const int lg = h.q < 6 ? h.q : 6;
+  const uint64_t threads = (uint64_t)ns << lg;
+  const uint64_t blocks = (threads + kTailThreads - 1) / kTailThreads;
+  const int R = h.q <= 6 ? 1 : (1 << (h.q - 6));
+  {
+    dim3 g((unsigned)blocks), b(kTailThreads);
+    switch (R) {
+      case 1: hipLaunchKernelGGL(k_tail_bwd<1>, g, b, 0, st, d_desc, d_ops, svals, s0, ns, W); break;
+      case 2: hipLaunchKernelGGL(k_tail_bwd<2>, g, b, 0, st, d_desc, d_ops, svals, s0, ns, W); break;
+      case 4: hipLaunchKernelGGL(k_tail_bwd<4>, g, b, 0, st, d_desc, d_ops, svals, s0, ns, W); break;
+      case 8: hipLaunchKernelGGL(k_tail_bwd<8>, g, b, 0, st, d_desc, d_ops, svals, s0, ns, W); break;
+      case 16: hipLaunchKernelGGL(k_tail_bwd<16>, g, b, 0, st, d_desc, d_ops, svals, s0, ns, W); break;
+      default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    const int Lam = 1 << h.M;
+    dim3 g((unsigned)((h.n_nodes + kTN - 1) / kTN), (unsigned)((Lam + kTM - 1) / kTM), (unsigned)ns);
+    if (g.y > 65535 || g.z > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_tail_mm, g, dim3(kTailThreads), 0, st, d_desc, W, states, svals, s0,
+                       node_k, leaf_k, X);
+  }
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ split-BF16 assembly
+// ------------------------------------------------------------------ assembly GEMM
 //
-// Each FP32 value a is split as hi = bf16(a) (round to nearest even) and
-// lo = bf16(a - hi).  A product a*b is taken as hi_a hi_b + hi_a lo_b + lo_a hi_b
-// (the lo*lo term, below 2^-16 relative, is dropped), accumulated in FP32 on
-// v_mfma_f32_16x16x32_bf16.  The split operands are staged in planar form
-// [k][i] per component (re, im) and part (hi, lo).
+// C (M x N) = A^T B over the copy index k, complex64, with both operands stored
+// k-major: A[k*lda + i] (upper half amplitudes), B[k*ldb + j] (lower half).
+// Real form: Cre = Are Bre - Aim Bim, Cim = Are Bim + Aim Bre.
+//
+// Workgroup tile 128 x 128 (4 waves of 64 x 64, each 4 x 4 MFMA tiles of
+// 16 x 16).  The copy index is split over gridDim.z; each split writes a
+// partial tile and k_zgemm_reduce adds the partials in a fixed order (the
+// result does not depend on scheduling).
+
+constexpr int kGemmThreads = 256;
+constexpr int kGBM = 128, kGBN = 128;
+
+static inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// FP32 MFMA: v_mfma_f32_16x16x4f32, K step 8 complex, LDS double-buffered.
+constexpr int kFK = 8;
+constexpr int kFPad = 4;
+
+__global__ void __launch_bounds__(kGemmThreads)
+k_zgemm_tn_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int lda,
+               const float2* __restrict__ B, int ldb, float2* __restrict__ out, int ldo,
+               size_t split_stride) {
+  __shared__ float2 As[2][kFK][kGBM + kFPad];
+  __shared__ float2 Bs[2][kFK][kGBN + kFPad];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int i_blk = blockIdx.y * kGBM, j_blk = blockIdx.x * kGBN;
+  const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
+  const int kb = blockIdx.z * kper;
+  const int ke = min(K, kb + kper);
+  floatx4 ar[4][4], ai[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      ar[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+      ai[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+  // each thread stages 4 complex of A and 4 of B per K step: row tid/32, cols 4*(tid%32)..+3
+  const int lr = tid >> 5, lc = (tid & 31) * 4;
+  float2 ra[4], rb[4];
+  auto gload = [&](int k0) {
+    const int k = k0 + lr;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int i = i_blk + lc + x, j = j_blk + lc + x;
+      ra[x] = (k < ke && i < M) ? A[(size_t)k * lda + i] : make_float2(0.f, 0.f);
+      rb[x] = (k < ke && j < N) ? B[(size_t)k * ldb + j] : make_float2(0.f, 0.f);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      As[buf][lr][lc + x] = ra[x];
+      Bs[buf][lr][lc + x] = rb[x];
+    }
+  };
+  int buf = 0;
+  gload(kb);
+  sstore(0);
+  __syncthreads();
+  for (int k0 = kb; k0 < ke; k0 += kFK) {
+    const bool more = k0 + kFK < ke;
+    if (more) gload(k0 + kFK);
+#pragma unroll
+    for (int kk = 0; kk < kFK; kk += 4) {
+      float2 av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[buf][kk + (lane >> 4)][wi + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[buf][kk + (lane >> 4)][wj + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          ar[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[b].x, ar[a][b], 0, 0, 0);
+          ar[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av[a].y, bv[b].y, ar[a][b], 0, 0, 0);
+          ai[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[b].y, ai[a][b], 0, 0, 0);
+          ai[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].y, bv[b].x, ai[a][b], 0, 0, 0);
+        }
+    }
+    if (more) {
+      sstore(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+  float2* o = out + (size_t)blockIdx.z * split_stride;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = i_blk + wi + a * 16 + 4 * (lane >> 4) + e;
+        const int j = j_blk + wj + b * 16 + (lane & 15);
+        if (i < M && j < N) o[(size_t)i * ldo + j] = make_float2(ar[a][b][e], ai[a][b][e]);
+      }
+}
+
+// C[i][j] = (accumulate ? C[i][j] : 0) + sum over splits of P[z][i][j], in split order.
+__global__ void k_zgemm_reduce(int M, int N, int splits, const float2* __restrict__ P,
+                               size_t split_stride, float2* __restrict__ C, int ldc, int accumulate) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)M * N) return;
+  const int i = (int)(t / N), j = (int)(t % N);
+  float2 acc = accumulate ? C[(size_t)i * ldc + j] : make_float2(0.f, 0.f);
+  for (int z = 0; z < splits; ++z) {
+    const float2 p = P[(size_t)z * split_stride + (size_t)i * N + j];
+    acc.x += p.x;
+    acc.y += p.y;
+  }
+  C[(size_t)i * ldc + j] = acc;
+}
+
+// Split-BF16: each FP32 value a is split as hi = bf16(a) (round to nearest
+// even) and lo = bf16(a - hi); a product a*b is taken as
+// hi_a hi_b + hi_a lo_b + lo_a hi_b (the dropped lo_a lo_b is below 2^-16
+// relative), accumulated in FP32 on v_mfma_f32_16x16x32_bf16.  The split
+// operands are staged as four planes (re hi, re lo, im hi, im lo), each
+// row-major over the M (or N) index with the copy index contiguous, so that a
+// lane's eight consecutive k values are one 16-byte read.
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-__global__ void k_split_bf16(const float2* __restrict__ src, int ld, int rows, int cols,
-                             int cols_pad, __hip_bfloat16* __restrict__ dst) {
-  // dst planes: [4][rows_pad][cols_pad] = re_hi, re_lo, im_hi, im_lo; rows_pad = rows rounded to 32
+constexpr int kBK = 32;
+
+__global__ void k_split_bf16(const float2* __restrict__ src, int ld, int K, int rows, int Kp,
+                             int rows_pad, __hip_bfloat16* __restrict__ dst) {
+  // dst[p][row][k], p = re_hi, re_lo, im_hi, im_lo; zero padding beyond K and rows
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int rows_pad = (rows + 31) & ~31;
-  const size_t plane = (size_t)rows_pad * cols_pad;
+  const size_t plane = (size_t)rows_pad * Kp;
   if (idx >= plane) return;
-  const int k = (int)(idx / cols_pad), i = (int)(idx % cols_pad);
-  float2 v = (k < rows && i < cols) ? src[(size_t)k * ld + i] : make_float2(0.f, 0.f);
-  __hip_bfloat16 rh = __float2bfloat16(v.x);
-  __hip_bfloat16 rl = __float2bfloat16(v.x - __bfloat162float(rh));
-  __hip_bfloat16 ih = __float2bfloat16(v.y);
-  __hip_bfloat16 il = __float2bfloat16(v.y - __bfloat162float(ih));
+  const int row = (int)(idx / Kp), k = (int)(idx % Kp);
+  const float2 v = (k < K && row < rows) ? src[(size_t)k * ld + row] : make_float2(0.f, 0.f);
+  const __hip_bfloat16 rh = __float2bfloat16(v.x);
+  const __hip_bfloat16 rl = __float2bfloat16(v.x - __bfloat162float(rh));
+  const __hip_bfloat16 ih = __float2bfloat16(v.y);
+  const __hip_bfloat16 il = __float2bfloat16(v.y - __bfloat162float(ih));
   dst[idx] = rh;
   dst[plane + idx] = rl;
   dst[2 * plane + idx] = ih;
   dst[3 * plane + idx] = il;
 }
 
-constexpr int kBBM = 64, kBBN = 64, kBBK = 32;
+__device__ __forceinline__ bf16x8 bf_neg(bf16x8 v) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 u = __builtin_bit_cast(u32x4, v);
+  u ^= 0x80008000u;
+  return __builtin_bit_cast(bf16x8, u);
+}
 
 __global__ void __launch_bounds__(kGemmThreads)
-k_zgemm_tn_bf16x3(int M, int N, int Kp, const __hip_bfloat16* __restrict__ Ap, int ldap,
-                  const __hip_bfloat16* __restrict__ Bp, int ldbp, float2* __restrict__ C, int ldc,
-                  int accumulate) {
-  // planes: Ap[p * Kp * ldap + k * ldap + i], p = 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo
-  __shared__ __hip_bfloat16 As[4][kBBK][kBBM];
-  __shared__ __hip_bfloat16 Bs[4][kBBK][kBBN];
+k_zgemm_tn_bf16x3(int M, int N, int Kp, int kper, const __hip_bfloat16* __restrict__ Ap,
+                  int Mp, const __hip_bfloat16* __restrict__ Bp, int Np, float2* __restrict__ out,
+                  int ldo, size_t split_stride) {
+  // LDS: [plane][row][k] with rows of kBK bf16 (64 bytes) plus 16 bytes of padding
+  constexpr int RS = kBK + 8;
+  __shared__ __attribute__((aligned(16))) __hip_bfloat16 As[4][kGBM][RS];
+  __shared__ __attribute__((aligned(16))) __hip_bfloat16 Bs[4][kGBN][RS];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int i_blk = blockIdx.y * kBBM, j_blk = blockIdx.x * kBBN;
-  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
-  const size_t pa = (size_t)Kp * ldap, pb = (size_t)Kp * ldbp;
-  floatx4 acc_re[2][2], acc_im[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      acc_re[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-      acc_im[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int i_blk = blockIdx.y * kGBM, j_blk = blockIdx.x * kGBN;
+  const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
+  const int kb = blockIdx.z * kper;
+  const int ke = min(Kp, kb + kper);
+  const size_t pa = (size_t)Mp * Kp, pb = (size_t)Np * Kp;
+  floatx4 ar[4][4], ai[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      ar[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+      ai[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-  for (int k0 = 0; k0 < Kp; k0 += kBBK) {
-    for (int e = tid; e < kBBK * kBBM; e += kGemmThreads) {
-      const int kk = e / kBBM, ii = e % kBBM;
-      const size_t ka = (size_t)(k0 + kk) * ldap, kb = (size_t)(k0 + kk) * ldbp;
-      for (int p = 0; p < 4; ++p) {
-        As[p][kk][ii] = Ap[p * pa + ka + i_blk + ii];
-        Bs[p][kk][ii] = Bp[p * pb + kb + j_blk + ii];
-      }
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  for (int k0 = kb; k0 < ke; k0 += kBK) {
+    // stage: 4 planes x 128 rows x 64 bytes per operand = 2048 16-byte chunks; 8 per thread
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+      const int c = tid + x * kGemmThreads;  // 0..2047
+      const int p = c >> 9, row = (c >> 2) & 127, q = c & 3;
+      const u32x4 va = *(const u32x4*)(Ap + p * pa + (size_t)(i_blk + row) * Kp + k0 + q * 8);
+      const u32x4 vb = *(const u32x4*)(Bp + p * pb + (size_t)(j_blk + row) * Kp + k0 + q * 8);
+      *(u32x4*)(&As[p][row][q * 8]) = va;
+      *(u32x4*)(&Bs[p][row][q * 8]) = vb;
     }
     __syncthreads();
-    // lane holds A[row = lane & 15][k = 8 * (lane >> 4) + 0..7]
-    bf16x8 a_[2][4], b_[2][4];
-    for (int a = 0; a < 2; ++a)
+    bf16x8 fa[4][4];  // [a tile][plane]
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
       for (int p = 0; p < 4; ++p)
-        for (int x = 0; x < 8; ++x) {
-          a_[a][p][x] = (__bf16)As[p][8 * (lane >> 4) + x][wi + a * 16 + (lane & 15)];
-          b_[a][p][x] = (__bf16)Bs[p][8 * (lane >> 4) + x][wj + a * 16 + (lane & 15)];
-        }
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) {
-        // negated imaginary parts of A for the Aim*Bim term
-        bf16x8 nih = -a_[a][2], nil = -a_[a][3];
-        floatx4 r = acc_re[a][b], im = acc_im[a][b];
-        // re += Are*Bre
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_[a][0], b_[b][0], r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_[a][0], b_[b][1], r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_[a][1], b_[b][0], r, 0, 0, 0);
-        // re -= Aim*Bim
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b_[b][2], r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b_[b][3], r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nil, b_[b][2], r, 0, 0, 0);
-        // im += Are*Bim
-        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_[a][0], b_[b][2], im, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_[a][0], b_[b][3], im, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_[a][1], b_[b][2], im, 0, 0, 0);
-        // im += Aim*Bre
-        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_[a][2], b_[b][0], im, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_[a][2], b_[b][1], im, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_[a][3], b_[b][0], im, 0, 0, 0);
-        acc_re[a][b] = r;
-        acc_im[a][b] = im;
+        fa[a][p] = *(const bf16x8*)(&As[p][wi + a * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      bf16x8 fb[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        fb[p] = *(const bf16x8*)(&Bs[p][wj + b * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        floatx4 r = ar[a][b], im = ai[a][b];
+        const bf16x8 nih = bf_neg(fa[a][2]), nil = bf_neg(fa[a][3]);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[0], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[1], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][1], fb[0], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, fb[2], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, fb[3], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nil, fb[2], r, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[2], im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[3], im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][1], fb[2], im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][2], fb[0], im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][2], fb[1], im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][3], fb[0], im, 0, 0, 0);
+        ar[a][b] = r;
+        ai[a][b] = im;
       }
+    }
     __syncthreads();
   }
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
+  float2* o = out + (size_t)blockIdx.z * split_stride;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int i = i_blk + wi + a * 16 + 4 * (lane >> 4) + e;
         const int j = j_blk + wj + b * 16 + (lane & 15);
-        if (i < M && j < N) {
-          float2 r = make_float2(acc_re[a][b][e], acc_im[a][b][e]);
-          float2* p = C + (size_t)i * ldc + j;
-          if (accumulate) {
-            float2 o = *p;
-            r.x += o.x;
-            r.y += o.y;
-          }
-          *p = r;
-        }
+        if (i < M && j < N) o[(size_t)i * ldo + j] = make_float2(ar[a][b][e], ai[a][b][e]);
       }
 }
 
-static inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+namespace {
 
-size_t split_bf16_workspace_bytes(int M, int N, int K) {
-  const size_t Kp = (size_t)round_up(K, 32);
-  return 4 * Kp * (size_t)(round_up(M, kBBM) + round_up(N, kBBN)) * sizeof(__hip_bfloat16);
+struct GemmShape {
+  int tiles, splits, kper;
+};
+
+// Enough workgroups to fill the 256 compute units a few times over.
+GemmShape gemm_shape(int M, int N, int K, int kstep) {
+  GemmShape g;
+  g.tiles = ((M + kGBM - 1) / kGBM) * ((N + kGBN - 1) / kGBN);
+  const int want = std::max(1, 1024 / std::max(1, g.tiles));
+  const int maxsplit = std::max(1, K / (4 * kstep));
+  g.splits = std::max(1, std::min({want, maxsplit, 64}));
+  g.kper = round_up((K + g.splits - 1) / g.splits, kstep);
+  g.splits = (K + g.kper - 1) / g.kper;
+  return g;
 }
 
-hipError_t launch_zgemm_tn_split_bf16(int M, int N, int K, const float2* A, int lda,
-                                      const float2* B, int ldb, float2* C, int ldc,
-                                      int accumulate, void* work, hipStream_t st) {
+}  // namespace
+
+size_t zgemm_workspace_bytes(int prec, int M, int N, int K) {
+  const int kstep = prec == 0 ? kFK : kBK;
+  const int Kp = prec == 0 ? K : round_up(K, kBK);
+  const GemmShape g = gemm_shape(M, N, Kp, kstep);
+  size_t b = (size_t)g.splits * M * N * sizeof(float2);
+  if (prec != 0)
+    b += 4 * (size_t)Kp * (round_up(M, kGBM) + round_up(N, kGBN)) * sizeof(__hip_bfloat16) + 256;
+  return b;
+}
+
+hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int lda,
+                           const float2* B, int ldb, float2* C, int ldc, int accumulate,
+                           void* work, hipStream_t st) {
   if (M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
-  const int Kp = round_up(K, 32);
-  const int Mp = round_up(M, kBBM), Np = round_up(N, kBBN);
-  __hip_bfloat16* Ap = (__hip_bfloat16*)work;
-  __hip_bfloat16* Bp = Ap + 4 * (size_t)Kp * Mp;
-  {
-    const size_t tot = (size_t)Kp * Mp;
-    hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, A, lda,
-                       K, M, Mp, Ap);
+  const int kstep = prec == 0 ? kFK : kBK;
+  const int Kp = prec == 0 ? K : round_up(K, kBK);
+  const GemmShape g = gemm_shape(M, N, Kp, kstep);
+  const size_t ss = (size_t)M * N;
+  float2* P = (float2*)work;
+  dim3 grid((N + kGBN - 1) / kGBN, (M + kGBM - 1) / kGBM, g.splits);
+  if (prec == 0) {
+    hipLaunchKernelGGL(k_zgemm_tn_f32, grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper, A, lda,
+                       B, ldb, P, N, ss);
+  } else {
+    const int Mp = round_up(M, kGBM), Np = round_up(N, kGBN);
+    char* base = (char*)work + (size_t)g.splits * ss * sizeof(float2);
+    base = (char*)(((uintptr_t)base + 255) & ~(uintptr_t)255);
+    __hip_bfloat16* Ap = (__hip_bfloat16*)base;
+    __hip_bfloat16* Bp = Ap + 4 * (size_t)Mp * Kp;
+    const size_t ta = (size_t)Mp * Kp, tb = (size_t)Np * Kp;
+    hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((ta + 255) / 256)), dim3(256), 0, st, A, lda,
+                       K, M, Kp, Mp, Ap);
+    hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, st, B, ldb,
+                       K, N, Kp, Np, Bp);
+    hipLaunchKernelGGL(k_zgemm_tn_bf16x3, grid, dim3(kGemmThreads), 0, st, M, N, Kp, g.kper, Ap,
+                       Mp, Bp, Np, P, N, ss);
   }
-  {
-    const size_t tot = (size_t)Kp * Np;
-    hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, B, ldb,
-                       K, N, Np, Bp);
-  }
-  dim3 g(Np / kBBN, Mp / kBBM);
-  hipLaunchKernelGGL(k_zgemm_tn_bf16x3, g, dim3(kGemmThreads), 0, st, M, N, Kp, Ap, Mp, Bp, Np, C,
-                     ldc, accumulate);
+  const size_t tot = ss;
+  hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, N,
+                     g.splits, P, ss, C, ldc, accumulate);
   return hipGetLastError();
 }
 

@@ -175,11 +175,15 @@ namespace {
 // in the tile; an op that does not fit is deferred together with every later
 // op that does not commute with a deferred one.
 void absorb(const Side& s, const std::vector<int>& P, std::vector<int>& S, int tmax,
-            std::vector<int>& taken, std::vector<int>& deferred) {
+            std::vector<int>& taken, std::vector<int>& deferred, bool one_op) {
   std::vector<char> nd_def(s.n, 0), any_def(s.n, 0);
   taken.clear();
   deferred.clear();
   for (int i : P) {
+    if (one_op && !taken.empty()) {
+      deferred.push_back(i);
+      continue;
+    }
     const HOp& o = s.ops[i];
     bool nd = o.kind == OP_MAT;
     bool conflict = false;
@@ -211,8 +215,16 @@ bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, Side
   std::vector<uint64_t> nodes(L + 1, 1);
   for (int l = 1; l <= L; ++l) nodes[l] = nodes[l - 1] << tree.levels[l].cuts.size();
   const double B = std::ldexp(8.0, s.n);
-  const int t = std::min(kn.tile_bits, s.n);
-  const int b = std::max(0, std::min(kn.coalesce_bits, t - 1));
+  // states of 7+ qubits use wave tiles: lanes over state bits 0..5 plus up to
+  // 5 register bits; smaller states are staged whole in LDS
+  int t, b;
+  if (s.n >= 7) {
+    t = std::max(7, std::min({kn.tile_bits, s.n, 11}));
+    b = 6;
+  } else {
+    t = s.n;
+    b = std::max(0, std::min(kn.coalesce_bits, t - 1));
+  }
 
   bool found = false;
   SidePlan best;
@@ -246,11 +258,11 @@ bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, Side
       std::vector<int> S;
       for (int q = 0; q < b; ++q) S.push_back(q);
       std::vector<int> deferred;
-      absorb(s, pending[cur], S, t, pp.ops_in, deferred);
+      absorb(s, pending[cur], S, t, pp.ops_in, deferred, kn.one_op_per_pass);
       pending[cur] = deferred;
-      if (deferred.empty() && cur < ls) {
+      if (deferred.empty() && cur < ls && !(kn.one_op_per_pass && !pp.ops_in.empty())) {
         std::vector<int> d2;
-        absorb(s, pending[cur + 1], S, t, pp.ops_out, d2);
+        absorb(s, pending[cur + 1], S, t, pp.ops_out, d2, kn.one_op_per_pass);
         pending[cur + 1] = d2;
         pp.branch = true;
         ++cur;
@@ -270,17 +282,27 @@ bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, Side
       sp.passes.push_back(pp);
       if (cur == ls && pending[ls].empty()) break;
     }
-    // leaf evaluation estimate: gather plus arithmetic per (node, value)
-    const double q = (double)Q.size();
-    double per = std::ldexp(32.0, (int)q);
-    double leaves = 1;
-    for (int l = ls + 1; l <= L; ++l) {
-      leaves *= std::ldexp(1.0, (int)tree.levels[l].cuts.size());
-      double nmat = 0, ndiag = 0;
-      for (int i : tree.levels[l].ops) (s.ops[i].kind == OP_MAT ? nmat : ndiag) += 1;
-      per += leaves * std::ldexp(1.0, (int)q) * (nmat * 16 + ndiag * 12 + 8) / 4.0;
+    // leaf evaluation estimate, in bytes at HBM speed: the backward rows per
+    // requested value (arithmetic and the W round trip), the gathers of the
+    // node amplitudes, and the per-value GEMM (arithmetic)
+    const int q = (int)Q.size();
+    const int nlev = L - ls;
+    int M = 0;
+    for (int l = ls + 1; l <= L; ++l) M += (int)tree.levels[l].cuts.size();
+    if (nlev > kMaxTailLevels || M > 16) continue;
+    const double K = std::ldexp(1.0, q), Lam = std::ldexp(1.0, M), Sd = kn.S;
+    double rev = 0, paths = 1;
+    for (int l = L; l > ls; --l) {
+      double nops = 1;
+      for (int i : tree.levels[l].ops) nops += s.ops[i].kind == OP_MAT ? 1.0 : 1.5;
+      rev += paths * nops * K;
+      paths *= std::ldexp(1.0, (int)tree.levels[l].cuts.size());
     }
-    cost += per * (double)nodes[ls] * kn.S;
+    const double flop_per_byte = 8.0;  // sustained arithmetic vs bandwidth of these kernels
+    cost += Sd * rev * 24.0 / flop_per_byte;              // backward rows
+    cost += Sd * Lam * K * 16.0;                          // W written and read
+    cost += Sd * std::ceil(Lam / 64.0) * K * (double)nodes[ls] * 64.0;  // gathers (line per element)
+    cost += Sd * Lam * K * (double)nodes[ls] * 8.0 / (4 * flop_per_byte);  // MFMA GEMM
     sp.cost_bytes = cost;
     sp.peak_states = peak;
     if (kn.mem_budget && (double)peak * B > (double)kn.mem_budget) continue;
@@ -366,7 +388,8 @@ void set_mat(DevOp& op, int mat) {
 }  // namespace
 
 bool encode_ops(const Side& s, const std::vector<int>& ops, const std::vector<int>& fixed_bits,
-                const std::vector<int>& work_of, std::vector<DevOp>& out, std::string& err) {
+                const std::vector<int>& work_of, std::vector<DevOp>& out, std::string& err,
+                bool transpose) {
   DiagAcc acc;
   for (int i : ops) {
     const HOp& o = s.ops[i];
@@ -382,6 +405,10 @@ bool encode_ops(const Side& s, const std::vector<int>& ops, const std::vector<in
         op.kind = 0;
         op.target = w;
         set_mat(op, o.mat);
+        if (transpose) {
+          std::swap(op.m[2], op.m[4]);
+          std::swap(op.m[3], op.m[5]);
+        }
         out.push_back(op);
         break;
       }

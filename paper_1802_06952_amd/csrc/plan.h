@@ -55,12 +55,13 @@ struct SidePlan {
 };
 
 struct PlanKnobs {
-  int tile_bits = 12;
+  int tile_bits = 11;
   int coalesce_bits = 5;
   int tail_max_qubits = 10;
   int force_lstar = -1;
   size_t mem_budget = 0;  // bytes; 0 = unlimited
   int S = 1;              // requested values of this half (for the cost model)
+  bool one_op_per_pass = false;  // flat comparison form: every half op is its own pass
 };
 
 bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, SidePlan& out,
@@ -69,8 +70,11 @@ bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, Side
 // Encode a sequence of half ops as kernel ops; `work_of` maps a local qubit to
 // the working bit of a MAT op (-1 if the qubit is not a working bit, which is
 // an error for MAT ops).  Diagonal ops between MATs are merged.
+// transpose = true encodes the transposed operator of the list: the caller
+// passes the ops in reverse order and every 2x2 matrix is transposed.
 bool encode_ops(const Side& s, const std::vector<int>& ops, const std::vector<int>& fixed_bits,
-                const std::vector<int>& work_of, std::vector<DevOp>& out, std::string& err);
+                const std::vector<int>& work_of, std::vector<DevOp>& out, std::string& err,
+                bool transpose = false);
 
 std::string dump_json(const Circuit& c, uint64_t upper_mask, const std::vector<Cut>& cuts,
                       const Side& up, const Side& lo, const SidePlan* pu, const SidePlan* pl);

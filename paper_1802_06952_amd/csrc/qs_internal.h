@@ -65,7 +65,7 @@ struct Side {
 
 constexpr int kMaxDiagDist = 8;
 constexpr int kMaxBranch = 8;
-constexpr int kMaxTailLevels = 10;
+constexpr int kMaxTailLevels = 12;
 constexpr int kMaxTileBits = 14;
 
 // One operation as the kernels see it.  DIAG multiplies amplitude x by
@@ -85,12 +85,15 @@ struct DevOp {
   uint64_t M[kMaxDiagDist];
 };
 
-// A full-state pass: every workgroup owns one tile of 2^t amplitudes (the
-// tile bits are state bits tbit[0..t-1], ascending, the first `coalesce` of
-// them the lowest state bits), applies `n_in` ops once, then for each of the
-// 2^m children of a branch (m = 0: a single output) applies the child's cut
-// factors and `n_out` ops and stores the tile.
+// A full-state pass: every tile of 2^t amplitudes (the tile bits are state
+// bits tbit[0..t-1]) is loaded once, gets `n_in` ops, then for each of the
+// 2^m children of a branch (m = 0: a single output) the child's cut factors
+// and `n_out` ops, and is stored.  wave = 1: one wavefront owns a tile; its
+// 64 lanes hold state bits 0..5 (tbit[0..5]) and each lane holds 2^(t-6)
+// amplitudes in registers over the state bits tbit[6..t-1].  wave = 0: one
+// workgroup stages the tile in LDS (small states).
 struct PassDesc {
+  int wave;
   int n;             // state qubits
   int t;             // tile bits
   int tbit[kMaxTileBits];
@@ -107,29 +110,35 @@ struct PassDesc {
 };
 
 struct TailLevel {
-  int m;                 // cut bits decided at this level (0 for the first, shared level)
+  int m;                 // cut bits decided at this level
   int bq[kMaxBranch];    // state bit of each cut qubit (bit 0 = MSB of b)
-  int op0, nops;         // range in the op table (MAT targets are Q indices)
+  int bop0, bnops;       // the level's ops reversed, MATs transposed (targets are Q indices)
+  int shift;             // position of the level's branch bits in the leaf index
   uint64_t kbit[kMaxBranch];  // copy-index contribution of each branch bit
 };
 
-// Leaf evaluation restricted to the light cone: for each materialised node
-// and each requested half value s, the 2^q amplitudes that differ from s only
-// on the qubits Q[0..q-1] are gathered, the tail levels are applied depth
-// first, and each leaf's amplitude at s is written (times the factors of the
-// cuts decided only at the end).
+// Leaf evaluation restricted to the light cone.  Below the materialised
+// level every operation is the same linear map for all materialised nodes,
+// and its non-diagonal gates touch only the qubits Q: the subspace of indices
+// that agree with a requested value s outside Q is invariant.  So the leaf
+// amplitude of node r, leaf path lam, at s is  sum_y w_{s,lam}[y] v_{r,s}[y],
+// where v_{r,s}[y] is node r's amplitude at s with the Q bits replaced by y and
+// w_{s,lam} is row s of the leaf path's operator, obtained by running the
+// transposed leaf levels backwards from the unit vector at s (k_tail_bwd).
+// The contraction over y is a small complex GEMM per s (k_tail_mm).  Cuts
+// with no later non-commuting gate multiply the result by their factor at s.
 struct TailDesc {
   int n;
   int q;
   int Q[16];            // state bit of working bit i
   int nlev;
+  int M;                // total branch bits of the leaf levels (leaf paths = 2^M)
   TailLevel lev[kMaxTailLevels];
   int n_end;            // cuts with no later non-commuting gate: applied to the output
   int eq[kMaxBranch * 2];   // state bit of each end cut's qubit (MSB first)
   uint64_t ekbit[kMaxBranch * 2];  // copy-index contribution of each end bit
   int upper;
   int n_nodes;          // materialised nodes
-  int nodes_per_copy_shift;  // unused
   int S;                // requested values
   int ldx;              // leading dimension (row stride) of the output X[k][s]
 };

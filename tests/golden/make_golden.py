@@ -28,7 +28,12 @@ if ROOT not in sys.path:
 
 
 def _part(args):
-    name, lo, hi, u, l, threads = args
+    name, lo, hi, u, l, threads, cache = args
+    if cache:
+        path = os.path.join(cache, f"{name}_{lo}_{hi}_{len(u)}_{len(l)}.npz")
+        if os.path.exists(path):
+            d = np.load(path)
+            return lo, d["A"], d["B"]
     import torch
     torch.set_num_threads(threads)
     from oracle import circuit as OC, partition as P
@@ -36,10 +41,14 @@ def _part(args):
     w = workload(name)
     c = OC.parse(w.circuit_text())
     A, B = P.gathered_halves(c, w.upper_mask, u, l, lo, hi)
+    if cache:
+        np.savez(path + ".tmp.npz", A=A, B=B)
+        os.replace(path + ".tmp.npz", path)
     return lo, A, B
 
 
-def make(name: str, nu: int | None, nl: int | None, workers: int, threads: int, parts: int) -> str:
+def make(name: str, nu: int | None, nl: int | None, workers: int, threads: int, parts: int,
+         cache: str | None = None) -> str:
     from oracle import circuit as OC, partition as P
     from workloads import workload, product_bitstrings
     w = workload(name)
@@ -51,7 +60,9 @@ def make(name: str, nu: int | None, nl: int | None, workers: int, threads: int, 
     u = u[: nu or len(u)].astype(np.int64)
     l = l[: nl or len(l)].astype(np.int64)
     step = max(1, (k1 - k0) // parts)
-    jobs = [(name, a, min(a + step, k1), u, l, threads) for a in range(k0, k1, step)]
+    if cache:
+        os.makedirs(cache, exist_ok=True)
+    jobs = [(name, a, min(a + step, k1), u, l, threads, cache) for a in range(k0, k1, step)]
     t0 = time.time()
     A = np.zeros((len(u), k1 - k0), dtype=np.complex128)
     B = np.zeros((len(l), k1 - k0), dtype=np.complex128)
@@ -77,8 +88,9 @@ def main():
     ap.add_argument("--workers", type=int, default=4)
     ap.add_argument("--threads", type=int, default=2)
     ap.add_argument("--parts", type=int, default=64)
+    ap.add_argument("--cache", default=None, help="directory for per-part results (resumable runs)")
     a = ap.parse_args()
-    make(a.name, a.nu, a.nl, a.workers, a.threads, a.parts)
+    make(a.name, a.nu, a.nl, a.workers, a.threads, a.parts, a.cache)
 
 
 if __name__ == "__main__":

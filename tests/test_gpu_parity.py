@@ -182,3 +182,37 @@ def test_grid6x7_d20_full_size_subset(prec):
     assert relerr(sub, g["amp"]) < TOL[prec]
     # uniform bitstrings: 2^n mean p estimates 1
     assert abs(stats[1] - 1.0) < 0.05
+
+
+def test_plain_form_and_device_outputs():
+    Q = _lib()
+    import torch
+    text = W.random_grid_circuit(4, 4, 12, 5)
+    mask = W.grid_rows_mask(4, 4, [0, 1])
+    bits, _, _ = product_bitstrings(16, mask, 32, 32, 3, 4)
+    ref = SV.simulate(OC.parse(text))[bits.astype(np.int64)]
+    say("case plain form")
+    amp, _ = run_plan(Q, text, mask, bits, plain=True)
+    assert relerr(amp, ref) < 1e-5
+    say("case device outputs")
+    p = Q.Plan(text, mask)
+    total = 1 << p.n_cuts
+    p.run_halves(0, total, bits)
+    d = torch.empty(2 * bits.size, dtype=torch.float32, device="cuda")
+    sums = torch.zeros(2, dtype=torch.float64, device="cuda")
+    p.amplitudes_device(0, d.data_ptr(), sums.data_ptr())
+    torch.cuda.synchronize()
+    got = d.cpu().numpy().view(np.complex64)
+    assert relerr(got, ref) < 1e-5
+    pr = np.abs(ref) ** 2
+    s = sums.cpu().numpy()
+    assert abs(s[0] - pr.sum()) < 1e-5 * pr.sum()
+    assert abs(s[1] - (pr ** 2).sum()) < 1e-4 * (pr ** 2).sum()
+    # a second round on the registered bitstrings, split-BF16 assembly
+    p.reset(keep_bitstrings=True)
+    p.run_halves(0, total)
+    p.amplitudes_device(1, d.data_ptr(), None)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy().view(np.complex64)
+    assert relerr(got, ref) < 1e-4
+    p.close()

@@ -100,10 +100,14 @@ qs_status qs_partition(const qs_circuit* circ, uint64_t upper_mask, const qs_opt
 /* Sizes of a plan: qubits per half and number of cut gates (copies = 1 << n_cuts). */
 qs_status qs_plan_info(const qs_plan* plan, int* n_upper, int* n_lower, int* n_cuts);
 
-/* JSON description of the plan (cuts, half programs, tree levels, passes),
- * for tests.  Writes at most cap bytes including the terminating NUL; *needed
- * receives the full size including the NUL.  buf may be NULL when cap is 0. */
-qs_status qs_plan_dump(const qs_plan* plan, char* buf, size_t cap, size_t* needed);
+/* JSON description of the plan for the first copy block of [copy_begin,
+ * copy_end) as qs_run_halves would split the range (cuts, half programs, tree
+ * levels, passes, light-cone qubits, cost estimate), for tests.  Host only.
+ * Writes at most cap bytes including the terminating NUL; *needed receives
+ * the full size including the NUL.  buf may be NULL when cap is 0.
+ * Errors: QS_ERR_ARG (null pointers, range outside [0, 2^c)). */
+qs_status qs_plan_dump(const qs_plan* plan, uint64_t copy_begin, uint64_t copy_end, char* buf,
+                       size_t cap, size_t* needed);
 
 void qs_plan_free(qs_plan* plan);
 
@@ -117,9 +121,14 @@ void qs_plan_free(qs_plan* plan);
  * twice.  Asynchronous on hip_stream (a hipStream_t, NULL = default stream)
  * once the plan has seen the same copy blocks before; the first call of a
  * block plans it and uploads its descriptors (host work, one stream sync).
+ * Assembly: when the distinct upper values times the distinct lower values
+ * are at most 4m + 1024 (the product sets of Sec. 2.3.1: sample each half,
+ * take the tensor product) the sum over copies is a GEMM over the whole
+ * value grid; otherwise every bitstring gets its own sum over copies (FP32
+ * accumulation for either precision).
  * Errors: QS_ERR_ARG (range outside [0, 2^c), empty, bits >= n, no
  * bitstrings), QS_ERR_STATE (different bitstrings, overlapping range),
- * QS_ERR_UNSUPPORTED (not a product set), QS_ERR_OOM, QS_ERR_HIP. */
+ * QS_ERR_UNSUPPORTED (a tree the kernels cannot hold), QS_ERR_OOM, QS_ERR_HIP. */
 qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
                         const uint64_t* bitstrings, size_t m, void* hip_stream);
 

@@ -56,7 +56,8 @@ def _load() -> C.CDLL:
     lib.qs_circuit_free.restype = None
     lib.qs_partition.argtypes = [vp, C.c_uint64, C.POINTER(qs_options), C.POINTER(vp)]
     lib.qs_plan_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
-    lib.qs_plan_dump.argtypes = [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
+    lib.qs_plan_dump.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_char_p, C.c_size_t,
+                                 C.POINTER(C.c_size_t)]
     lib.qs_plan_free.argtypes = [vp]
     lib.qs_plan_free.restype = None
     lib.qs_run_halves.argtypes = [vp, C.c_uint64, C.c_uint64, u64p, C.c_size_t, vp]
@@ -134,11 +135,14 @@ def qs_plan_info(plan) -> tuple[int, int, int]:
     return a.value, b.value, c.value
 
 
-def qs_plan_dump(plan) -> dict:
+def qs_plan_dump(plan, copy_begin: int = 0, copy_end: int | None = None) -> dict:
+    """Plan of the first copy block of [copy_begin, copy_end) (default: all copies)."""
+    if copy_end is None:
+        copy_end = 1 << qs_plan_info(plan)[2]
     need = C.c_size_t()
-    _check(_lib.qs_plan_dump(plan, None, 0, C.byref(need)))
+    _check(_lib.qs_plan_dump(plan, copy_begin, copy_end, None, 0, C.byref(need)))
     buf = C.create_string_buffer(need.value)
-    _check(_lib.qs_plan_dump(plan, buf, need.value, C.byref(need)))
+    _check(_lib.qs_plan_dump(plan, copy_begin, copy_end, buf, need.value, C.byref(need)))
     return json.loads(buf.value.decode())
 
 
@@ -216,8 +220,8 @@ class Plan:
     def handle(self):
         return self._plan
 
-    def dump(self) -> dict:
-        return qs_plan_dump(self._plan)
+    def dump(self, copy_begin: int = 0, copy_end: int | None = None) -> dict:
+        return qs_plan_dump(self._plan, copy_begin, copy_end)
 
     def run_halves(self, copy_begin: int, copy_end: int, bitstrings=None, stream=None) -> None:
         qs_run_halves(self._plan, copy_begin, copy_end, bitstrings, stream)

@@ -127,6 +127,7 @@ struct qs_plan {
   std::vector<int> idx[2];
   uint32_t* d_vals[2] = {nullptr, nullptr};
   int* d_idx[2] = {nullptr, nullptr};
+  bool list_mode = false;  // bitstrings far from a product set: per-bitstring sums
   std::vector<BlockRes> blocks;
   std::vector<std::pair<uint64_t, uint64_t>> ranges;
   std::map<std::tuple<int, uint64_t, int>, std::unique_ptr<Prepared>> cache;
@@ -455,8 +456,7 @@ qs_status register_bits(qs_plan* P, const uint64_t* bits, size_t m) {
     vals[sidx] = std::move(u);
   }
   const double prod = (double)vals[0].size() * (double)vals[1].size();
-  if (prod > 4.0 * (double)m + 1024.0)
-    return fail(QS_ERR_UNSUPPORTED, "bitstrings are not close to a product set of upper x lower values");
+  P->list_mode = prod > 4.0 * (double)m + 1024.0;
   for (int sidx = 0; sidx < 2; ++sidx) {
     const size_t bytes = vals[sidx].size() * sizeof(uint32_t);
     uint32_t* dv = (uint32_t*)P->pool.get(bytes);
@@ -482,32 +482,50 @@ qs_status register_bits(qs_plan* P, const uint64_t* bits, size_t m) {
 qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_sums, hipStream_t st) {
   const int M = (int)plan->vals[0].size(), N = (int)plan->vals[1].size();
   const size_t m = plan->bits.size();
-  float2* C = (float2*)plan->pool.get((size_t)M * N * sizeof(float2));
   const int nb = prob_partial_blocks(m);
   double* d_part = (double*)plan->pool.get((2 * (size_t)nb + 2) * sizeof(double));
-  if (!C || !d_part) return fail(QS_ERR_OOM, "assembly buffers");
-  {
+  if (!d_part) return fail(QS_ERR_OOM, "assembly buffers");
+  if (plan->list_mode) {
+    // the bitstrings are far from a product set: one sum over the copies per
+    // bitstring (FP32 accumulation for either precision)
     Timer tm(plan, st, 2);
     bool first = true;
     for (BlockRes& b : plan->blocks) {
       const int K = (int)(b.k1 - b.k0);
-      const size_t wb = zgemm_workspace_bytes((int)prec, M, N, K);
-      void* work = plan->pool.get(wb);
-      if (!work) return fail(QS_ERR_OOM, "assembly workspace");
-      HIPCHECK(launch_zgemm_tn((int)prec, M, N, K, b.X[0], M, b.X[1], N, C, N, first ? 0 : 1, work, st));
-      plan->pool.put(work);
-      tm.launches += prec == QS_PREC_FP32 ? 2 : 4;
-      if (plan->timing) plan->gemm_flops += 8.0 * M * N * (double)K;
+      HIPCHECK(launch_gathered_dot(K, b.X[0], M, b.X[1], N, plan->d_idx[0], plan->d_idx[1], m,
+                                   d_amps, first ? 0 : 1, st));
+      ++tm.launches;
+      if (plan->timing) plan->gemm_flops += 8.0 * (double)m * (double)K;
       first = false;
     }
+  } else {
+    float2* C = (float2*)plan->pool.get((size_t)M * N * sizeof(float2));
+    if (!C) return fail(QS_ERR_OOM, "assembly buffers");
+    {
+      Timer tm(plan, st, 2);
+      bool first = true;
+      for (BlockRes& b : plan->blocks) {
+        const int K = (int)(b.k1 - b.k0);
+        const size_t wb = zgemm_workspace_bytes((int)prec, M, N, K);
+        void* work = plan->pool.get(wb);
+        if (!work) return fail(QS_ERR_OOM, "assembly workspace");
+        HIPCHECK(launch_zgemm_tn((int)prec, M, N, K, b.X[0], M, b.X[1], N, C, N, first ? 0 : 1, work, st));
+        plan->pool.put(work);
+        tm.launches += prec == QS_PREC_FP32 ? 2 : 4;
+        if (plan->timing) plan->gemm_flops += 8.0 * M * N * (double)K;
+        first = false;
+      }
+    }
+    Timer tm(plan, st, 3);
+    HIPCHECK(launch_gather_amps(C, N, plan->d_idx[0], plan->d_idx[1], m, d_amps, st));
+    tm.launches += 1;
+    plan->pool.put(C);
   }
   {
     Timer tm(plan, st, 3);
-    HIPCHECK(launch_gather_amps(C, N, plan->d_idx[0], plan->d_idx[1], m, d_amps, st));
     HIPCHECK(launch_prob_sums(d_amps, m, d_part, d_sums ? d_sums : d_part + 2 * nb, st));
-    tm.launches += 3;
+    tm.launches += 2;
   }
-  plan->pool.put(C);
   plan->pool.put(d_part);
   return QS_OK;
 }
@@ -583,17 +601,28 @@ qs_status qs_plan_info(const qs_plan* plan, int* n_upper, int* n_lower, int* n_c
   return QS_OK;
 }
 
-qs_status qs_plan_dump(const qs_plan* plan, char* buf, size_t cap, size_t* needed) {
+qs_status qs_plan_dump(const qs_plan* plan, uint64_t copy_begin, uint64_t copy_end, char* buf,
+                       size_t cap, size_t* needed) {
   if (!plan || (!buf && cap)) return fail(QS_ERR_ARG, "null pointer");
   const int c = (int)plan->cuts.size();
+  if (copy_begin >= copy_end || copy_end > (1ULL << c)) return fail(QS_ERR_ARG, "copy range outside [0, 2^c)");
+  // the first block of the range, as qs_run_halves would split it
+  int sz = std::min(ctz64(copy_begin), c);
+  while (sz > 0 && copy_begin + (1ULL << sz) > copy_end) --sz;
+  if (plan->opts.plain) sz = 0;
   Block blk;
-  if (plan->opts.plain) blk.p = c;  // the flat form plans every copy alone
+  blk.k0 = copy_begin;
+  blk.p = c - sz;
   SidePlan sp[2];
   bool ok[2];
   std::string err;
   for (int k = 0; k < 2; ++k) ok[k] = plan_side(plan->side[k], c, blk, dump_knobs(plan, k), sp[k], err);
   std::string js = dump_json(plan->circ, plan->upper_mask, plan->cuts, plan->side[0],
                              plan->side[1], ok[0] ? &sp[0] : nullptr, ok[1] ? &sp[1] : nullptr);
+  js.pop_back();  // closing brace
+  js += ",\"block\":{\"k0\":" + std::to_string(blk.k0) + ",\"p\":" + std::to_string(blk.p) + "}";
+  if (!ok[0] || !ok[1]) js += ",\"error\":\"" + err + "\"";
+  js += "}";
   if (needed) *needed = js.size() + 1;
   if (cap) {
     size_t nb = std::min(cap - 1, js.size());

@@ -31,6 +31,11 @@ hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int l
                            const float2* B, int ldb, float2* C, int ldc, int accumulate,
                            void* work, hipStream_t st);
 
+// amps[t] (+)= sum_k A[k*lda + iu[t]] * B[k*ldb + il[t]] (one wavefront per t).
+hipError_t launch_gathered_dot(int K, const float2* A, int lda, const float2* B, int ldb,
+                               const int* iu, const int* il, size_t m, float2* amps,
+                               int accumulate, hipStream_t st);
+
 // amps[t] = C[iu[t] * ldc + il[t]].
 hipError_t launch_gather_amps(const float2* C, int ldc, const int* iu, const int* il, size_t m,
                               float2* amps, hipStream_t st);

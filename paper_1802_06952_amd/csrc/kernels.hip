@@ -909,6 +909,46 @@ hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int l
 
 // ------------------------------------------------------------------ small kernels
 
+// Sum over copies for one bitstring per wavefront; lanes stride over k, then
+// a fixed-order butterfly reduction.
+__global__ void __launch_bounds__(256)
+k_gathered_dot(int K, const float2* __restrict__ A, int lda, const float2* __restrict__ B, int ldb,
+               const int* __restrict__ iu, const int* __restrict__ il, size_t m,
+               float2* __restrict__ amps, int accumulate) {
+  const size_t t = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (t >= m) return;
+  const int u = iu[t], l = il[t];
+  float re = 0.f, im = 0.f;
+  for (int k = lane; k < K; k += 64) {
+    const float2 a = A[(size_t)k * lda + u], b = B[(size_t)k * ldb + l];
+    re += a.x * b.x - a.y * b.y;
+    im += a.x * b.y + a.y * b.x;
+  }
+  for (int w = 32; w > 0; w >>= 1) {
+    re += __shfl_xor(re, w);
+    im += __shfl_xor(im, w);
+  }
+  if (lane == 0) {
+    float2 o = make_float2(re, im);
+    if (accumulate) {
+      o.x += amps[t].x;
+      o.y += amps[t].y;
+    }
+    amps[t] = o;
+  }
+}
+
+hipError_t launch_gathered_dot(int K, const float2* A, int lda, const float2* B, int ldb,
+                               const int* iu, const int* il, size_t m, float2* amps,
+                               int accumulate, hipStream_t st) {
+  if (m == 0 || K <= 0) return hipSuccess;
+  const size_t blocks = (m * 64 + 255) / 256;
+  hipLaunchKernelGGL(k_gathered_dot, dim3((unsigned)blocks), dim3(256), 0, st, K, A, lda, B, ldb,
+                     iu, il, m, amps, accumulate);
+  return hipGetLastError();
+}
+
 __global__ void k_gather_amps(const float2* __restrict__ C, int ldc, const int* __restrict__ iu,
                               const int* __restrict__ il, size_t m, float2* __restrict__ amps) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -216,3 +216,89 @@ def test_plain_form_and_device_outputs():
     got = d.cpu().numpy().view(np.complex64)
     assert relerr(got, ref) < 1e-4
     p.close()
+
+
+def test_list_mode_non_product_bitstrings():
+    """Bitstrings that are not a product set take the per-bitstring sum."""
+    Q = _lib()
+    text = W.random_grid_circuit(4, 5, 14, 9)
+    mask = W.grid_rows_mask(4, 5, [0, 1])
+    rng = np.random.default_rng(5)
+    bits = rng.choice(1 << 20, size=3000, replace=False).astype(np.uint64)
+    say("case list mode")
+    amp, stats = run_plan(Q, text, mask, bits)
+    ref = SV.simulate(OC.parse(text))[bits.astype(np.int64)]
+    assert relerr(amp, ref) < 1e-5
+
+
+def _golden_bits(w, g):
+    """Full bitstrings of a golden file's (u, l) product set."""
+    from workloads.bitstrings import mask_bits
+    full = (1 << w.n) - 1
+    ub, lb = mask_bits(w.upper_mask), mask_bits(full & ~w.upper_mask)
+    U = np.zeros(len(g["u"]), dtype=np.uint64)
+    L = np.zeros(len(g["l"]), dtype=np.uint64)
+    for j, q in enumerate(ub):
+        U |= ((g["u"].astype(np.uint64) >> np.uint64(j)) & np.uint64(1)) << np.uint64(q)
+    for j, q in enumerate(lb):
+        L |= ((g["l"].astype(np.uint64) >> np.uint64(j)) & np.uint64(1)) << np.uint64(q)
+    return (U[:, None] | L[None, :]).reshape(-1)
+
+
+@pytest.mark.parametrize("row_name,cut_name,sub", [
+    ("grid6x7_d20", "grid6x7_d20_cols", None),
+    ("grid6x6_d16", "grid6x6_d16_stair", 4096),
+])
+def test_cut_invariance_against_golden(row_name, cut_name, sub):
+    """The same circuit cut another way (uneven halves) reproduces the oracle."""
+    Q = _lib()
+    wr, wc = workload(row_name), workload(cut_name)
+    g = _golden(row_name)
+    bits = _golden_bits(wr, g)
+    ref = g["amp"]
+    if sub:
+        idx = np.random.default_rng(0).choice(bits.size, size=sub, replace=False)
+        bits, ref = bits[idx], ref[idx]
+    say(f"case cut invariance {cut_name} m={bits.size}")
+    amp, _ = run_plan(Q, wc.circuit_text(), wc.upper_mask, bits)
+    assert relerr(amp, ref) < 1e-5
+
+
+def test_grid6x8_slice_golden():
+    """Copies [0, 64) of 65536 of a 48-qubit circuit: partial amplitudes vs the oracle."""
+    Q = _lib()
+    w = workload("grid6x8_d22_slice64")
+    g = _golden(w.name)
+    bits, u, l = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
+    say("case grid6x8 slice")
+    p = Q.Plan(w.circuit_text(), w.upper_mask)
+    p.run_halves(w.copy_begin, w.copy_end, bits)
+    amp, _ = p.amplitudes(bits)
+    p.close()
+    assert relerr(amp, g["amp"]) < 1e-5
+
+
+def test_grid8x8_slice_full_size():
+    """64 qubits, 32+32 halves, copies [0, 64): the two sub-slices add up to the
+    slice, and the split-BF16 assembly agrees with FP32."""
+    Q = _lib()
+    import torch
+    w = workload("grid8x8_d22_slice64")
+    bits, _, _ = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
+    text = w.circuit_text()
+    say("case grid8x8 slice [0,64)")
+    p = Q.Plan(text, w.upper_mask)
+    p.run_halves(0, 64, bits)
+    a32, _ = p.amplitudes(bits, 0)
+    ab, _ = p.amplitudes(bits, 1)
+    p.close()
+    torch.cuda.empty_cache()
+    assert np.linalg.norm(a32) > 0
+    assert relerr(ab, a32.astype(np.complex128)) < 1e-4
+    say("case grid8x8 slices [0,32) + [32,64)")
+    p = Q.Plan(text, w.upper_mask)
+    p.run_halves(0, 32, bits)
+    p.run_halves(32, 64, bits)
+    a2, _ = p.amplitudes(bits, 0)
+    p.close()
+    assert relerr(a2, a32.astype(np.complex128)) < 1e-5

@@ -62,6 +62,10 @@ _add(Workload("grid6x6_d16_stair", 6, 6, 16, 0,
               grid_rows_mask(6, 6, [0, 1]) | sum(1 << (2 * 6 + c) for c in range(4)),
               512, 512, 1004, 2004,
               note="36 qubits, rows 0-1 plus row 2 columns 0-3: 16+20 halves"))
+_add(Workload("grid6x8_d22_slice64", 6, 8, 22, 0, grid_rows_mask(6, 8, [0, 1, 2]), 256, 256,
+              1006, 2006, copy_begin=0, copy_end=64,
+              note="48 qubits, 24+24 halves, copies [0, 64) of 65536: the slice path at a size "
+                   "the oracle can check"))
 _add(Workload("grid8x8_d22_slice64", 8, 8, 22, 0, grid_rows_mask(8, 8, [0, 1, 2, 3]), 1024, 1024,
               1005, 2005, copy_begin=0, copy_end=64,
               note="64 qubits, 32+32 halves, copies [0, 64) of 65536: partial amplitudes"))

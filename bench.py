@@ -92,6 +92,8 @@ def main() -> int:
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--plain-copies", type=int, default=16)
     ap.add_argument("--cpu-copies", type=int, default=64)
+    ap.add_argument("--autotune", action="store_true",
+                    help="time a grid of schedule knobs first and run with the fastest")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="after the steps, copy a tensor of this size (for counter calibration)")
     a = ap.parse_args()
@@ -115,10 +117,16 @@ def main() -> int:
     text = w.circuit_text()
     bits, u_vals, l_vals = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
     m = int(bits.size)
-    plan = Q.Plan(text, w.upper_mask)
-    c = plan.n_cuts
+    c = Q.Plan(text, w.upper_mask).n_cuts
     k0 = w.copy_begin
     k1 = w.copy_end if w.copy_end is not None else (1 << c)
+    knobs = {}
+    tuned = None
+    if a.autotune:
+        from paper_1802_06952_amd.autotune import autotune
+        tuned = autotune(text, w.upper_mask, bits, k0, k1, budget_s=60.0)
+        knobs = tuned["opts"]
+    plan = Q.Plan(text, w.upper_mask, **knobs)
     stream = torch.cuda.current_stream()
     d_out = torch.empty(2 * m, dtype=torch.float32, device="cuda")
     d_sums = torch.zeros(2, dtype=torch.float64, device="cuda")
@@ -218,7 +226,10 @@ def main() -> int:
         "launches_per_step": launches,
         "setup_s": round(setup_s, 3),
         "roofline": roof,
+        "knobs": knobs or "cost model defaults",
     }
+    if tuned:
+        out["autotune"] = {"best_ms": round(tuned["ms"], 3), "candidates": len(tuned["tried"])}
 
     # split-BF16 assembly on the same simulated halves
     if prec == 0:

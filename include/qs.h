@@ -142,6 +142,20 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
 qs_status qs_amplitudes(qs_plan* plan, const uint64_t* bitstrings, size_t m, qs_precision prec,
                         float* out_c64, double* out_stats, void* hip_stream);
 
+/* Per-copy half amplitudes of an already run copy range [copy_begin,
+ * copy_end) (exactly one qs_run_halves range or a block of one): side 0 =
+ * upper, 1 = lower.  out_c64 (host) receives (copy_end - copy_begin) * S
+ * complex64 values, row k - copy_begin holding the half amplitudes of copy k
+ * at the S distinct registered half values (ascending packed half index:
+ * bit i = the i-th qubit of the half in ascending global id); *n_values
+ * receives S.  cap is the capacity of out_c64 in complex values.  These are
+ * the U_k[u] (side 0) and L_k[l] (side 1) of Supp. A, Eq. (8), whose sum over
+ * k of products is the amplitude.  Synchronises hip_stream.
+ * Errors: QS_ERR_ARG (null pointers, side, cap too small), QS_ERR_STATE
+ * (range not run as one block), QS_ERR_HIP. */
+qs_status qs_half_amplitudes(qs_plan* plan, int side, uint64_t copy_begin, uint64_t copy_end,
+                             float* out_c64, size_t cap, size_t* n_values, void* hip_stream);
+
 /* Device-resident variant of qs_amplitudes for the registered bitstrings:
  * d_out_c64 (device, 2*m floats in registration order) and d_out_sums (device,
  * nullable, 2 doubles: sum |a|^2 and sum |a|^4 in FP64) are written on

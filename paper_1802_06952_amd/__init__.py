@@ -29,8 +29,8 @@ _STATUS = {0: "QS_OK", -1: "QS_ERR_ARG", -2: "QS_ERR_PARSE", -3: "QS_ERR_UNSUPPO
 
 EXPORTED = ("qs_last_error", "qs_load_circuit", "qs_circuit_info", "qs_circuit_free",
             "qs_partition", "qs_plan_info", "qs_plan_dump", "qs_plan_free", "qs_run_halves",
-            "qs_amplitudes", "qs_amplitudes_device", "qs_plan_reset", "qs_get_timing",
-            "qs_set_timing")
+            "qs_amplitudes", "qs_amplitudes_device", "qs_half_amplitudes", "qs_plan_reset",
+            "qs_get_timing", "qs_set_timing")
 
 
 class QSError(RuntimeError):
@@ -64,6 +64,8 @@ def _load() -> C.CDLL:
     lib.qs_amplitudes.argtypes = [vp, u64p, C.c_size_t, C.c_int, C.POINTER(C.c_float),
                                   C.POINTER(C.c_double), vp]
     lib.qs_amplitudes_device.argtypes = [vp, C.c_int, vp, vp, vp]
+    lib.qs_half_amplitudes.argtypes = [vp, C.c_int, C.c_uint64, C.c_uint64, C.POINTER(C.c_float),
+                                       C.c_size_t, C.POINTER(C.c_size_t), vp]
     lib.qs_plan_reset.argtypes = [vp, C.c_int]
     lib.qs_get_timing.argtypes = [vp, C.POINTER(C.c_double)]
     lib.qs_set_timing.argtypes = [vp, C.c_int]
@@ -184,6 +186,17 @@ def qs_amplitudes_device(plan, prec: int, d_out_ptr: int, d_sums_ptr: int | None
                                      _stream_handle(stream)))
 
 
+def qs_half_amplitudes(plan, side: int, copy_begin: int, copy_end: int, n_values: int,
+                       stream=None) -> np.ndarray:
+    """Per-copy half amplitudes [copy][value] of a run copy block (complex64)."""
+    out = np.empty(2 * (copy_end - copy_begin) * n_values, dtype=np.float32)
+    nv = C.c_size_t()
+    _check(_lib.qs_half_amplitudes(plan, side, copy_begin, copy_end,
+                                   out.ctypes.data_as(C.POINTER(C.c_float)), out.size // 2,
+                                   C.byref(nv), _stream_handle(stream)))
+    return out.view(np.complex64).reshape(copy_end - copy_begin, nv.value)
+
+
 def qs_set_timing(plan, enable: bool) -> None:
     _check(_lib.qs_set_timing(plan, 1 if enable else 0))
 
@@ -232,6 +245,10 @@ class Plan:
     def amplitudes_device(self, prec: int, d_out_ptr: int, d_sums_ptr: int | None = None,
                           stream=None) -> None:
         qs_amplitudes_device(self._plan, prec, d_out_ptr, d_sums_ptr, stream)
+
+    def half_amplitudes(self, side: int, copy_begin: int, copy_end: int, n_values: int,
+                        stream=None) -> np.ndarray:
+        return qs_half_amplitudes(self._plan, side, copy_begin, copy_end, n_values, stream)
 
     def reset(self, keep_bitstrings: bool = False) -> None:
         qs_plan_reset(self._plan, keep_bitstrings)

@@ -737,6 +737,24 @@ qs_status qs_amplitudes_device(qs_plan* plan, qs_precision prec, float* d_out_c6
   return assemble(plan, prec, (float2*)d_out_c64, d_out_sums, (hipStream_t)hip_stream);
 }
 
+qs_status qs_half_amplitudes(qs_plan* plan, int side, uint64_t copy_begin, uint64_t copy_end,
+                             float* out_c64, size_t cap, size_t* n_values, void* hip_stream) {
+  if (!plan || !out_c64 || !n_values) return fail(QS_ERR_ARG, "null pointer");
+  if (side != 0 && side != 1) return fail(QS_ERR_ARG, "side must be 0 or 1");
+  const BlockRes* hit = nullptr;
+  for (const BlockRes& b : plan->blocks)
+    if (b.k0 == copy_begin && b.k1 == copy_end) hit = &b;
+  if (!hit) return fail(QS_ERR_STATE, "copy range was not run as one block");
+  const size_t S = plan->vals[side].size();
+  const size_t cnt = (size_t)(copy_end - copy_begin) * S;
+  if (cap < cnt) return fail(QS_ERR_ARG, "output capacity too small");
+  hipStream_t st = (hipStream_t)hip_stream;
+  HIPCHECK(hipMemcpyAsync(out_c64, hit->X[side], cnt * sizeof(float2), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  *n_values = S;
+  return QS_OK;
+}
+
 qs_status qs_get_timing(qs_plan* plan, double* out10) {
   if (!plan || !out10) return fail(QS_ERR_ARG, "null pointer");
   // out10 holds 11 doubles (see qs.h)

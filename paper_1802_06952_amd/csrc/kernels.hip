@@ -165,6 +165,35 @@ k_pass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops,
   }
 }
 
+// Cut factors of branch b over m cut bits (bit k of the branch = (b >> (m-1-k)) & 1
+// acts on state bit bq[k]): an amplitude x survives iff (x & cmask) == cval and
+// is negated iff popc(x & zmask) is odd.  Upper half: P_b on each cut qubit;
+// two cuts on one qubit with different bits give P0 P1 = 0 (cval gets a bit
+// outside cmask, so nothing survives).  Lower half: Z^b, and Z^b0 Z^b1 on one
+// qubit is Z^(b0 xor b1).
+__device__ __forceinline__ void cut_factors(const int* bq, int m, int b, int upper,
+                                            uint32_t& cmask, uint32_t& cval, uint32_t& zmask) {
+  cmask = 0;
+  cval = 0;
+  zmask = 0;
+  bool never = false;
+  for (int k = 0; k < m; ++k) {
+    const uint32_t want = (b >> (m - 1 - k)) & 1;
+    const uint32_t qb = 1u << bq[k];
+    if (upper) {
+      if ((cmask & qb) && (((cval & qb) != 0) != (want != 0))) never = true;
+      cmask |= qb;
+      if (want) cval |= qb;
+    } else if (want) {
+      zmask ^= qb;
+    }
+  }
+  if (never) {
+    cmask = 0;
+    cval = 1;  // (x & 0) == 1 never holds
+  }
+}
+
 // ------------------------------------------------------------------ wave-tile pass
 //
 // One wavefront owns a tile of 64 x 2^R amplitudes: lane l holds the state
@@ -292,19 +321,8 @@ k_wpass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops, const f
   const int m = P.m;
   for (int b = 0; b < (1 << m); ++b) {
     float2 w[E];
-    // cut factors of this child: a mask (upper) or a sign (lower) per cut bit
-    uint32_t cmask = 0, cval = 0, zmask = 0;
-    for (int k = 0; k < m; ++k) {
-      const uint32_t want = (b >> (m - 1 - k)) & 1;
-      const uint32_t qb = 1u << P.bq[k];
-      cmask |= qb;
-      if (want) cval |= qb;
-    }
-    if (!P.upper) {
-      zmask = cval;
-      cmask = 0;
-      cval = 0;
-    }
+    uint32_t cmask, cval, zmask;
+    cut_factors(P.bq, m, b, P.upper, cmask, cval, zmask);
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const uint32_t x = F | reg_index<R>(r, RB);
@@ -415,20 +433,14 @@ __device__ __forceinline__ void tail_bwd_rec(const float2 (&v)[R], const TailCtx
     const int m = L.m;
     const int G = 1 << c.lg;
     for (int b = 0; b < (1 << m); ++b) {
-      uint32_t cmask = 0, cval = 0;
-      for (int k = 0; k < m; ++k) {
-        cmask |= 1u << L.bq[k];
-        if ((b >> (m - 1 - k)) & 1) cval |= 1u << L.bq[k];
-      }
+      uint32_t cmask, cval, zmask;
+      cut_factors(L.bq, m, b, T.upper, cmask, cval, zmask);
       float2 w[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         float2 a = u[r];
-        if (T.upper) {
-          if ((c.xs[r] & cmask) != cval) a = make_float2(0.f, 0.f);
-        } else if (__popc(c.xs[r] & cval) & 1) {
-          a = make_float2(-a.x, -a.y);
-        }
+        if ((c.xs[r] & cmask) != cval) a = make_float2(0.f, 0.f);
+        if (__popc(c.xs[r] & zmask) & 1) a = make_float2(-a.x, -a.y);
         w[r] = a;
       }
       const uint32_t lam2 = lam | ((uint32_t)b << L.shift);

@@ -302,3 +302,18 @@ def test_grid8x8_slice_full_size():
     a2, _ = p.amplitudes(bits, 0)
     p.close()
     assert relerr(a2, a32.astype(np.complex128)) < 1e-5
+
+
+@pytest.mark.parametrize("level", [0, 1, 2, 3, 4, 5, 100])
+def test_two_cuts_on_one_qubit_in_one_level(level):
+    """Interleaved columns put two cuts on one qubit at the same tree level:
+    P0 P1 = 0 on the upper half and Z^b0 Z^b1 = Z^(b0 xor b1) on the lower half,
+    in the branch passes and in the leaf evaluation alike."""
+    Q = _lib()
+    text = W.random_grid_circuit(2, 6, 12, 3)
+    mask = W.grid_cols_mask(2, 6, [0, 2, 4])
+    bits, _, _ = product_bitstrings(12, mask, 64, 64, 3, 4)
+    ref = SV.simulate(OC.parse(text))[bits.astype(np.int64)]
+    say(f"case same-qubit cuts materialize_level={level}")
+    amp, _ = run_plan(Q, text, mask, bits, materialize_level=level, tail_max_qubits=10)
+    assert relerr(amp, ref) < 1e-5

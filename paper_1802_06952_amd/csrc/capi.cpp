@@ -99,7 +99,7 @@ struct Prepared {
   std::vector<PassDesc> pds;
   TailDesc td{};
   char* dev = nullptr;  // descriptors, tail desc, ops, node copy indices (owned)
-  size_t o_pd = 0, o_td = 0, o_ops = 0, o_nk = 0, o_lk = 0;
+  size_t o_pd = 0, o_td = 0, o_ops = 0, o_nk = 0, o_lk = 0, o_sv = 0;
   std::vector<uint64_t> leaf_k;
   double pass_bytes = 0;  // algorithmic bytes of the passes
   double tail_flops = 0;  // 2x2-gate flops of the leaf evaluation
@@ -209,13 +209,14 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
     (void)hipDeviceSynchronize();
     P->cache.clear();
   }
-  const Side& s = P->side[sidx];
   const int c = (int)P->cuts.size();
   const int S = (int)P->vals[sidx].size();
   std::unique_ptr<Prepared> pr(new Prepared());
   SidePlan& sp = pr->sp;
   std::string err;
-  if (!plan_side(s, c, blk, knobs_of(P, S), sp, err)) return fail(QS_ERR_UNSUPPORTED, err);
+  if (!plan_side(P->side[sidx], c, blk, knobs_of(P, S), sp, err)) return fail(QS_ERR_UNSUPPORTED, err);
+  // from here on the half program is the relabelled one: local qubit ids are state bits
+  const Side& s = sp.side;
   const Tree& tr = sp.tree;
   const int L = (int)tr.levels.size() - 1;
   if (L - sp.lstar > kMaxTailLevels) return fail(QS_ERR_UNSUPPORTED, "too many leaf levels");
@@ -243,11 +244,17 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
     d.init = pp.init ? 1 : 0;
     d.hinit = s.hinit;
     d.hamp = (float)std::pow(2.0, -0.5 * __builtin_popcountll(s.hinit));
+    std::vector<int> regs;
+    if (d.wave)
+      for (int i = 6; i < d.t; ++i) regs.push_back(pp.tile[i]);
+    const std::vector<int>* rp = d.wave ? &regs : nullptr;
     d.op_in = (int)ops.size();
-    if (!encode_ops(s, pp.ops_in, tr.fixed, work_of, ops, err)) return fail(QS_ERR_UNSUPPORTED, err);
+    if (!encode_ops(s, pp.ops_in, tr.fixed, work_of, ops, err, false, rp))
+      return fail(QS_ERR_UNSUPPORTED, err);
     d.n_in = (int)ops.size() - d.op_in;
     d.op_out = (int)ops.size();
-    if (!encode_ops(s, pp.ops_out, tr.fixed, work_of, ops, err)) return fail(QS_ERR_UNSUPPORTED, err);
+    if (!encode_ops(s, pp.ops_out, tr.fixed, work_of, ops, err, false, rp))
+      return fail(QS_ERR_UNSUPPORTED, err);
     d.n_out = (int)ops.size() - d.op_out;
     d.m = 0;
     const double nin = (double)sp.nodes[pp.level_in];
@@ -267,8 +274,8 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   td.q = (int)sp.Q.size();
   std::vector<int> work_q(s.n, -1);
   for (int i = 0; i < td.q; ++i) {
-    td.Q[i] = sp.Q[i];
-    work_q[sp.Q[i]] = i;
+    td.Q[i] = sp.perm[sp.Q[i]];  // = i: the light cone is on the lowest state bits
+    work_q[sp.perm[sp.Q[i]]] = i;
   }
   td.nlev = L - sp.lstar;
   td.M = 0;
@@ -344,19 +351,31 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   const size_t b_ops = std::max<size_t>(1, ops.size()) * sizeof(DevOp);
   const size_t b_nk = node_k.size() * sizeof(uint64_t);
   const size_t b_lk = pr->leaf_k.size() * sizeof(uint64_t);
+  // requested half values in the relabelled bit order
+  std::vector<uint32_t> sv(S);
+  for (int i = 0; i < S; ++i) {
+    const uint32_t v = P->vals[sidx][i];
+    uint32_t w = 0;
+    for (int qq = 0; qq < s.n; ++qq)
+      if ((v >> qq) & 1) w |= 1u << sp.perm[qq];
+    sv[i] = w;
+  }
+  const size_t b_sv = (size_t)S * sizeof(uint32_t);
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t total = al(b_pd) + al(b_td) + al(b_ops) + al(b_nk) + al(b_lk);
+  const size_t total = al(b_pd) + al(b_td) + al(b_ops) + al(b_nk) + al(b_lk) + al(b_sv);
   std::vector<char> host(total, 0);
   pr->o_pd = 0;
   pr->o_td = al(b_pd);
   pr->o_ops = pr->o_td + al(b_td);
   pr->o_nk = pr->o_ops + al(b_ops);
   pr->o_lk = pr->o_nk + al(b_nk);
+  pr->o_sv = pr->o_lk + al(b_lk);
   if (b_pd) std::memcpy(host.data() + pr->o_pd, pr->pds.data(), b_pd);
   std::memcpy(host.data() + pr->o_td, &td, b_td);
   if (!ops.empty()) std::memcpy(host.data() + pr->o_ops, ops.data(), ops.size() * sizeof(DevOp));
   std::memcpy(host.data() + pr->o_nk, node_k.data(), b_nk);
   std::memcpy(host.data() + pr->o_lk, pr->leaf_k.data(), b_lk);
+  std::memcpy(host.data() + pr->o_sv, sv.data(), b_sv);
   if (hipMalloc(&pr->dev, total) != hipSuccess) {
     (void)hipGetLastError();
     pr->dev = nullptr;
@@ -412,7 +431,8 @@ qs_status run_side(qs_plan* P, int sidx, const Prepared& pr, float2* X, hipStrea
     if (!W) return fail(QS_ERR_OOM, "leaf rows");
     for (int s0 = 0; s0 < S; s0 += chunk) {
       const int ns = std::min(chunk, S - s0);
-      HIPCHECK(launch_tail(pr.td, (const TailDesc*)(pr.dev + pr.o_td), d_ops, cur, P->d_vals[sidx],
+      HIPCHECK(launch_tail(pr.td, (const TailDesc*)(pr.dev + pr.o_td), d_ops, cur,
+                           (const uint32_t*)(pr.dev + pr.o_sv),
                            (const uint64_t*)(pr.dev + pr.o_nk), (const uint64_t*)(pr.dev + pr.o_lk),
                            s0, ns, W, X, st));
       tm.launches += 2;

@@ -272,8 +272,34 @@ __device__ __forceinline__ void wave_apply_ops(float2 (&v)[1 << R], const DevOp*
         if constexpr (R >= 5) { if (k == 4) tail_mat_reg<E>(v, op.m, 4); }
       }
     } else {
+      // exponent of the lane's fixed bits F, then of each register index by
+      // adding one register bit at a time (see DevOp)
+      int eF = __popc(F & (uint32_t)op.t0) + 2 * __popc(F & (uint32_t)op.t1) +
+               4 * __popc(F & (uint32_t)op.t2);
+      for (int i = 0; i < op.nd; ++i) eF += 4 * __popc(F & (F >> op.d[i]) & (uint32_t)op.M[i]);
+      int wk[R];
+      uint32_t rr[R];
 #pragma unroll
-      for (int r = 0; r < E; ++r) v[r] = diag_fast(op, F | reg_index<R>(r, RB), v[r]);
+      for (int k = 0; k < R; ++k) {
+        wk[k] = op.wl[k] + 4 * __popc(F & op.cross[k]);
+        rr[k] = op.rr[k];
+      }
+      int ex[E];
+      ex[0] = eF;
+#pragma unroll
+      for (int r = 1; r < E; ++r) {
+        const int top = 31 - __builtin_clz((unsigned)r);
+        const int low = r ^ (1 << top);
+        ex[r] = ex[low] + wk[top] + 4 * __popc(rr[top] & (uint32_t)low);
+      }
+#pragma unroll
+      for (int r = 0; r < E; ++r) v[r] = phase_mul(v[r], ex[r]);
+      if (op.pmask) {
+        const uint32_t pm = (uint32_t)op.pmask, pv = (uint32_t)op.pval;
+#pragma unroll
+        for (int r = 0; r < E; ++r)
+          if (((F | reg_index<R>(r, RB)) & pm) != pv) v[r] = make_float2(0.f, 0.f);
+      }
     }
   }
 }

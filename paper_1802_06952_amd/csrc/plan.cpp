@@ -208,6 +208,86 @@ void absorb(const Side& s, const std::vector<int>& P, std::vector<int>& S, int t
 
 }  // namespace
 
+namespace {
+
+// Cost units: bytes moved at HBM speed (8 TB/s); arithmetic is converted at the
+// VALU rate of the chip without packed FP32 (one wave64 instruction per cycle
+// per compute unit: about 39 T lane-operations per second, i.e. 0.2 byte per
+// lane-operation), and every launch costs about 10 us.
+constexpr double kBytesPerLaneOp = 8.0e12 / 39.3e12;
+constexpr double kLaunchBytes = 8.0e12 * 10e-6;
+
+double op_cost(const Side& s, const std::vector<int>& ops) {
+  // lane-operations per amplitude: a 2x2 gate about 10, a fused diagonal run about 16
+  double c = 0;
+  bool in_diag = false;
+  for (int i : ops) {
+    if (s.ops[i].kind == OP_MAT) {
+      c += 10;
+      in_diag = false;
+    } else if (!in_diag) {
+      c += 16;
+      in_diag = true;
+    }
+  }
+  return c;
+}
+
+// Greedy packing of the materialised levels 0..ls into passes.
+void build_passes(const Side& s, const Tree& tree, int ls, int t, int b, bool one_op,
+                  const std::vector<uint64_t>& nodes, std::vector<PassPlan>& passes,
+                  double& cost, size_t& peak) {
+  const double B = std::ldexp(8.0, s.n);
+  const double N = std::ldexp(1.0, s.n);
+  std::vector<std::vector<int>> pending(ls + 1);
+  for (int l = 0; l <= ls; ++l) pending[l] = tree.levels[l].ops;
+  int cur = 0;
+  bool first = true;
+  cost = 0;
+  peak = 1;
+  passes.clear();
+  for (int guard = 0; guard < 100000; ++guard) {
+    PassPlan pp;
+    pp.level_in = cur;
+    pp.init = first;
+    first = false;
+    std::vector<int> S;
+    for (int q = 0; q < b; ++q) S.push_back(q);
+    std::vector<int> deferred;
+    absorb(s, pending[cur], S, t, pp.ops_in, deferred, one_op);
+    pending[cur] = deferred;
+    if (deferred.empty() && cur < ls && !(one_op && !pp.ops_in.empty())) {
+      std::vector<int> d2;
+      absorb(s, pending[cur + 1], S, t, pp.ops_out, d2, one_op);
+      pending[cur + 1] = d2;
+      pp.branch = true;
+      ++cur;
+    }
+    // fill the tile up to t bits with the lowest unused qubits
+    for (int q = 0; (int)S.size() < t && q < s.n; ++q)
+      if (std::find(S.begin(), S.end(), q) == S.end()) S.push_back(q);
+    std::sort(S.begin(), S.end());
+    pp.tile = S;
+    const double nin = (double)nodes[pp.level_in];
+    double bytes, alu;
+    if (pp.branch) {
+      const double nout = (double)nodes[cur];
+      bytes = (pp.init ? 0 : B * nin) + B * nout;
+      alu = N * nin * (op_cost(s, pp.ops_in) + (nout / nin) * (op_cost(s, pp.ops_out) + 6));
+      peak = std::max<size_t>(peak, nodes[pp.level_in] + nodes[cur]);
+    } else {
+      bytes = (pp.init ? 1 : 2) * B * nin;
+      alu = N * nin * (op_cost(s, pp.ops_in) + 4);
+      peak = std::max<size_t>(peak, nodes[cur]);
+    }
+    cost += std::max(bytes, alu * kBytesPerLaneOp) + kLaunchBytes;
+    passes.push_back(pp);
+    if (cur == ls && pending[ls].empty()) break;
+  }
+}
+
+}  // namespace
+
 bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, SidePlan& out,
                std::string& err) {
   Tree tree = build_tree(s, c, blk);
@@ -243,53 +323,18 @@ bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, Side
     std::sort(Q.begin(), Q.end());
     if ((int)Q.size() > kn.tail_max_qubits) continue;
     sp.Q = Q;
-    // passes for levels 0..ls
-    std::vector<std::vector<int>> pending(ls + 1);
-    for (int l = 0; l <= ls; ++l) pending[l] = tree.levels[l].ops;
-    int cur = 0;
-    bool first = true;
-    double cost = 0;
-    size_t peak = 1;
-    for (int guard = 0; guard < 100000; ++guard) {
-      PassPlan pp;
-      pp.level_in = cur;
-      pp.init = first;
-      first = false;
-      std::vector<int> S;
-      for (int q = 0; q < b; ++q) S.push_back(q);
-      std::vector<int> deferred;
-      absorb(s, pending[cur], S, t, pp.ops_in, deferred, kn.one_op_per_pass);
-      pending[cur] = deferred;
-      if (deferred.empty() && cur < ls && !(kn.one_op_per_pass && !pp.ops_in.empty())) {
-        std::vector<int> d2;
-        absorb(s, pending[cur + 1], S, t, pp.ops_out, d2, kn.one_op_per_pass);
-        pending[cur + 1] = d2;
-        pp.branch = true;
-        ++cur;
-      }
-      // fill the tile up to t bits with the lowest unused qubits (keeps runs long)
-      for (int q = 0; (int)S.size() < t && q < s.n; ++q)
-        if (std::find(S.begin(), S.end(), q) == S.end()) S.push_back(q);
-      std::sort(S.begin(), S.end());
-      pp.tile = S;
-      if (pp.branch) {
-        cost += (pp.init ? 0 : B * nodes[pp.level_in]) + B * nodes[cur];
-        peak = std::max<size_t>(peak, nodes[pp.level_in] + nodes[cur]);
-      } else {
-        cost += (pp.init ? 1 : 2) * B * nodes[cur];
-        peak = std::max<size_t>(peak, nodes[cur]);
-      }
-      sp.passes.push_back(pp);
-      if (cur == ls && pending[ls].empty()) break;
-    }
-    // leaf evaluation estimate, in bytes at HBM speed: the backward rows per
-    // requested value (arithmetic and the W round trip), the gathers of the
-    // node amplitudes, and the per-value GEMM (arithmetic)
     const int q = (int)Q.size();
     const int nlev = L - ls;
     int M = 0;
     for (int l = ls + 1; l <= L; ++l) M += (int)tree.levels[l].cuts.size();
     if (nlev > kMaxTailLevels || M > 16) continue;
+    double cost = 0;
+    size_t peak = 1;
+    build_passes(s, tree, ls, t, b, kn.one_op_per_pass, nodes, sp.passes, cost, peak);
+    // leaf evaluation: the backward rows per requested value (arithmetic and
+    // the W round trip), the contiguous gathers of the node amplitudes (the
+    // light cone is relabelled onto the lowest state bits), and the per-value
+    // GEMM on MFMA
     const double K = std::ldexp(1.0, q), Lam = std::ldexp(1.0, M), Sd = kn.S;
     double rev = 0, paths = 1;
     for (int l = L; l > ls; --l) {
@@ -298,11 +343,11 @@ bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, Side
       rev += paths * nops * K;
       paths *= std::ldexp(1.0, (int)tree.levels[l].cuts.size());
     }
-    const double flop_per_byte = 8.0;  // sustained arithmetic vs bandwidth of these kernels
-    cost += Sd * rev * 24.0 / flop_per_byte;              // backward rows
-    cost += Sd * Lam * K * 16.0;                          // W written and read
-    cost += Sd * std::ceil(Lam / 64.0) * K * (double)nodes[ls] * 64.0;  // gathers (line per element)
-    cost += Sd * Lam * K * (double)nodes[ls] * 8.0 / (4 * flop_per_byte);  // MFMA GEMM
+    cost += Sd * rev * 12.0 * kBytesPerLaneOp;                              // backward rows
+    cost += Sd * Lam * K * 16.0;                                            // W written and read
+    cost += Sd * std::ceil(Lam / 64.0) * K * (double)nodes[ls] * 8.0;       // gathers
+    cost += Sd * Lam * K * (double)nodes[ls] * 8.0 / 80.0e12 * 8.0e12;      // MFMA GEMM
+    cost += 2 * kLaunchBytes;
     sp.cost_bytes = cost;
     sp.peak_states = peak;
     if (kn.mem_budget && (double)peak * B > (double)kn.mem_budget) continue;
@@ -315,6 +360,30 @@ bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, Side
     err = "no feasible schedule: light cone of the leaf levels exceeds the limit or the "
           "materialised states exceed the memory budget";
     return false;
+  }
+  // relabel the half's qubits so that the light cone sits on the lowest state
+  // bits (the leaf evaluation then gathers contiguous runs), and pack the
+  // passes again for the relabelled program
+  best.perm.assign(s.n, -1);
+  int next = 0;
+  for (int qq : best.Q) best.perm[qq] = next++;
+  for (int qq = 0; qq < s.n; ++qq)
+    if (best.perm[qq] < 0) best.perm[qq] = next++;
+  Side& r = best.side;
+  r = s;
+  for (int i = 0; i < s.n; ++i) r.qubits[best.perm[i]] = s.qubits[i];
+  r.hinit = 0;
+  for (int i = 0; i < s.n; ++i)
+    if ((s.hinit >> i) & 1) r.hinit |= 1ULL << best.perm[i];
+  for (HOp& o : r.ops) {
+    o.q0 = best.perm[o.q0];
+    if (o.q1 >= 0) o.q1 = best.perm[o.q1];
+  }
+  {
+    double cost = 0;
+    size_t peak = 1;
+    build_passes(r, best.tree, best.lstar, t, b, kn.one_op_per_pass, best.nodes, best.passes,
+                 cost, peak);
   }
   out = std::move(best);
   return true;
@@ -387,9 +456,46 @@ void set_mat(DevOp& op, int mat) {
 
 }  // namespace
 
+namespace {
+
+// Register split of a DIAG op for a wave-tile pass (see DevOp).
+void split_registers(DevOp& op, const std::vector<int>& rb) {
+  const int R = (int)rb.size();
+  auto reg_index = [&](int bit) {
+    for (int k = 0; k < R; ++k)
+      if (rb[k] == bit) return k;
+    return -1;
+  };
+  for (int k = 0; k < R; ++k) {
+    const int rho = rb[k];
+    op.wl[k] = (int)(((op.t0 >> rho) & 1) + 2 * ((op.t1 >> rho) & 1) + 4 * ((op.t2 >> rho) & 1));
+    op.cross[k] = 0;
+    op.rr[k] = 0;
+  }
+  for (int i = 0; i < op.nd; ++i) {
+    const int d = op.d[i];
+    for (int a = 0; a + d < 64; ++a) {
+      if (!((op.M[i] >> a) & 1)) continue;
+      const int b = a + d;  // the pair (a, b) of state bits
+      const int ka = reg_index(a), kb = reg_index(b);
+      if (ka >= 0 && kb >= 0) {
+        if (ka < kb) op.rr[kb] |= 1u << ka;
+        else op.rr[ka] |= 1u << kb;
+      } else if (ka >= 0) {
+        op.cross[ka] |= 1u << b;
+      } else if (kb >= 0) {
+        op.cross[kb] |= 1u << a;
+      }
+    }
+  }
+}
+
+}  // namespace
+
 bool encode_ops(const Side& s, const std::vector<int>& ops, const std::vector<int>& fixed_bits,
                 const std::vector<int>& work_of, std::vector<DevOp>& out, std::string& err,
-                bool transpose) {
+                bool transpose, const std::vector<int>* reg_bits) {
+  const size_t first_new = out.size();
   DiagAcc acc;
   for (int i : ops) {
     const HOp& o = s.ops[i];
@@ -442,6 +548,9 @@ bool encode_ops(const Side& s, const std::vector<int>& ops, const std::vector<in
     }
   }
   flush(acc, out);
+  if (reg_bits)
+    for (size_t i = first_new; i < out.size(); ++i)
+      if (out[i].kind == 1) split_registers(out[i], *reg_bits);
   return true;
 }
 
@@ -490,11 +599,17 @@ std::string dump_json(const Circuit& c, uint64_t upper_mask, const std::vector<C
         o << "],\"ops_out\":[";
         for (size_t i = 0; i < pp.ops_out.size(); ++i) o << (i ? "," : "") << pp.ops_out[i];
         o << "],\"tile\":[";
-        for (size_t i = 0; i < pp.tile.size(); ++i) o << (i ? "," : "") << pp.tile[i];
+        // tiles are printed as local qubit ids of the unrelabelled half
+        std::vector<int> inv(sp->perm.size());
+        for (size_t i = 0; i < sp->perm.size(); ++i) inv[sp->perm[i]] = (int)i;
+        for (size_t i = 0; i < pp.tile.size(); ++i)
+          o << (i ? "," : "") << (inv.empty() ? pp.tile[i] : inv[pp.tile[i]]);
         o << "]}";
       }
       o << "],\"Q\":[";
       for (size_t i = 0; i < sp->Q.size(); ++i) o << (i ? "," : "") << sp->Q[i];
+      o << "],\"perm\":[";
+      for (size_t i = 0; i < sp->perm.size(); ++i) o << (i ? "," : "") << sp->perm[i];
       o << "]";
     }
     o << "}";

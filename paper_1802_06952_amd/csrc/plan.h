@@ -47,8 +47,10 @@ struct PassPlan {
 struct SidePlan {
   Tree tree;
   int lstar = 0;                  // last materialised level
-  std::vector<PassPlan> passes;
-  std::vector<int> Q;             // light-cone qubits of the leaf evaluation (ascending)
+  std::vector<int> Q;             // light-cone qubits of the leaf evaluation (local ids, ascending)
+  std::vector<int> perm;          // state bit of each local qubit: the light cone takes bits 0..q-1
+  Side side;                      // the half program relabelled by perm (what the kernels run)
+  std::vector<PassPlan> passes;   // passes of the relabelled program (tiles are state bits)
   double cost_bytes = 0;          // cost model estimate
   size_t peak_states = 0;         // largest number of live states
   std::vector<uint64_t> nodes;    // nodes per level
@@ -72,9 +74,11 @@ bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, Side
 // an error for MAT ops).  Diagonal ops between MATs are merged.
 // transpose = true encodes the transposed operator of the list: the caller
 // passes the ops in reverse order and every 2x2 matrix is transposed.
+// reg_bits (optional): the state bits of a wave-tile pass's register bits, for
+// the register split of DIAG ops.
 bool encode_ops(const Side& s, const std::vector<int>& ops, const std::vector<int>& fixed_bits,
                 const std::vector<int>& work_of, std::vector<DevOp>& out, std::string& err,
-                bool transpose = false);
+                bool transpose = false, const std::vector<int>* reg_bits = nullptr);
 
 std::string dump_json(const Circuit& c, uint64_t upper_mask, const std::vector<Cut>& cuts,
                       const Side& up, const Side& lo, const SidePlan* pu, const SidePlan* pl);

@@ -74,6 +74,8 @@ constexpr int kMaxTileBits = 14;
 // and zeroes it unless (x & pmask) == pval (omega = (1+i)/sqrt 2; Eq. 4 and 6
 // fused with the cut projectors and Z of Eq. 1).  MAT applies a 2x2 matrix on
 // index bit `target` of the kernel's working index space.
+constexpr int kMaxRegBits = 5;
+
 struct DevOp {
   int kind;    // 0 = MAT, 1 = DIAG
   int target;  // MAT: working bit
@@ -83,6 +85,14 @@ struct DevOp {
   uint64_t t0, t1, t2, pmask, pval;
   int d[kMaxDiagDist];
   uint64_t M[kMaxDiagDist];
+  // DIAG in a wave-tile pass, split over the pass's register bits rho_k (the
+  // other bits F of an index are fixed per lane): the exponent of index
+  // F | sum_k r_k 2^rho_k is
+  //   e(F) + sum_k r_k (wl[k] + 4 popc(F & cross[k]))
+  //        + 4 sum_{k2 < k} r_k r_k2 [bit k2 of rr[k]]   (mod 8).
+  int wl[kMaxRegBits];
+  uint32_t cross[kMaxRegBits];
+  uint32_t rr[kMaxRegBits];
 };
 
 // A full-state pass: every tile of 2^t amplitudes (the tile bits are state

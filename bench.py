@@ -124,7 +124,7 @@ def main() -> int:
     tuned = None
     if a.autotune:
         from paper_1802_06952_amd.autotune import autotune
-        tuned = autotune(text, w.upper_mask, bits, k0, k1, budget_s=60.0)
+        tuned = autotune(text, w.upper_mask, bits, k0, k1, budget_s=90.0, extra_levels=(4, 5, 6, 7))
         knobs = tuned["opts"]
     plan = Q.Plan(text, w.upper_mask, **knobs)
     stream = torch.cuda.current_stream()

@@ -61,9 +61,9 @@ def _scratch(m: int) -> int:
 
 def candidates(base_levels=(-1,)):
     out = []
-    for tb in (9, 10, 11):
-        for tq in (8, 10):
-            for ml in base_levels:
+    for ml in base_levels:
+        for tb in (10, 11):
+            for tq in (8, 10):
                 out.append(dict(tile_bits=tb, tail_max_qubits=tq, materialize_level=ml))
     return out
 

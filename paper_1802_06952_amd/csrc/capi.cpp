@@ -84,7 +84,11 @@ struct Pool {
 
 struct BlockRes {
   uint64_t k0 = 0, k1 = 0;
-  float2* X[2] = {nullptr, nullptr};  // [K_b][S_side]
+  // X[side][s * K_b + nu]: half amplitudes at requested value s; nu runs over
+  // the block's copies in the upper half's natural order (the lower half is
+  // permuted onto it), so both sides share the contraction index
+  float2* X[2] = {nullptr, nullptr};
+  std::shared_ptr<std::vector<uint32_t>> nu_to_k;  // copy (block-local) of each nu
 };
 
 }  // namespace
@@ -101,6 +105,7 @@ struct Prepared {
   char* dev = nullptr;  // descriptors, tail desc, ops, node copy indices (owned)
   size_t o_pd = 0, o_td = 0, o_ops = 0, o_nk = 0, o_lk = 0, o_sv = 0;
   std::vector<uint64_t> leaf_k;
+  std::vector<uint32_t> nu_to_k;  // block-local copy index of each natural position nu
   double pass_bytes = 0;  // algorithmic bytes of the passes
   double tail_flops = 0;  // 2x2-gate flops of the leaf evaluation
   ~Prepared() {
@@ -131,6 +136,9 @@ struct qs_plan {
   std::vector<BlockRes> blocks;
   std::vector<std::pair<uint64_t, uint64_t>> ranges;
   std::map<std::tuple<int, uint64_t, int>, std::unique_ptr<Prepared>> cache;
+  // per copy block: device table nu_U -> nu_L and the upper half's nu -> copy
+  std::map<std::pair<uint64_t, int>, std::pair<uint32_t*, std::shared_ptr<std::vector<uint32_t>>>>
+      perms;
   bool timing = false;
   std::vector<EvRec> events;
   double tms[4] = {0, 0, 0, 0};
@@ -143,6 +151,7 @@ struct qs_plan {
       (void)hipEventDestroy(e.b);
     }
     cache.clear();
+    for (auto& kv : perms) (void)hipFree(kv.second.first);
     pool.release_all();
   }
 };
@@ -332,7 +341,7 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   td.upper = s.upper ? 1 : 0;
   td.n_nodes = (int)sp.nodes[sp.lstar];
   td.S = S;
-  td.ldx = S;
+  td.ldx = 1 << (c - blk.p);  // row stride of X[s][nu]: the block's copies
   ops.insert(ops.end(), tops.begin(), tops.end());
   // copy-index contribution of each materialised node
   std::vector<int> ncuts;
@@ -345,6 +354,21 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
     for (int i = 0; i < nb; ++i)
       if ((r >> (nb - 1 - i)) & 1) k |= 1ULL << (c - 1 - ncuts[i]);
     node_k[r] = k;
+  }
+  {
+    // natural order nu = ((node << M) + lam) << n_end | end bits
+    const size_t Kb = (size_t)1 << (c - blk.p);
+    const int ne = td.n_end;
+    pr->nu_to_k.assign(Kb, 0);
+    for (size_t r = 0; r < node_k.size(); ++r)
+      for (size_t lam = 0; lam < pr->leaf_k.size(); ++lam)
+        for (int e = 0; e < (1 << ne); ++e) {
+          uint64_t k = node_k[r] | pr->leaf_k[lam];
+          for (int i = 0; i < ne; ++i)
+            if ((e >> (ne - 1 - i)) & 1) k |= td.ekbit[i];
+          const size_t nu = (((r << td.M) + lam) << ne) | (size_t)e;
+          if (nu < Kb) pr->nu_to_k[nu] = (uint32_t)k;
+        }
   }
   const size_t b_pd = pr->pds.size() * sizeof(PassDesc);
   const size_t b_td = sizeof(TailDesc);
@@ -432,9 +456,7 @@ qs_status run_side(qs_plan* P, int sidx, const Prepared& pr, float2* X, hipStrea
     for (int s0 = 0; s0 < S; s0 += chunk) {
       const int ns = std::min(chunk, S - s0);
       HIPCHECK(launch_tail(pr.td, (const TailDesc*)(pr.dev + pr.o_td), d_ops, cur,
-                           (const uint32_t*)(pr.dev + pr.o_sv),
-                           (const uint64_t*)(pr.dev + pr.o_nk), (const uint64_t*)(pr.dev + pr.o_lk),
-                           s0, ns, W, X, st));
+                           (const uint32_t*)(pr.dev + pr.o_sv), s0, ns, W, X, st));
       tm.launches += 2;
     }
     P->pool.put(W);
@@ -512,7 +534,7 @@ qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_s
     bool first = true;
     for (BlockRes& b : plan->blocks) {
       const int K = (int)(b.k1 - b.k0);
-      HIPCHECK(launch_gathered_dot(K, b.X[0], M, b.X[1], N, plan->d_idx[0], plan->d_idx[1], m,
+      HIPCHECK(launch_gathered_dot(K, b.X[0], K, b.X[1], K, plan->d_idx[0], plan->d_idx[1], m,
                                    d_amps, first ? 0 : 1, st));
       ++tm.launches;
       if (plan->timing) plan->gemm_flops += 8.0 * (double)m * (double)K;
@@ -529,7 +551,7 @@ qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_s
         const size_t wb = zgemm_workspace_bytes((int)prec, M, N, K);
         void* work = plan->pool.get(wb);
         if (!work) return fail(QS_ERR_OOM, "assembly workspace");
-        HIPCHECK(launch_zgemm_tn((int)prec, M, N, K, b.X[0], M, b.X[1], N, C, N, first ? 0 : 1, work, st));
+        HIPCHECK(launch_zgemm_tn((int)prec, M, N, K, b.X[0], K, b.X[1], K, C, N, first ? 0 : 1, work, st));
         plan->pool.put(work);
         tm.launches += prec == QS_PREC_FP32 ? 2 : 4;
         if (plan->timing) plan->gemm_flops += 8.0 * M * N * (double)K;
@@ -699,15 +721,46 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
     br.k0 = k;
     br.k1 = k + (1ULL << sz);
     const uint64_t Kb = 1ULL << sz;
+    Prepared* prs[2] = {nullptr, nullptr};
     for (int sidx = 0; sidx < 2; ++sidx) {
-      Prepared* pr = nullptr;
-      s = prepare_side(plan, sidx, blk, &pr);
+      s = prepare_side(plan, sidx, blk, &prs[sidx]);
       if (s != QS_OK) return s;
+    }
+    // the lower half's natural order mapped onto the upper half's (cached per block)
+    auto pkey = std::make_pair(blk.k0, blk.p);
+    auto pit = plan->perms.find(pkey);
+    if (pit == plan->perms.end()) {
+      const std::vector<uint32_t>& ku = prs[0]->nu_to_k;
+      const std::vector<uint32_t>& kl = prs[1]->nu_to_k;
+      std::vector<uint32_t> inv(Kb), perm(Kb);
+      for (uint64_t nu = 0; nu < Kb; ++nu) inv[kl[nu]] = (uint32_t)nu;
+      for (uint64_t nu = 0; nu < Kb; ++nu) perm[nu] = inv[ku[nu]];
+      uint32_t* d = nullptr;
+      if (hipMalloc(&d, Kb * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(QS_ERR_OOM, "copy permutation");
+      }
+      HIPCHECK(hipMemcpy(d, perm.data(), Kb * sizeof(uint32_t), hipMemcpyHostToDevice));
+      pit = plan->perms.emplace(pkey, std::make_pair(d, std::make_shared<std::vector<uint32_t>>(ku))).first;
+    }
+    br.nu_to_k = pit->second.second;
+    for (int sidx = 0; sidx < 2; ++sidx) {
       const size_t bytes = Kb * plan->vals[sidx].size() * sizeof(float2);
       br.X[sidx] = (float2*)plan->pool.get(bytes);
       if (!br.X[sidx]) return fail(QS_ERR_OOM, "gathered half amplitudes");
-      s = run_side(plan, sidx, *pr, br.X[sidx], st);
+      s = run_side(plan, sidx, *prs[sidx], br.X[sidx], st);
       if (s != QS_OK) return s;
+    }
+    {
+      const size_t bytes = Kb * plan->vals[1].size() * sizeof(float2);
+      float2* XL = (float2*)plan->pool.get(bytes);
+      if (!XL) return fail(QS_ERR_OOM, "gathered half amplitudes");
+      Timer tm(plan, st, 3);
+      HIPCHECK(launch_permute_cols(br.X[1], XL, pit->second.first, (int)plan->vals[1].size(),
+                                   (int)Kb, st));
+      ++tm.launches;
+      plan->pool.put(br.X[1]);
+      br.X[1] = XL;
     }
     plan->blocks.push_back(br);
     k = br.k1;
@@ -769,8 +822,15 @@ qs_status qs_half_amplitudes(qs_plan* plan, int side, uint64_t copy_begin, uint6
   const size_t cnt = (size_t)(copy_end - copy_begin) * S;
   if (cap < cnt) return fail(QS_ERR_ARG, "output capacity too small");
   hipStream_t st = (hipStream_t)hip_stream;
-  HIPCHECK(hipMemcpyAsync(out_c64, hit->X[side], cnt * sizeof(float2), hipMemcpyDeviceToHost, st));
+  const size_t Kb = (size_t)(copy_end - copy_begin);
+  std::vector<float2> tmp(cnt);
+  HIPCHECK(hipMemcpyAsync(tmp.data(), hit->X[side], cnt * sizeof(float2), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
+  // stored as [s][nu] in the upper half's natural copy order; returned as [k][s]
+  const std::vector<uint32_t>& nk = *hit->nu_to_k;
+  float2* o = (float2*)out_c64;
+  for (size_t si = 0; si < S; ++si)
+    for (size_t nu = 0; nu < Kb; ++nu) o[(size_t)nk[nu] * S + si] = tmp[si * Kb + nu];
   *n_values = S;
   return QS_OK;
 }

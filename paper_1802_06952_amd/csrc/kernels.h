@@ -18,11 +18,14 @@ hipError_t launch_pass(const PassDesc& h_desc, const PassDesc* d_desc, const Dev
 // the materialised node states into X[k * ldx + s_index].
 size_t tail_w_bytes(const TailDesc& h, int ns);
 hipError_t launch_tail(const TailDesc& h_desc, const TailDesc* d_desc, const DevOp* d_ops,
-                       const float2* states, const uint32_t* svals, const uint64_t* node_k,
-                       const uint64_t* leaf_k, int s0, int ns, float2* W, float2* X,
-                       hipStream_t st);
+                       const float2* states, const uint32_t* svals, int s0, int ns, float2* W,
+                       float2* X, hipStream_t st);
 
-// C[i*ldc + j] (+)= sum_k A[k*lda + i] * B[k*ldb + j], complex64.  prec 0:
+// out[row * K + j] = in[row * K + perm[j]].
+hipError_t launch_permute_cols(const float2* in, float2* out, const uint32_t* perm, int rows,
+                               int K, hipStream_t st);
+
+// C[i*ldc + j] (+)= sum_k A[i*lda + k] * B[j*ldb + k], complex64.  prec 0:
 // FP32 MFMA; prec 1: split-BF16 (three bf16 products, FP32 accumulation).
 // `work` must hold zgemm_workspace_bytes(prec, M, N, K) bytes (split-K
 // partials and, for prec 1, the split operands).
@@ -31,7 +34,7 @@ hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int l
                            const float2* B, int ldb, float2* C, int ldc, int accumulate,
                            void* work, hipStream_t st);
 
-// amps[t] (+)= sum_k A[k*lda + iu[t]] * B[k*ldb + il[t]] (one wavefront per t).
+// amps[t] (+)= sum_k A[iu[t]*lda + k] * B[il[t]*ldb + k] (one wavefront per t).
 hipError_t launch_gathered_dot(int K, const float2* A, int lda, const float2* B, int ldb,
                                const int* iu, const int* il, size_t m, float2* amps,
                                int accumulate, hipStream_t st);

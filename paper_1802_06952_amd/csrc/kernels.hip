@@ -522,13 +522,18 @@ k_tail_bwd(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
 
 constexpr int kTM = 64, kTN = 64, kTK = 16;
 
+// Per requested value s: C[node][lam] = sum_y v_node[x(s, y)] W[s][lam][y] on
+// v_mfma_f32_16x16x4f32 with three real products per complex one
+// (Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)); rows are materialised nodes, columns leaf
+// paths, so consecutive lanes of a store hold consecutive leaf paths and the
+// row X[s][nu] of the output is written in contiguous runs.  nu is the half's
+// natural copy order ((node * 2^M + lam) * 2^n_end + end bits).
 __global__ void __launch_bounds__(kTailThreads)
 k_tail_mm(const TailDesc* __restrict__ tdp, const float2* __restrict__ W,
           const float2* __restrict__ states, const uint32_t* __restrict__ svals, int s0,
-          const uint64_t* __restrict__ node_k, const uint64_t* __restrict__ leaf_k,
           float2* __restrict__ X) {
-  __shared__ float2 As[kTK][kTM];   // [y][lam]
-  __shared__ float2 Bs[kTK][kTN];   // [y][node]
+  __shared__ float2 As[kTK][kTM + 1];   // [y][node]
+  __shared__ float2 Bs[kTK][kTN + 1];   // [y][lam]
   __shared__ uint32_t xy[kTK];
   const TailDesc& T = *tdp;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -538,18 +543,19 @@ k_tail_mm(const TailDesc* __restrict__ tdp, const float2* __restrict__ W,
   const int K = 1 << T.q;
   const int Lam = 1 << T.M;
   const int Nn = T.n_nodes;
-  const int lam0 = blockIdx.y * kTM, r0 = blockIdx.x * kTN;
+  const int r0 = blockIdx.y * kTM, lam0 = blockIdx.x * kTN;
   uint32_t qmask = 0;
   for (int i = 0; i < T.q; ++i) qmask |= 1u << T.Q[i];
   const uint32_t base = s & ~qmask;
   const float2* Ws = W + (size_t)sl * Lam * K;
   const size_t N = (size_t)1 << T.n;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
-  floatx4 acc_re[2][2], acc_im[2][2];
+  floatx4 p1[2][2], p2[2][2], p3[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) {
-      acc_re[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-      acc_im[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+      p1[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+      p2[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+      p3[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
   for (int y0 = 0; y0 < K; y0 += kTK) {
     if (tid < kTK) {
@@ -561,10 +567,10 @@ k_tail_mm(const TailDesc* __restrict__ tdp, const float2* __restrict__ W,
     __syncthreads();
     for (int e = tid; e < kTK * kTM; e += kTailThreads) {
       const int kk = e % kTK, ii = e / kTK;
-      const int y = y0 + kk, lam = lam0 + ii;
-      As[kk][ii] = (y < K && lam < Lam) ? Ws[(size_t)lam * K + y] : make_float2(0.f, 0.f);
-      const int rr = r0 + ii;
-      Bs[kk][ii] = (y < K && rr < Nn) ? states[(size_t)rr * N + xy[kk]] : make_float2(0.f, 0.f);
+      const int y = y0 + kk;
+      const int rr = r0 + ii, lam = lam0 + ii;
+      As[kk][ii] = (y < K && rr < Nn) ? states[(size_t)rr * N + xy[kk]] : make_float2(0.f, 0.f);
+      Bs[kk][ii] = (y < K && lam < Lam) ? Ws[(size_t)lam * K + y] : make_float2(0.f, 0.f);
     }
     __syncthreads();
 #pragma unroll
@@ -574,10 +580,10 @@ k_tail_mm(const TailDesc* __restrict__ tdp, const float2* __restrict__ W,
       for (int b = 0; b < 2; ++b) bv[b] = Bs[kk + (lane >> 4)][wj + b * 16 + (lane & 15)];
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
-          acc_re[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[b].x, acc_re[a][b], 0, 0, 0);
-          acc_re[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av[a].y, bv[b].y, acc_re[a][b], 0, 0, 0);
-          acc_im[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[b].y, acc_im[a][b], 0, 0, 0);
-          acc_im[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].y, bv[b].x, acc_im[a][b], 0, 0, 0);
+          p1[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[b].x, p1[a][b], 0, 0, 0);
+          p2[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].y, bv[b].y, p2[a][b], 0, 0, 0);
+          p3[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x + av[a].y, bv[b].x + bv[b].y,
+                                                          p3[a][b], 0, 0, 0);
         }
     }
     __syncthreads();
@@ -586,25 +592,24 @@ k_tail_mm(const TailDesc* __restrict__ tdp, const float2* __restrict__ W,
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int e4 = 0; e4 < 4; ++e4) {
-        const int lam = lam0 + wi + a * 16 + 4 * (lane >> 4) + e4;
-        const int rr = r0 + wj + b * 16 + (lane & 15);
+        const int rr = r0 + wi + a * 16 + 4 * (lane >> 4) + e4;
+        const int lam = lam0 + wj + b * 16 + (lane & 15);
         if (lam >= Lam || rr >= Nn) continue;
-        const float2 val = make_float2(acc_re[a][b][e4], acc_im[a][b][e4]);
-        const uint64_t kb = node_k[rr] | leaf_k[lam];
+        const float re = p1[a][b][e4] - p2[a][b][e4];
+        const float im = p3[a][b][e4] - p1[a][b][e4] - p2[a][b][e4];
+        float2* dst = X + (size_t)si * T.ldx + ((((size_t)rr << T.M) + lam) << ne);
         for (int e = 0; e < (1 << ne); ++e) {
-          float2 f = val;
-          uint64_t k = kb;
+          float2 f = make_float2(re, im);
           for (int i = 0; i < ne; ++i) {
             const uint32_t eb = (e >> (ne - 1 - i)) & 1;
             const uint32_t sb = (s >> T.eq[i]) & 1;
-            if (eb) k |= T.ekbit[i];
             if (T.upper) {
               if (eb != sb) f = make_float2(0.f, 0.f);
             } else if (eb & sb) {
               f = make_float2(-f.x, -f.y);
             }
           }
-          X[k * (uint64_t)T.ldx + si] = f;
+          dst[e] = f;
         }
       }
 }
@@ -614,9 +619,8 @@ size_t tail_w_bytes(const TailDesc& h, int ns) {
 }
 
 hipError_t launch_tail(const TailDesc& h, const TailDesc* d_desc, const DevOp* d_ops,
-                       const float2* states, const uint32_t* svals, const uint64_t* node_k,
-                       const uint64_t* leaf_k, int s0, int ns, float2* W, float2* X,
-                       hipStream_t st) {
+                       const float2* states, const uint32_t* svals, int s0, int ns, float2* W,
+                       float2* X, hipStream_t st) {
   if (ns <= 0) return hipSuccess;
   const int lg = h.q < 6 ? h.q : 6;
   const uint64_t threads = (uint64_t)ns << lg;
@@ -637,19 +641,20 @@ hipError_t launch_tail(const TailDesc& h, const TailDesc* d_desc, const DevOp* d
   }
   {
     const int Lam = 1 << h.M;
-    dim3 g((unsigned)((h.n_nodes + kTN - 1) / kTN), (unsigned)((Lam + kTM - 1) / kTM), (unsigned)ns);
+    dim3 g((unsigned)((Lam + kTN - 1) / kTN), (unsigned)((h.n_nodes + kTM - 1) / kTM), (unsigned)ns);
     if (g.y > 65535 || g.z > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_tail_mm, g, dim3(kTailThreads), 0, st, d_desc, W, states, svals, s0,
-                       node_k, leaf_k, X);
+    hipLaunchKernelGGL(k_tail_mm, g, dim3(kTailThreads), 0, st, d_desc, W, states, svals, s0, X);
   }
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ assembly GEMM
 //
-// C (M x N) = A^T B over the copy index k, complex64, with both operands stored
-// k-major: A[k*lda + i] (upper half amplitudes), B[k*ldb + j] (lower half).
-// Real form: Cre = Are Bre - Aim Bim, Cim = Are Bim + Aim Bre.
+// C (M x N) = A B^T over the copy index k, complex64, with both operands stored
+// with the copy index contiguous: A[i*lda + k] (upper half amplitudes at value
+// i), B[j*ldb + k] (lower half at value j).  Each complex product is taken as
+// three real ones: P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), with
+// Cre = P1 - P2 and Cim = P3 - P1 - P2.
 //
 // Workgroup tile 128 x 128 (4 waves of 64 x 64, each 4 x 4 MFMA tiles of
 // 16 x 16).  The copy index is split over gridDim.z; each split writes a
@@ -666,7 +671,7 @@ constexpr int kFK = 8;
 constexpr int kFPad = 4;
 
 __global__ void __launch_bounds__(kGemmThreads)
-k_zgemm_tn_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int lda,
+k_zgemm_nt_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int lda,
                const float2* __restrict__ B, int ldb, float2* __restrict__ out, int ldo,
                size_t split_stride) {
   __shared__ float2 As[2][kFK][kGBM + kFPad];
@@ -677,31 +682,32 @@ k_zgemm_tn_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int 
   const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
   const int kb = blockIdx.z * kper;
   const int ke = min(K, kb + kper);
-  floatx4 ar[4][4], ai[4][4];
+  floatx4 p1[4][4], p2[4][4], p3[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      ar[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-      ai[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+      p1[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+      p2[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+      p3[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-  // each thread stages 4 complex of A and 4 of B per K step: row tid/32, cols 4*(tid%32)..+3
-  const int lr = tid >> 5, lc = (tid & 31) * 4;
+  // each thread stages 4 consecutive k of one row of A and of B per K step
+  const int lr = tid >> 1, lk = (tid & 1) * 4;
   float2 ra[4], rb[4];
   auto gload = [&](int k0) {
-    const int k = k0 + lr;
+    const int i = i_blk + lr, j = j_blk + lr;
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
-      const int i = i_blk + lc + x, j = j_blk + lc + x;
-      ra[x] = (k < ke && i < M) ? A[(size_t)k * lda + i] : make_float2(0.f, 0.f);
-      rb[x] = (k < ke && j < N) ? B[(size_t)k * ldb + j] : make_float2(0.f, 0.f);
+      const int k = k0 + lk + x;
+      ra[x] = (k < ke && i < M) ? A[(size_t)i * lda + k] : make_float2(0.f, 0.f);
+      rb[x] = (k < ke && j < N) ? B[(size_t)j * ldb + k] : make_float2(0.f, 0.f);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
-      As[buf][lr][lc + x] = ra[x];
-      Bs[buf][lr][lc + x] = rb[x];
+      As[buf][lk + x][lr] = ra[x];
+      Bs[buf][lk + x][lr] = rb[x];
     }
   };
   int buf = 0;
@@ -722,10 +728,10 @@ k_zgemm_tn_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int 
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          ar[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[b].x, ar[a][b], 0, 0, 0);
-          ar[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av[a].y, bv[b].y, ar[a][b], 0, 0, 0);
-          ai[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[b].y, ai[a][b], 0, 0, 0);
-          ai[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].y, bv[b].x, ai[a][b], 0, 0, 0);
+          p1[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[b].x, p1[a][b], 0, 0, 0);
+          p2[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].y, bv[b].y, p2[a][b], 0, 0, 0);
+          p3[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x + av[a].y, bv[b].x + bv[b].y,
+                                                          p3[a][b], 0, 0, 0);
         }
     }
     if (more) {
@@ -743,7 +749,9 @@ k_zgemm_tn_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int 
       for (int e = 0; e < 4; ++e) {
         const int i = i_blk + wi + a * 16 + 4 * (lane >> 4) + e;
         const int j = j_blk + wj + b * 16 + (lane & 15);
-        if (i < M && j < N) o[(size_t)i * ldo + j] = make_float2(ar[a][b][e], ai[a][b][e]);
+        if (i < M && j < N)
+          o[(size_t)i * ldo + j] = make_float2(p1[a][b][e] - p2[a][b][e],
+                                               p3[a][b][e] - p1[a][b][e] - p2[a][b][e]);
       }
 }
 
@@ -776,12 +784,12 @@ constexpr int kBK = 32;
 
 __global__ void k_split_bf16(const float2* __restrict__ src, int ld, int K, int rows, int Kp,
                              int rows_pad, __hip_bfloat16* __restrict__ dst) {
-  // dst[p][row][k], p = re_hi, re_lo, im_hi, im_lo; zero padding beyond K and rows
+  // src[row * ld + k]; dst[p][row][k], p = re_hi, re_lo, im_hi, im_lo; zero padding
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t plane = (size_t)rows_pad * Kp;
   if (idx >= plane) return;
   const int row = (int)(idx / Kp), k = (int)(idx % Kp);
-  const float2 v = (k < K && row < rows) ? src[(size_t)k * ld + row] : make_float2(0.f, 0.f);
+  const float2 v = (k < K && row < rows) ? src[(size_t)row * ld + k] : make_float2(0.f, 0.f);
   const __hip_bfloat16 rh = __float2bfloat16(v.x);
   const __hip_bfloat16 rl = __float2bfloat16(v.x - __bfloat162float(rh));
   const __hip_bfloat16 ih = __float2bfloat16(v.y);
@@ -923,7 +931,7 @@ hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int l
   float2* P = (float2*)work;
   dim3 grid((N + kGBN - 1) / kGBN, (M + kGBM - 1) / kGBM, g.splits);
   if (prec == 0) {
-    hipLaunchKernelGGL(k_zgemm_tn_f32, grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper, A, lda,
+    hipLaunchKernelGGL(k_zgemm_nt_f32, grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper, A, lda,
                        B, ldb, P, N, ss);
   } else {
     const int Mp = round_up(M, kGBM), Np = round_up(N, kGBN);
@@ -947,6 +955,26 @@ hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int l
 
 // ------------------------------------------------------------------ small kernels
 
+// out[row][j] = in[row][perm[j]] for every row (K columns): brings the lower
+// half's copy order onto the upper half's.
+__global__ void k_permute_cols(const float2* __restrict__ in, float2* __restrict__ out,
+                               const uint32_t* __restrict__ perm, int rows, int K) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)rows * K) return;
+  const size_t row = t / K;
+  const int j = (int)(t % K);
+  out[t] = in[row * K + perm[j]];
+}
+
+hipError_t launch_permute_cols(const float2* in, float2* out, const uint32_t* perm, int rows,
+                               int K, hipStream_t st) {
+  const size_t tot = (size_t)rows * K;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_permute_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, in, out,
+                     perm, rows, K);
+  return hipGetLastError();
+}
+
 // Sum over copies for one bitstring per wavefront; lanes stride over k, then
 // a fixed-order butterfly reduction.
 __global__ void __launch_bounds__(256)
@@ -959,7 +987,7 @@ k_gathered_dot(int K, const float2* __restrict__ A, int lda, const float2* __res
   const int u = iu[t], l = il[t];
   float re = 0.f, im = 0.f;
   for (int k = lane; k < K; k += 64) {
-    const float2 a = A[(size_t)k * lda + u], b = B[(size_t)k * ldb + l];
+    const float2 a = A[(size_t)u * lda + k], b = B[(size_t)l * ldb + k];
     re += a.x * b.x - a.y * b.y;
     im += a.x * b.y + a.y * b.x;
   }

@@ -57,7 +57,7 @@ struct SidePlan {
 };
 
 struct PlanKnobs {
-  int tile_bits = 11;
+  int tile_bits = 10;
   int coalesce_bits = 5;
   int tail_max_qubits = 10;
   int force_lstar = -1;

@@ -338,6 +338,16 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
     td.eq[i] = cut_qubit(tr.end_cuts[i]);
     td.ekbit[i] = 1ULL << (c - 1 - tr.end_cuts[i]);
   }
+  // spread each value's backward rows over up to 8 wavefronts (the first
+  // reverse levels' branches) so that a launch has several waves per SIMD
+  td.split_levels = 0;
+  td.split_bits = 0;
+  while (td.split_levels < td.nlev) {
+    const int m = td.lev[td.nlev - 1 - td.split_levels].m;
+    if (td.split_bits + m > 3) break;
+    td.split_bits += m;
+    ++td.split_levels;
+  }
   td.upper = s.upper ? 1 : 0;
   td.n_nodes = (int)sp.nodes[sp.lstar];
   td.S = S;

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace qs {
@@ -409,6 +411,7 @@ struct TailCtx {
   uint32_t xs[R];
   int g;       // lane inside the group
   int lg;      // log2 of the group width
+  int sub;     // this wavefront's branches of the first reverse levels
 };
 
 template <int R>
@@ -458,7 +461,15 @@ __device__ __forceinline__ void tail_bwd_rec(const float2 (&v)[R], const TailCtx
     tail_apply_ops<R>(u, c, ops + L.bop0, L.bnops);
     const int m = L.m;
     const int G = 1 << c.lg;
-    for (int b = 0; b < (1 << m); ++b) {
+    int b_lo = 0, b_hi = 1 << m;
+    if (D < T.split_levels) {
+      // only the branch this wavefront owns
+      int sh = 0;
+      for (int d2 = D + 1; d2 < T.split_levels; ++d2) sh += T.lev[T.nlev - 1 - d2].m;
+      b_lo = (c.sub >> sh) & ((1 << m) - 1);
+      b_hi = b_lo + 1;
+    }
+    for (int b = b_lo; b < b_hi; ++b) {
       uint32_t cmask, cval, zmask;
       cut_factors(L.bq, m, b, T.upper, cmask, cval, zmask);
       float2 w[R];
@@ -489,11 +500,13 @@ k_tail_bwd(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
   const int lg = T.q < 6 ? T.q : 6;
   const int G = 1 << lg;
   const uint64_t gtid = (uint64_t)blockIdx.x * kTailThreads + threadIdx.x;
-  const uint64_t gid = gtid >> lg;
-  if (gid >= (uint64_t)ns) return;
+  const uint64_t grp = gtid >> lg;
+  if (grp >= ((uint64_t)ns << T.split_bits)) return;
+  const uint64_t gid = grp >> T.split_bits;
   TailCtx<R> c;
   c.g = (int)(gtid & (G - 1));
   c.lg = lg;
+  c.sub = (int)(grp & ((1u << T.split_bits) - 1));
   const uint32_t s = svals[s0 + gid];
   uint32_t qmask = 0, ys = 0;
   for (int i = 0; i < T.q; ++i) {
@@ -514,7 +527,7 @@ k_tail_bwd(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
   float2* Wrow = W + gid * ((size_t)1 << T.M) * K;
   if (T.nlev == 0) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) Wrow[c.g + (r << lg)] = v[r];
+    for (int r = 0; r < R; ++r) Wrow[c.g + (r << lg)] = v[r];  // split_bits is 0 here
     return;
   }
   tail_bwd_rec<R, 0>(v, c, T, ops, 0u, Wrow);
@@ -623,7 +636,7 @@ hipError_t launch_tail(const TailDesc& h, const TailDesc* d_desc, const DevOp* d
                        float2* X, hipStream_t st) {
   if (ns <= 0) return hipSuccess;
   const int lg = h.q < 6 ? h.q : 6;
-  const uint64_t threads = (uint64_t)ns << lg;
+  const uint64_t threads = ((uint64_t)ns << h.split_bits) << lg;
   const uint64_t blocks = (threads + kTailThreads - 1) / kTailThreads;
   const int R = h.q <= 6 ? 1 : (1 << (h.q - 6));
   {
@@ -667,48 +680,59 @@ constexpr int kGBM = 128, kGBN = 128;
 static inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 // FP32 MFMA: v_mfma_f32_16x16x4f32, K step 8 complex, LDS double-buffered.
+// Each of the 2 x 2 waves owns TM x TN MFMA tiles (16 x 16 each), so the
+// workgroup tile is (32 TM) x (32 TN).
 constexpr int kFK = 8;
 constexpr int kFPad = 4;
 
+template <int TM, int TN>
 __global__ void __launch_bounds__(kGemmThreads)
 k_zgemm_nt_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int lda,
                const float2* __restrict__ B, int ldb, float2* __restrict__ out, int ldo,
                size_t split_stride) {
-  __shared__ float2 As[2][kFK][kGBM + kFPad];
-  __shared__ float2 Bs[2][kFK][kGBN + kFPad];
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  __shared__ float2 As[2][kFK][BM + kFPad];
+  __shared__ float2 Bs[2][kFK][BN + kFPad];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int i_blk = blockIdx.y * kGBM, j_blk = blockIdx.x * kGBN;
-  const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
+  const int i_blk = blockIdx.y * BM, j_blk = blockIdx.x * BN;
+  const int wi = (wave >> 1) * (16 * TM), wj = (wave & 1) * (16 * TN);
   const int kb = blockIdx.z * kper;
   const int ke = min(K, kb + kper);
-  floatx4 p1[4][4], p2[4][4], p3[4][4];
+  floatx4 p1[TM][TN], p2[TM][TN], p3[TM][TN];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < TN; ++b) {
       p1[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
       p2[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
       p3[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-  // each thread stages 4 consecutive k of one row of A and of B per K step
-  const int lr = tid >> 1, lk = (tid & 1) * 4;
-  float2 ra[4], rb[4];
+  // staging: BM (BN) rows of kFK consecutive k; each thread takes VA (VB)
+  // consecutive k of one row
+  constexpr int VA = BM * kFK / kGemmThreads, VB = BN * kFK / kGemmThreads;
+  static_assert(VA >= 1 && VB >= 1 && kFK % VA == 0 && kFK % VB == 0, "staging map");
+  float2 ra[VA], rb[VB];
+  const int ra_row = tid / (kFK / VA), ra_k = (tid % (kFK / VA)) * VA;
+  const int rb_row = tid / (kFK / VB), rb_k = (tid % (kFK / VB)) * VB;
   auto gload = [&](int k0) {
-    const int i = i_blk + lr, j = j_blk + lr;
+    const int i = i_blk + ra_row, j = j_blk + rb_row;
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      const int k = k0 + lk + x;
+    for (int x = 0; x < VA; ++x) {
+      const int k = k0 + ra_k + x;
       ra[x] = (k < ke && i < M) ? A[(size_t)i * lda + k] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int x = 0; x < VB; ++x) {
+      const int k = k0 + rb_k + x;
       rb[x] = (k < ke && j < N) ? B[(size_t)j * ldb + k] : make_float2(0.f, 0.f);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      As[buf][lk + x][lr] = ra[x];
-      Bs[buf][lk + x][lr] = rb[x];
-    }
+    for (int x = 0; x < VA; ++x) As[buf][ra_k + x][ra_row] = ra[x];
+#pragma unroll
+    for (int x = 0; x < VB; ++x) Bs[buf][rb_k + x][rb_row] = rb[x];
   };
   int buf = 0;
   gload(kb);
@@ -719,15 +743,15 @@ k_zgemm_nt_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int 
     if (more) gload(k0 + kFK);
 #pragma unroll
     for (int kk = 0; kk < kFK; kk += 4) {
-      float2 av[4], bv[4];
+      float2 av[TM], bv[TN];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[buf][kk + (lane >> 4)][wi + a * 16 + (lane & 15)];
+      for (int a = 0; a < TM; ++a) av[a] = As[buf][kk + (lane >> 4)][wi + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = Bs[buf][kk + (lane >> 4)][wj + b * 16 + (lane & 15)];
+      for (int b = 0; b < TN; ++b) bv[b] = Bs[buf][kk + (lane >> 4)][wj + b * 16 + (lane & 15)];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < TM; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < TN; ++b) {
           p1[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[b].x, p1[a][b], 0, 0, 0);
           p2[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].y, bv[b].y, p2[a][b], 0, 0, 0);
           p3[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x + av[a].y, bv[b].x + bv[b].y,
@@ -742,9 +766,9 @@ k_zgemm_nt_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int 
   }
   float2* o = out + (size_t)blockIdx.z * split_stride;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int i = i_blk + wi + a * 16 + 4 * (lane >> 4) + e;
@@ -893,13 +917,17 @@ k_zgemm_tn_bf16x3(int M, int N, int Kp, int kper, const __hip_bfloat16* __restri
 namespace {
 
 struct GemmShape {
-  int tiles, splits, kper;
+  int bm, bn, tiles, splits, kper;
 };
 
 // Enough workgroups to fill the 256 compute units a few times over.
-GemmShape gemm_shape(int M, int N, int K, int kstep) {
+GemmShape gemm_shape(int prec, int M, int N, int K, int kstep) {
   GemmShape g;
-  g.tiles = ((M + kGBM - 1) / kGBM) * ((N + kGBN - 1) / kGBN);
+  // FP32: 128 x 64 tiles (measured faster than 128 x 128 and 64 x 64 at
+  // 1024 x 1024 outputs: two waves per SIMD instead of one)
+  g.bm = 128;
+  g.bn = prec == 0 ? 64 : 128;
+  g.tiles = ((M + g.bm - 1) / g.bm) * ((N + g.bn - 1) / g.bn);
   const int want = std::max(1, 1024 / std::max(1, g.tiles));
   const int maxsplit = std::max(1, K / (4 * kstep));
   g.splits = std::max(1, std::min({want, maxsplit, 64}));
@@ -913,7 +941,7 @@ GemmShape gemm_shape(int M, int N, int K, int kstep) {
 size_t zgemm_workspace_bytes(int prec, int M, int N, int K) {
   const int kstep = prec == 0 ? kFK : kBK;
   const int Kp = prec == 0 ? K : round_up(K, kBK);
-  const GemmShape g = gemm_shape(M, N, Kp, kstep);
+  const GemmShape g = gemm_shape(prec, M, N, Kp, kstep);
   size_t b = (size_t)g.splits * M * N * sizeof(float2);
   if (prec != 0)
     b += 4 * (size_t)Kp * (round_up(M, kGBM) + round_up(N, kGBN)) * sizeof(__hip_bfloat16) + 256;
@@ -926,13 +954,13 @@ hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int l
   if (M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
   const int kstep = prec == 0 ? kFK : kBK;
   const int Kp = prec == 0 ? K : round_up(K, kBK);
-  const GemmShape g = gemm_shape(M, N, Kp, kstep);
+  const GemmShape g = gemm_shape(prec, M, N, Kp, kstep);
   const size_t ss = (size_t)M * N;
   float2* P = (float2*)work;
-  dim3 grid((N + kGBN - 1) / kGBN, (M + kGBM - 1) / kGBM, g.splits);
+  dim3 grid((N + g.bn - 1) / g.bn, (M + g.bm - 1) / g.bm, g.splits);
   if (prec == 0) {
-    hipLaunchKernelGGL(k_zgemm_nt_f32, grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper, A, lda,
-                       B, ldb, P, N, ss);
+    hipLaunchKernelGGL((k_zgemm_nt_f32<4, 2>), grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper,
+                       A, lda, B, ldb, P, N, ss);
   } else {
     const int Mp = round_up(M, kGBM), Np = round_up(N, kGBN);
     char* base = (char*)work + (size_t)g.splits * ss * sizeof(float2);

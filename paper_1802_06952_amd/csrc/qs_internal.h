@@ -143,6 +143,8 @@ struct TailDesc {
   int Q[16];            // state bit of working bit i
   int nlev;
   int M;                // total branch bits of the leaf levels (leaf paths = 2^M)
+  int split_levels;     // the backward rows of one value are spread over 2^split_bits
+  int split_bits;       //   wavefronts by the branches of the first split_levels reverse levels
   TailLevel lev[kMaxTailLevels];
   int n_end;            // cuts with no later non-commuting gate: applied to the output
   int eq[kMaxBranch * 2];   // state bit of each end cut's qubit (MSB first)

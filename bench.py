@@ -91,7 +91,7 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--plain-copies", type=int, default=16)
-    ap.add_argument("--cpu-copies", type=int, default=64)
+    ap.add_argument("--cpu-copies", type=int, default=256)
     ap.add_argument("--autotune", action="store_true",
                     help="time a grid of schedule knobs first and run with the fastest")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -171,15 +171,15 @@ def main() -> int:
         achieved = flops_per_step / t / 1e12
         roof = {"kernel": "k_tail", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": 157.3, "unit": "TFLOP/s", "frac": round(achieved / 157.3, 4),
-                "traffic": _traffic_from_profile("k_tail", w.name),
+                "traffic": _traffic_from_profile("k_tail_bwd", w.name),
                 "note": "2x2 complex gate flops on the light-cone subspaces (14 per amplitude per gate)"}
     elif dominant == "pass":
         bytes_per_step = tm["pass_bytes"] / a.steps
         avg_launch_s = per_step["pass"] / 1000.0 / max(1.0, launches["pass"])
         per_launch = bytes_per_step / max(1.0, launches["pass"])
         achieved = per_launch / avg_launch_s / 1e9
-        traffic = _traffic_from_profile("k_pass", w.name)
-        roof = {"kernel": "k_pass", "bound": "hbm", "achieved": round(achieved, 1),
+        traffic = _traffic_from_profile("k_wpass", w.name)
+        roof = {"kernel": "k_wpass", "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "algorithmic_bytes_per_launch": per_launch,
                 "avg_launch_us": avg_launch_s * 1e6}
@@ -188,10 +188,10 @@ def main() -> int:
         t = per_step["gemm"] / 1000.0
         achieved = flops_per_step / t / 1e12
         peak = MFMA_PEAK_TFLOPS[prec]
-        roof = {"kernel": "k_zgemm_tn_f32" if prec == 0 else "k_zgemm_tn_bf16x3", "bound": "mfma",
+        roof = {"kernel": "k_zgemm_nt_f32" if prec == 0 else "k_zgemm_tn_bf16x3", "bound": "mfma",
                 "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4),
-                "traffic": _traffic_from_profile("k_zgemm", w.name),
+                "traffic": _traffic_from_profile("k_zgemm_nt_f32" if prec == 0 else "k_zgemm_tn_bf16x3", w.name),
                 "note": "FP32-equivalent flops 8*M*N*K" if prec else "8*M*N*K"}
 
     # executed and flat (paper accounting) amp-updates

@@ -1,0 +1,138 @@
+"""Summaries of rocprofv3 output databases (kernel traces and PMC counters).
+
+rocprofv3 writes one SQLite database per run.  Two summaries are made here:
+
+* ``trace``: per-kernel call count, total and average duration from a
+  ``--kernel-trace --stats`` run, plus each kernel's register and LDS use;
+* ``counters``: HBM bytes per dispatch of one kernel family from two ``--pmc``
+  runs (``FETCH_SIZE``, then ``WRITE_SIZE``, both in KiB per dispatch).  Each
+  counter is divided by what it reads for a plain copy of known size made in
+  the same run (the largest copy-like dispatch), which turns it into bytes.
+
+Usage::
+
+    python -m paper_1802_06952_amd.profiling trace DIR --cmd "..." > summary.md
+    python -m paper_1802_06952_amd.profiling counters FETCH_DIR WRITE_DIR \\
+        --kernel k_wpass --workload grid6x7_d20 --calib-bytes N --cmd "..."
+"""
+
+from __future__ import annotations
+
+import argparse
+import collections
+import glob
+import hashlib
+import json
+import os
+import re
+import sqlite3
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _db(d: str) -> sqlite3.Connection:
+    files = sorted(glob.glob(os.path.join(d, "**", "*.db"), recursive=True))
+    if not files:
+        raise SystemExit(f"no rocprofv3 database under {d}")
+    return sqlite3.connect(files[0])
+
+
+def short_name(n: str) -> str:
+    n = re.sub(r"\(.*", "", n).replace("void ", "")
+    return n
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_1802_06952_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def trace_summary(d: str, cmd: str) -> str:
+    con = _db(d)
+    out = [f"Command: `{cmd}`", "",
+           "rocprofv3 `--kernel-trace --stats` summary (durations in microseconds, all dispatches "
+           "of the run).", "",
+           "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
+    for n, c, t, a, p in con.execute(
+            "select name, total_calls, total_duration, average, percentage from top_kernels"):
+        out.append(f"| `{short_name(n)}` | {c} | {t:.1f} | {a:.2f} | {p:.1f} |")
+    out += ["", "Resources per kernel:", "", "| kernel | vgpr | agpr | sgpr | lds | scratch |",
+            "|---|---|---|---|---|---|"]
+    for n, v, acc, sg, lds, scr in con.execute(
+            "select name, vgpr_count, accum_vgpr_count, sgpr_count, lds_size, scratch_size "
+            "from kernels group by name"):
+        out.append(f"| `{short_name(n)}` | {v} | {acc} | {sg} | {lds} | {scr} |")
+    out.append("")
+    out.append(f"kernels.hip sha256[:16] = {kernel_source_hash()}")
+    return "\n".join(out) + "\n"
+
+
+def _pmc(d: str):
+    con = _db(d)
+    vals = collections.defaultdict(dict)
+    names = {}
+    for disp, kname, cname, val in con.execute(
+            "select dispatch_id, name, counter_name, counter_value from pmc_events"):
+        vals[disp][cname] = vals[disp].get(cname, 0.0) + float(val)
+        names[disp] = short_name(kname)
+    return vals, names
+
+
+def _is_copy(name: str) -> bool:
+    return "copy" in name.lower() or "elementwise" in name.lower()
+
+
+def counter_summary(fetch_dir: str, write_dir: str, kernel: str, calib_bytes: int) -> dict:
+    f, fn = _pmc(fetch_dir)
+    w, wn = _pmc(write_dir)
+
+    def calib(vals, names, counter):
+        cand = [vals[k].get(counter, 0.0) for k in vals if _is_copy(names[k])]
+        if not cand:
+            raise SystemExit("no copy dispatch found for calibration")
+        return max(cand) * 1024.0 / calib_bytes   # counter KiB -> bytes, over the true bytes
+
+    cf = calib(f, fn, "FETCH_SIZE")
+    cw = calib(w, wn, "WRITE_SIZE")
+    fk = [f[k].get("FETCH_SIZE", 0.0) for k in f if fn[k].startswith(f"qs::{kernel}")]
+    wk = [w[k].get("WRITE_SIZE", 0.0) for k in w if wn[k].startswith(f"qs::{kernel}")]
+    if not fk or not wk:
+        raise SystemExit(f"no dispatch of {kernel}")
+    fetch = sum(fk) / len(fk) * 1024.0 / cf
+    write = sum(wk) / len(wk) * 1024.0 / cw
+    return {"kernel": kernel, "dispatches": len(fk),
+            "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+            "hbm_bytes_per_launch": fetch + write,
+            "calibration": {"copy_bytes": calib_bytes, "fetch_factor": cf, "write_factor": cw,
+                            "note": "counter bytes read for a plain copy of copy_bytes, divided "
+                                    "by copy_bytes; kernel counters are divided by it"},
+            "kernels_hip_sha256_16": kernel_source_hash()}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("dir")
+    t.add_argument("--cmd", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("fetch_dir")
+    c.add_argument("write_dir")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--workload", required=True)
+    c.add_argument("--calib-bytes", type=int, required=True)
+    c.add_argument("--cmd", required=True)
+    a = ap.parse_args(argv)
+    if a.what == "trace":
+        sys.stdout.write(trace_summary(a.dir, a.cmd))
+    else:
+        d = counter_summary(a.fetch_dir, a.write_dir, a.kernel, a.calib_bytes)
+        d["workload"] = a.workload
+        d["command"] = a.cmd
+        json.dump(d, sys.stdout, indent=1)
+        sys.stdout.write("\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -103,7 +103,8 @@ struct Prepared {
   std::vector<PassDesc> pds;
   TailDesc td{};
   char* dev = nullptr;  // descriptors, tail desc, ops, node copy indices (owned)
-  size_t o_pd = 0, o_td = 0, o_ops = 0, o_nk = 0, o_lk = 0, o_sv = 0;
+  size_t o_pd = 0, o_td = 0, o_ops = 0, o_nk = 0, o_lk = 0, o_sv = 0, o_tl = 0;
+  uint32_t n_list = 0;  // tiles of the last pass that the leaf evaluation reads (0 = all)
   std::vector<uint64_t> leaf_k;
   std::vector<uint32_t> nu_to_k;  // block-local copy index of each natural position nu
   double pass_bytes = 0;  // algorithmic bytes of the passes
@@ -237,6 +238,7 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   };
   const double SB = std::ldexp(8.0, s.n);
   std::vector<DevOp> ops;
+  double last_bytes = 0;
   for (const PassPlan& pp : sp.passes) {
     PassDesc d{};
     d.wave = s.n >= 7 ? 1 : 0;
@@ -271,10 +273,11 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
       const Level& nx = tr.levels[pp.level_in + 1];
       d.m = (int)nx.cuts.size();
       for (int i = 0; i < d.m; ++i) d.bq[i] = cut_qubit(nx.cuts[i]);
-      pr->pass_bytes += (pp.init ? 0.0 : nin * SB) + (double)sp.nodes[pp.level_in + 1] * SB;
+      last_bytes = (pp.init ? 0.0 : nin * SB) + (double)sp.nodes[pp.level_in + 1] * SB;
     } else {
-      pr->pass_bytes += (pp.init ? 1.0 : 2.0) * nin * SB;
+      last_bytes = (pp.init ? 1.0 : 2.0) * nin * SB;
     }
+    pr->pass_bytes += last_bytes;
     d.upper = s.upper ? 1 : 0;
     pr->pds.push_back(d);
   }
@@ -395,8 +398,44 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
     sv[i] = w;
   }
   const size_t b_sv = (size_t)S * sizeof(uint32_t);
+  // The leaf evaluation reads the last materialised states only at the
+  // requested values with their light-cone bits free, so the last pass need
+  // only produce the tiles whose outer bits agree with some requested value
+  // (outer bits inside the light cone take both values).
+  std::vector<uint32_t> tl;
+  if (!P->opts.plain && !pr->pds.empty() && pr->pds.back().wave) {
+    const PassDesc& d = pr->pds.back();
+    uint32_t qmask = 0;
+    for (int i = 0; i < td.q; ++i) qmask |= 1u << td.Q[i];
+    std::vector<int> fixed_j, free_j;
+    for (int j = 0; j < d.n_outer; ++j) ((qmask >> d.obit[j]) & 1 ? free_j : fixed_j).push_back(j);
+    const int nf = (int)free_j.size();
+    if (d.n_outer > 0 && nf <= 6) {
+      tl.reserve((size_t)S << nf);
+      for (int i = 0; i < S; ++i) {
+        uint32_t t0 = 0;
+        for (int j : fixed_j) t0 |= ((sv[i] >> d.obit[j]) & 1u) << j;
+        for (int f = 0; f < (1 << nf); ++f) {
+          uint32_t t = t0;
+          for (int b = 0; b < nf; ++b) t |= (uint32_t)((f >> b) & 1) << free_j[b];
+          tl.push_back(t);
+        }
+      }
+      std::sort(tl.begin(), tl.end());
+      tl.erase(std::unique(tl.begin(), tl.end()), tl.end());
+      const double frac = (double)tl.size() / std::ldexp(1.0, d.n_outer);
+      if (frac > 0.75) {
+        tl.clear();
+      } else {
+        pr->pass_bytes -= last_bytes * (1.0 - frac);
+      }
+    }
+  }
+  pr->n_list = (uint32_t)tl.size();
+  const size_t b_tl = tl.size() * sizeof(uint32_t);
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t total = al(b_pd) + al(b_td) + al(b_ops) + al(b_nk) + al(b_lk) + al(b_sv);
+  const size_t total =
+      al(b_pd) + al(b_td) + al(b_ops) + al(b_nk) + al(b_lk) + al(b_sv) + al(b_tl);
   std::vector<char> host(total, 0);
   pr->o_pd = 0;
   pr->o_td = al(b_pd);
@@ -404,12 +443,14 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   pr->o_nk = pr->o_ops + al(b_ops);
   pr->o_lk = pr->o_nk + al(b_nk);
   pr->o_sv = pr->o_lk + al(b_lk);
+  pr->o_tl = pr->o_sv + al(b_sv);
   if (b_pd) std::memcpy(host.data() + pr->o_pd, pr->pds.data(), b_pd);
   std::memcpy(host.data() + pr->o_td, &td, b_td);
   if (!ops.empty()) std::memcpy(host.data() + pr->o_ops, ops.data(), ops.size() * sizeof(DevOp));
   std::memcpy(host.data() + pr->o_nk, node_k.data(), b_nk);
   std::memcpy(host.data() + pr->o_lk, pr->leaf_k.data(), b_lk);
   std::memcpy(host.data() + pr->o_sv, sv.data(), b_sv);
+  if (b_tl) std::memcpy(host.data() + pr->o_tl, tl.data(), b_tl);
   if (hipMalloc(&pr->dev, total) != hipSuccess) {
     (void)hipGetLastError();
     pr->dev = nullptr;
@@ -435,6 +476,9 @@ qs_status run_side(qs_plan* P, int sidx, const Prepared& pr, float2* X, hipStrea
     for (size_t pi = 0; pi < sp.passes.size(); ++pi) {
       const PassPlan& pp = sp.passes[pi];
       const PassDesc* dd = (const PassDesc*)(pr.dev + pr.o_pd) + pi;
+      const bool last = pi + 1 == sp.passes.size() && pr.n_list > 0;
+      const uint32_t* tl = last ? (const uint32_t*)(pr.dev + pr.o_tl) : nullptr;
+      const uint32_t nl = last ? pr.n_list : 0;
       if (pp.init) {
         cur_nodes = 1;
         cur = (float2*)P->pool.get(SB);
@@ -444,12 +488,12 @@ qs_status run_side(qs_plan* P, int sidx, const Prepared& pr, float2* X, hipStrea
         const uint64_t on = sp.nodes[pp.level_in + 1];
         float2* nxt = (float2*)P->pool.get(SB * on);
         if (!nxt) return fail(QS_ERR_OOM, "tree level states");
-        HIPCHECK(launch_pass(pr.pds[pi], dd, d_ops, cur, nxt, cur_nodes, st));
+        HIPCHECK(launch_pass(pr.pds[pi], dd, d_ops, cur, nxt, cur_nodes, tl, nl, st));
         P->pool.put(cur);
         cur = nxt;
         cur_nodes = on;
       } else {
-        HIPCHECK(launch_pass(pr.pds[pi], dd, d_ops, cur, cur, cur_nodes, st));
+        HIPCHECK(launch_pass(pr.pds[pi], dd, d_ops, cur, cur, cur_nodes, tl, nl, st));
       }
       ++tm.launches;
     }

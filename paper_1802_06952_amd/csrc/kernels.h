@@ -10,8 +10,12 @@ namespace qs {
 // Full-state pass over all tiles of `n_in_nodes` input states (or 1 when the
 // pass starts from the initial product state).  d_desc / d_ops live in device
 // memory; h_desc is the same descriptor on the host (for the launch shape).
+// tlist (optional, wave-tile passes only): the n_list outer-bit values of
+// the tiles to compute in every node; the other tiles of the output are left
+// as they are.
 hipError_t launch_pass(const PassDesc& h_desc, const PassDesc* d_desc, const DevOp* d_ops,
-                       const float2* in, float2* out, uint64_t n_in_nodes, hipStream_t st);
+                       const float2* in, float2* out, uint64_t n_in_nodes, const uint32_t* tlist,
+                       uint32_t n_list, hipStream_t st);
 
 // Light-cone leaf evaluation for the requested values s0 .. s0+ns-1: the
 // backward rows into W (tail_w_bytes(h, ns) bytes), then the contraction with

@@ -309,15 +309,22 @@ __device__ __forceinline__ void wave_apply_ops(float2 (&v)[1 << R], const DevOp*
 template <int R>
 __global__ void __launch_bounds__(kWaveThreads)
 k_wpass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops, const float2* in,
-        float2* out, uint64_t total_tiles) {
+        float2* out, uint64_t total_tiles, const uint32_t* __restrict__ tlist, uint32_t n_list) {
   constexpr int E = 1 << R;
   const PassDesc& P = *pdp;
   const int lane = threadIdx.x & 63;
   const uint64_t wt = (uint64_t)blockIdx.x * (kWaveThreads / 64) + (threadIdx.x >> 6);
   if (wt >= total_tiles) return;
   const int nouter = P.n_outer;
-  const uint64_t node = wt >> nouter;
-  const uint64_t tile = wt & ((1ull << nouter) - 1);
+  uint64_t node, tile;
+  if (tlist) {
+    // only the listed tiles of every node (the rest is never read)
+    node = wt / n_list;
+    tile = tlist[wt - node * n_list];
+  } else {
+    node = wt >> nouter;
+    tile = wt & ((1ull << nouter) - 1);
+  }
   uint32_t xo = 0;
   for (int j = 0; j < nouter; ++j) xo |= (uint32_t)((tile >> j) & 1) << P.obit[j];
   uint32_t RB[R];
@@ -367,19 +374,31 @@ k_wpass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops, const f
 }
 
 hipError_t launch_pass(const PassDesc& h, const PassDesc* d_desc, const DevOp* d_ops,
-                       const float2* in, float2* out, uint64_t n_in_nodes, hipStream_t st) {
+                       const float2* in, float2* out, uint64_t n_in_nodes, const uint32_t* tlist,
+                       uint32_t n_list, hipStream_t st) {
+  if (tlist && (!h.wave || n_list == 0)) return hipErrorInvalidValue;
   if (h.wave) {
     const int R = h.t - 6;
-    const uint64_t tiles = n_in_nodes << h.n_outer;
+    const uint64_t tiles = tlist ? n_in_nodes * n_list : n_in_nodes << h.n_outer;
     const uint64_t blocks = (tiles + (kWaveThreads / 64) - 1) / (kWaveThreads / 64);
     if (blocks == 0 || blocks > 0x7fffffffull) return hipErrorInvalidValue;
     dim3 g((unsigned)blocks), b(kWaveThreads);
     switch (R) {
-      case 1: hipLaunchKernelGGL(k_wpass<1>, g, b, 0, st, d_desc, d_ops, in, out, tiles); break;
-      case 2: hipLaunchKernelGGL(k_wpass<2>, g, b, 0, st, d_desc, d_ops, in, out, tiles); break;
-      case 3: hipLaunchKernelGGL(k_wpass<3>, g, b, 0, st, d_desc, d_ops, in, out, tiles); break;
-      case 4: hipLaunchKernelGGL(k_wpass<4>, g, b, 0, st, d_desc, d_ops, in, out, tiles); break;
-      case 5: hipLaunchKernelGGL(k_wpass<5>, g, b, 0, st, d_desc, d_ops, in, out, tiles); break;
+      case 1:
+        hipLaunchKernelGGL(k_wpass<1>, g, b, 0, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
+        break;
+      case 2:
+        hipLaunchKernelGGL(k_wpass<2>, g, b, 0, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
+        break;
+      case 3:
+        hipLaunchKernelGGL(k_wpass<3>, g, b, 0, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
+        break;
+      case 4:
+        hipLaunchKernelGGL(k_wpass<4>, g, b, 0, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
+        break;
+      case 5:
+        hipLaunchKernelGGL(k_wpass<5>, g, b, 0, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
+        break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

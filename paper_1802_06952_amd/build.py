@@ -3,7 +3,8 @@
     python -m paper_1802_06952_amd.build        (or python paper_1802_06952_amd/build.py)
 
 Compiles every source under csrc/ into one shared library next to this file.
-Packed FP32 instructions are switched off for the device code.
+Packed FP32 instructions are switched off for the device code, and MFMA
+results are kept in ordinary vector registers.
 """
 
 from __future__ import annotations
@@ -32,6 +33,9 @@ def build(verbose: bool = True, extra: list[str] | None = None) -> str:
     cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-command-line-argument",
+           # MFMA accumulators in ordinary VGPRs: without it the FP32 GEMM's
+           # loop copies every accumulator between AGPRs and VGPRs
+           "-mllvm", "-amdgpu-mfma-vgpr-form",
            "-I", os.path.join(os.path.dirname(HERE), "include"),
            *srcs, "-o", tmp] + (extra or [])
     if verbose:

@@ -688,7 +688,7 @@ hipError_t launch_tail(const TailDesc& h, const TailDesc* d_desc, const DevOp* d
 // three real ones: P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), with
 // Cre = P1 - P2 and Cim = P3 - P1 - P2.
 //
-// Workgroup tile 128 x 128 (4 waves of 64 x 64, each 4 x 4 MFMA tiles of
+// FP32 workgroup tile 128 x 64 (4 waves of 64 x 32, each 4 x 2 MFMA tiles of
 // 16 x 16).  The copy index is split over gridDim.z; each split writes a
 // partial tile and k_zgemm_reduce adds the partials in a fixed order (the
 // result does not depend on scheduling).
@@ -698,10 +698,10 @@ constexpr int kGBM = 128, kGBN = 128;
 
 static inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-// FP32 MFMA: v_mfma_f32_16x16x4f32, K step 8 complex, LDS double-buffered.
+// FP32 MFMA: v_mfma_f32_16x16x4f32, K step 16 complex, LDS double-buffered.
 // Each of the 2 x 2 waves owns TM x TN MFMA tiles (16 x 16 each), so the
 // workgroup tile is (32 TM) x (32 TN).
-constexpr int kFK = 8;
+constexpr int kFK = 16;
 constexpr int kFPad = 4;
 
 template <int TM, int TN>

@@ -165,34 +165,42 @@ def main() -> int:
     launches = {"pass": tm["pass_launches"] / a.steps, "tail": tm["tail_launches"] / a.steps,
                 "gemm": tm["gemm_launches"] / a.steps, "other": tm["other_launches"] / a.steps}
     dominant = max(("pass", "tail", "gemm"), key=lambda k: fam_ms[k])
-    if dominant == "tail":
-        flops_per_step = tm["tail_flops"] / a.steps
-        t = per_step["tail"] / 1000.0
-        achieved = flops_per_step / t / 1e12
-        roof = {"kernel": "k_tail", "bound": "alu", "achieved": round(achieved, 3),
-                "peak": 157.3, "unit": "TFLOP/s", "frac": round(achieved / 157.3, 4),
-                "traffic": _traffic_from_profile("k_tail_bwd", w.name),
-                "note": "2x2 complex gate flops on the light-cone subspaces (14 per amplitude per gate)"}
-    elif dominant == "pass":
-        bytes_per_step = tm["pass_bytes"] / a.steps
-        avg_launch_s = per_step["pass"] / 1000.0 / max(1.0, launches["pass"])
-        per_launch = bytes_per_step / max(1.0, launches["pass"])
-        achieved = per_launch / avg_launch_s / 1e9
-        traffic = _traffic_from_profile("k_wpass", w.name)
-        roof = {"kernel": "k_wpass", "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "algorithmic_bytes_per_launch": per_launch,
-                "avg_launch_us": avg_launch_s * 1e6}
-    else:
-        flops_per_step = tm["gemm_flops"] / a.steps
-        t = per_step["gemm"] / 1000.0
-        achieved = flops_per_step / t / 1e12
-        peak = MFMA_PEAK_TFLOPS[prec]
-        roof = {"kernel": "k_zgemm_nt_f32" if prec == 0 else "k_zgemm_tn_bf16x3", "bound": "mfma",
-                "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4),
-                "traffic": _traffic_from_profile("k_zgemm_nt_f32" if prec == 0 else "k_zgemm_tn_bf16x3", w.name),
-                "note": "FP32-equivalent flops 8*M*N*K" if prec else "8*M*N*K"}
+    roofs = {}
+    # leaf evaluation: 2x2-gate rows on the vector units and per-value
+    # contractions on FP32 MFMA; priced against the FP32 peak
+    t = per_step["tail"] / 1000.0
+    if t > 0:
+        achieved = tm["tail_flops"] / a.steps / t / 1e12
+        roofs["tail"] = {"kernel": "k_tail_bwd + k_tail_mm", "bound": "alu", "achieved": round(achieved, 3),
+                         "peak": 157.3, "unit": "TFLOP/s", "frac": round(achieved / 157.3, 4),
+                         "traffic": _traffic_from_profile("k_tail_bwd", w.name),
+                         "note": "14 flops per amplitude per 2x2 gate on the light-cone rows, "
+                                 "8 per complex multiply-add in the per-value contraction"}
+    # layer and branch passes: algorithmic bytes = 8 B read + 8 B written per
+    # amplitude of every state a pass reads or writes
+    bytes_per_step = tm["pass_bytes"] / a.steps
+    avg_launch_s = per_step["pass"] / 1000.0 / max(1.0, launches["pass"])
+    per_launch = bytes_per_step / max(1.0, launches["pass"])
+    achieved = per_launch / avg_launch_s / 1e9
+    roofs["pass"] = {"kernel": "k_wpass", "bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": _traffic_from_profile("k_wpass", w.name),
+                     "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": avg_launch_s * 1e6}
+    # assembly: executed MFMA flops (FP32: three real products per complex
+    # one, 6 M N K; split-BF16: twelve BF16 products, 24 M N K) over the GEMM
+    # and split-reduce time
+    t = per_step["gemm"] / 1000.0
+    cplx = tm["gemm_flops"] / a.steps          # 8 M N K, the complex-product count
+    executed = cplx * (0.75 if prec == 0 else 3.0)
+    peak = MFMA_PEAK_TFLOPS[prec]
+    roofs["gemm"] = {"kernel": "k_zgemm_nt_f32" if prec == 0 else "k_zgemm_tn_bf16x3", "bound": "mfma",
+                     "achieved": round(executed / t / 1e12, 2), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(executed / t / 1e12 / peak, 4),
+                     "traffic": _traffic_from_profile("k_zgemm_nt_f32" if prec == 0 else "k_zgemm_tn_bf16x3",
+                                                      w.name),
+                     "complex_8mnk_tflops": round(cplx / t / 1e12, 2),
+                     "note": "executed MFMA flops: 6 M N K (FP32, 3 real products) or 24 M N K (BF16)"}
+    roof = roofs[dominant]
 
     # executed and flat (paper accounting) amp-updates
     oc_gates = [ln.split() for ln in text.splitlines() if ln and ln[0].isdigit()]
@@ -226,6 +234,7 @@ def main() -> int:
         "launches_per_step": launches,
         "setup_s": round(setup_s, 3),
         "roofline": roof,
+        "roofline_by_family": roofs,
         "knobs": knobs or "cost model defaults",
     }
     if tuned:

@@ -688,7 +688,7 @@ hipError_t launch_tail(const TailDesc& h, const TailDesc* d_desc, const DevOp* d
 // three real ones: P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), with
 // Cre = P1 - P2 and Cim = P3 - P1 - P2.
 //
-// FP32 workgroup tile 128 x 64 (4 waves of 64 x 32, each 4 x 2 MFMA tiles of
+// Workgroup tile 128 x 128 (4 waves of 64 x 64, each 4 x 4 MFMA tiles of
 // 16 x 16).  The copy index is split over gridDim.z; each split writes a
 // partial tile and k_zgemm_reduce adds the partials in a fixed order (the
 // result does not depend on scheduling).
@@ -703,6 +703,31 @@ static inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 // workgroup tile is (32 TM) x (32 TN).
 constexpr int kFK = 16;
 constexpr int kFPad = 4;
+// Launch shape, measured at 1024 x 1024 outputs over 16384 copies against
+// 128 x 64 tiles and other split counts: 128 x 128 tiles (255 VGPRs, two
+// waves per SIMD), the split count sized so that every workgroup is resident
+// at once (two per CU), and each XCD running whole splits.
+constexpr int kF32TN = 4;     // MFMA tiles per wave along N: 2 -> 128 x 64, 4 -> 128 x 128
+constexpr int kF32Slots = 2;  // resident workgroups per CU used to size the split count (0: 1024)
+constexpr int kXcdMap = 1;    // 1: the workgroups of one split run on one XCD
+
+// Block coordinates; with kXcdMap the linear workgroup id (dispatched to the
+// eight XCDs round-robin) is remapped so that XCD g runs splits
+// [g nz/8, (g+1) nz/8) and its L2 holds only those splits' copy range.
+__device__ __forceinline__ void gemm_block(int& bx, int& by, int& bz) {
+  bx = blockIdx.x;
+  by = blockIdx.y;
+  bz = blockIdx.z;
+  if (kXcdMap && gridDim.z % 8 == 0) {
+    const int nx = gridDim.x, ny = gridDim.y, nz = gridDim.z;
+    const int bid = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+    const int xcd = bid & 7, loc = bid >> 3, per = nx * ny;
+    bz = xcd * (nz / 8) + loc / per;
+    const int r = loc % per;
+    bx = r % nx;
+    by = r / nx;
+  }
+}
 
 template <int TM, int TN>
 __global__ void __launch_bounds__(kGemmThreads)
@@ -714,9 +739,11 @@ k_zgemm_nt_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int 
   __shared__ float2 Bs[2][kFK][BN + kFPad];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int i_blk = blockIdx.y * BM, j_blk = blockIdx.x * BN;
+  int bx, by, bz;
+  gemm_block(bx, by, bz);
+  const int i_blk = by * BM, j_blk = bx * BN;
   const int wi = (wave >> 1) * (16 * TM), wj = (wave & 1) * (16 * TN);
-  const int kb = blockIdx.z * kper;
+  const int kb = bz * kper;
   const int ke = min(K, kb + kper);
   floatx4 p1[TM][TN], p2[TM][TN], p3[TM][TN];
 #pragma unroll
@@ -783,7 +810,7 @@ k_zgemm_nt_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int 
       buf ^= 1;
     }
   }
-  float2* o = out + (size_t)blockIdx.z * split_stride;
+  float2* o = out + (size_t)bz * split_stride;
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -942,12 +969,11 @@ struct GemmShape {
 // Enough workgroups to fill the 256 compute units a few times over.
 GemmShape gemm_shape(int prec, int M, int N, int K, int kstep) {
   GemmShape g;
-  // FP32: 128 x 64 tiles (measured faster than 128 x 128 and 64 x 64 at
-  // 1024 x 1024 outputs: two waves per SIMD instead of one)
   g.bm = 128;
-  g.bn = prec == 0 ? 64 : 128;
+  g.bn = prec == 0 ? 32 * kF32TN : 128;
   g.tiles = ((M + g.bm - 1) / g.bm) * ((N + g.bn - 1) / g.bn);
-  const int want = std::max(1, 1024 / std::max(1, g.tiles));
+  const int wgs = prec == 0 && kF32Slots > 0 ? 256 * kF32Slots : 1024;
+  const int want = std::max(1, wgs / std::max(1, g.tiles));
   const int maxsplit = std::max(1, K / (4 * kstep));
   g.splits = std::max(1, std::min({want, maxsplit, 64}));
   g.kper = round_up((K + g.splits - 1) / g.splits, kstep);
@@ -978,7 +1004,7 @@ hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int l
   float2* P = (float2*)work;
   dim3 grid((N + g.bn - 1) / g.bn, (M + g.bm - 1) / g.bm, g.splits);
   if (prec == 0) {
-    hipLaunchKernelGGL((k_zgemm_nt_f32<4, 2>), grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper,
+    hipLaunchKernelGGL((k_zgemm_nt_f32<4, kF32TN>), grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper,
                        A, lda, B, ldb, P, N, ss);
   } else {
     const int Mp = round_up(M, kGBM), Np = round_up(N, kGBN);

@@ -294,6 +294,10 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   for (int l = sp.lstar + 1; l <= L; ++l) td.M += (int)tr.levels[l].cuts.size();
   std::vector<DevOp> tops;
   {
+    // the backward rows keep light-cone bits lg..q-1 in registers (lg = min(q, 6)
+    // bits across the lanes of a group): the register split of their DIAG ops
+    std::vector<int> tail_regs;
+    for (int i = std::min(td.q, 6); i < td.q; ++i) tail_regs.push_back(td.Q[i]);
     int shift = td.M;
     for (int l = sp.lstar + 1; l <= L; ++l) {
       TailLevel& tl = td.lev[l - sp.lstar - 1];
@@ -308,7 +312,8 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
       std::vector<int> rev(lv.ops.rbegin(), lv.ops.rend());
       tl.bop0 = (int)(ops.size() + tops.size());
       size_t before = tops.size();
-      if (!encode_ops(s, rev, tr.fixed, work_q, tops, err, true)) return fail(QS_ERR_UNSUPPORTED, err);
+      if (!encode_ops(s, rev, tr.fixed, work_q, tops, err, true, &tail_regs))
+        return fail(QS_ERR_UNSUPPORTED, err);
       tl.bnops = (int)(tops.size() - before);
     }
   }

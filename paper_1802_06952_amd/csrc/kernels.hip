@@ -207,32 +207,28 @@ __device__ __forceinline__ void cut_factors(const int* bq, int m, int b, int upp
 
 constexpr int kWaveThreads = 256;
 
-// v * omega^e, omega = (1+i)/sqrt 2, e mod 8: an optional 45-degree step then a
-// quarter turn.
-__device__ __forceinline__ float2 phase_mul(float2 v, int e) {
-  const float r = 0.70710678118654752f;
-  float a = v.x, b = v.y;
-  if (e & 1) {
-    const float a2 = (a - b) * r, b2 = (a + b) * r;
-    a = a2;
-    b = b2;
+// omega^e for e = 0..7 at entry e, and 0 at entry 8, in LDS: a DIAG op reads
+// its factor at byte offset 8 (e mod 8), or 64 where the projector fails.
+constexpr int kPhaseEntries = 9;
+
+__device__ __forceinline__ void init_phase_table(float2* tab) {
+  if (threadIdx.x == 0) {
+    const float r = 0.70710678118654752f;
+    tab[0] = make_float2(1.f, 0.f);
+    tab[1] = make_float2(r, r);
+    tab[2] = make_float2(0.f, 1.f);
+    tab[3] = make_float2(-r, r);
+    tab[4] = make_float2(-1.f, 0.f);
+    tab[5] = make_float2(-r, -r);
+    tab[6] = make_float2(0.f, -1.f);
+    tab[7] = make_float2(r, -r);
+    tab[8] = make_float2(0.f, 0.f);
   }
-  const int q = (e >> 1) & 3;
-  float xr = (q & 1) ? -b : a;
-  float yr = (q & 1) ? a : b;
-  if (q & 2) {
-    xr = -xr;
-    yr = -yr;
-  }
-  return make_float2(xr, yr);
+  __syncthreads();
 }
 
-__device__ __forceinline__ float2 diag_fast(const DevOp& op, uint32_t x, float2 v) {
-  int e = __popc(x & (uint32_t)op.t0) + 2 * __popc(x & (uint32_t)op.t1) +
-          4 * __popc(x & (uint32_t)op.t2);
-  for (int i = 0; i < op.nd; ++i) e += 4 * __popc(x & (x >> op.d[i]) & (uint32_t)op.M[i]);
-  v = phase_mul(v, e);
-  return ((x & (uint32_t)op.pmask) == (uint32_t)op.pval) ? v : make_float2(0.f, 0.f);
+__device__ __forceinline__ float uniform_f(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
 template <int R>
@@ -244,10 +240,65 @@ __device__ __forceinline__ uint32_t reg_index(int r, const uint32_t (&RB)[R]) {
   return d;
 }
 
+// A DIAG op on the 2^NB registers of a lane: index of register r is
+// F | sum_k r_k RB[k], with F fixed per lane.  The exponent of F is taken
+// once, then each register's by adding one register bit at a time (the
+// register split of the op); it is kept as 8 e, the byte offset of omega^e in
+// the phase table, where a failed projector points at the zero entry.
+template <int NB>
+__device__ __forceinline__ void diag_regs(float2 (&v)[1 << NB], const DevOp& op, uint32_t F,
+                                          const uint32_t (&RB)[NB > 0 ? NB : 1],
+                                          const float2* tab) {
+  constexpr int E = 1 << NB;
+  int eF = __popc(F & (uint32_t)op.t0) + 2 * __popc(F & (uint32_t)op.t1) +
+           4 * __popc(F & (uint32_t)op.t2);
+  for (int i = 0; i < op.nd; ++i) eF += 4 * __popc(F & (F >> op.d[i]) & (uint32_t)op.M[i]);
+  int ex[E];
+  ex[0] = eF << 3;
+  if constexpr (NB > 0) {
+    int wk[NB];
+    uint32_t rr[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      wk[k] = (op.wl[k] + 4 * __popc(F & op.cross[k])) << 3;
+      rr[k] = op.rr[k];
+    }
+#pragma unroll
+    for (int r = 1; r < E; ++r) {
+      const int top = 31 - __builtin_clz((unsigned)r);
+      const int low = r ^ (1 << top);
+      ex[r] = ex[low] + wk[top] + 32 * __popc(rr[top] & (uint32_t)low);
+    }
+  }
+  uint32_t off[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) off[r] = (uint32_t)ex[r] & 56u;
+  if (op.pmask) {
+    // (x & pm) == pv splits into the lane's fixed bits and the register bits,
+    // whose part is the same in every lane
+    const uint32_t pm = (uint32_t)op.pmask, pv = (uint32_t)op.pval;
+    uint32_t rbm = 0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) rbm |= RB[k];
+    const bool lane_ok = (F & pm) == (pv & ~rbm);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      uint32_t ri = 0;
+#pragma unroll
+      for (int k = 0; k < NB; ++k)
+        if ((r >> k) & 1) ri |= RB[k];
+      const bool reg_ok = (ri & pm) == (pv & rbm);
+      if (!(lane_ok && reg_ok)) off[r] = 8u * (kPhaseEntries - 1);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < E; ++r) v[r] = cmul(v[r], *(const float2*)((const char*)tab + off[r]));
+}
+
 template <int R>
 __device__ __forceinline__ void wave_apply_ops(float2 (&v)[1 << R], const DevOp* __restrict__ ops,
                                                int nops, uint32_t F, const uint32_t (&RB)[R],
-                                               int lane) {
+                                               int lane, const float2* tab) {
   constexpr int E = 1 << R;
   for (int o = 0; o < nops; ++o) {
     const DevOp& op = ops[o];
@@ -255,8 +306,11 @@ __device__ __forceinline__ void wave_apply_ops(float2 (&v)[1 << R], const DevOp*
       const int w = op.target;
       if (w < 6) {
         const bool bit = (lane >> w) & 1;
-        const float sr = bit ? op.m[6] : op.m[0], si = bit ? op.m[7] : op.m[1];
-        const float pr = bit ? op.m[4] : op.m[2], pi = bit ? op.m[5] : op.m[3];
+        float m[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) m[i] = uniform_f(op.m[i]);
+        const float sr = bit ? m[6] : m[0], si = bit ? m[7] : m[1];
+        const float pr = bit ? m[4] : m[2], pi = bit ? m[5] : m[3];
 #pragma unroll
         for (int r = 0; r < E; ++r) {
           const float px = __shfl_xor(v[r].x, 1 << w);
@@ -274,34 +328,7 @@ __device__ __forceinline__ void wave_apply_ops(float2 (&v)[1 << R], const DevOp*
         if constexpr (R >= 5) { if (k == 4) tail_mat_reg<E>(v, op.m, 4); }
       }
     } else {
-      // exponent of the lane's fixed bits F, then of each register index by
-      // adding one register bit at a time (see DevOp)
-      int eF = __popc(F & (uint32_t)op.t0) + 2 * __popc(F & (uint32_t)op.t1) +
-               4 * __popc(F & (uint32_t)op.t2);
-      for (int i = 0; i < op.nd; ++i) eF += 4 * __popc(F & (F >> op.d[i]) & (uint32_t)op.M[i]);
-      int wk[R];
-      uint32_t rr[R];
-#pragma unroll
-      for (int k = 0; k < R; ++k) {
-        wk[k] = op.wl[k] + 4 * __popc(F & op.cross[k]);
-        rr[k] = op.rr[k];
-      }
-      int ex[E];
-      ex[0] = eF;
-#pragma unroll
-      for (int r = 1; r < E; ++r) {
-        const int top = 31 - __builtin_clz((unsigned)r);
-        const int low = r ^ (1 << top);
-        ex[r] = ex[low] + wk[top] + 4 * __popc(rr[top] & (uint32_t)low);
-      }
-#pragma unroll
-      for (int r = 0; r < E; ++r) v[r] = phase_mul(v[r], ex[r]);
-      if (op.pmask) {
-        const uint32_t pm = (uint32_t)op.pmask, pv = (uint32_t)op.pval;
-#pragma unroll
-        for (int r = 0; r < E; ++r)
-          if (((F | reg_index<R>(r, RB)) & pm) != pv) v[r] = make_float2(0.f, 0.f);
-      }
+      diag_regs<R>(v, op, F, RB, tab);
     }
   }
 }
@@ -311,6 +338,8 @@ __global__ void __launch_bounds__(kWaveThreads)
 k_wpass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops, const float2* in,
         float2* out, uint64_t total_tiles, const uint32_t* __restrict__ tlist, uint32_t n_list) {
   constexpr int E = 1 << R;
+  __shared__ float2 tab[kPhaseEntries];
+  init_phase_table(tab);
   const PassDesc& P = *pdp;
   const int lane = threadIdx.x & 63;
   const uint64_t wt = (uint64_t)blockIdx.x * (kWaveThreads / 64) + (threadIdx.x >> 6);
@@ -346,7 +375,7 @@ k_wpass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops, const f
 #pragma unroll
     for (int r = 0; r < E; ++r) v[r] = src[F | reg_index<R>(r, RB)];
   }
-  wave_apply_ops<R>(v, ops + P.op_in, P.n_in, F, RB, lane);
+  wave_apply_ops<R>(v, ops + P.op_in, P.n_in, F, RB, lane, tab);
   if (P.m == 0) {
     float2* dst = out + node * N;
 #pragma unroll
@@ -366,7 +395,7 @@ k_wpass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops, const f
       if (__popc(x & zmask) & 1) a = make_float2(-a.x, -a.y);
       w[r] = a;
     }
-    wave_apply_ops<R>(w, ops + P.op_out, P.n_out, F, RB, lane);
+    wave_apply_ops<R>(w, ops + P.op_out, P.n_out, F, RB, lane, tab);
     float2* dst = out + ((node << m) | (uint64_t)b) * N;
 #pragma unroll
     for (int r = 0; r < E; ++r) dst[F | reg_index<R>(r, RB)] = w[r];
@@ -425,12 +454,17 @@ hipError_t launch_pass(const PassDesc& h, const PassDesc* d_desc, const DevOp* d
 
 constexpr int kTailThreads = 256;
 
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
 template <int R>
 struct TailCtx {
+  static constexpr int NB = ilog2(R);
   uint32_t xs[R];
+  uint32_t RB[NB > 0 ? NB : 1];  // state bit of each register bit (light-cone bits lg..q-1)
   int g;       // lane inside the group
   int lg;      // log2 of the group width
   int sub;     // this wavefront's branches of the first reverse levels
+  const float2* tab;  // phase table (LDS)
 };
 
 template <int R>
@@ -442,8 +476,11 @@ __device__ __forceinline__ void tail_apply_ops(float2 (&v)[R], const TailCtx<R>&
       const int w = op.target;
       if (w < c.lg) {
         const bool bit = (c.g >> w) & 1;
-        const float sr = bit ? op.m[6] : op.m[0], si = bit ? op.m[7] : op.m[1];
-        const float pr = bit ? op.m[4] : op.m[2], pi = bit ? op.m[5] : op.m[3];
+        float m[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) m[i] = uniform_f(op.m[i]);
+        const float sr = bit ? m[6] : m[0], si = bit ? m[7] : m[1];
+        const float pr = bit ? m[4] : m[2], pi = bit ? m[5] : m[3];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const float px = __shfl_xor(v[r].x, 1 << w);
@@ -460,8 +497,7 @@ __device__ __forceinline__ void tail_apply_ops(float2 (&v)[R], const TailCtx<R>&
         if constexpr (R >= 16) { if (rb == 3) tail_mat_reg<R>(v, op.m, 3); }
       }
     } else {
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = diag_fast(op, c.xs[r], v[r]);
+      diag_regs<TailCtx<R>::NB>(v, op, c.xs[0], c.RB, c.tab);
     }
   }
 }
@@ -515,6 +551,8 @@ template <int R>
 __global__ void __launch_bounds__(kTailThreads)
 k_tail_bwd(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
            const uint32_t* __restrict__ svals, int s0, int ns, float2* __restrict__ W) {
+  __shared__ float2 tab[kPhaseEntries];
+  init_phase_table(tab);
   const TailDesc& T = *tdp;
   const int lg = T.q < 6 ? T.q : 6;
   const int G = 1 << lg;
@@ -526,6 +564,9 @@ k_tail_bwd(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
   c.g = (int)(gtid & (G - 1));
   c.lg = lg;
   c.sub = (int)(grp & ((1u << T.split_bits) - 1));
+  c.tab = tab;
+#pragma unroll
+  for (int k = 0; k < TailCtx<R>::NB; ++k) c.RB[k] = 1u << T.Q[lg + k];
   const uint32_t s = svals[s0 + gid];
   uint32_t qmask = 0, ys = 0;
   for (int i = 0; i < T.q; ++i) {

@@ -400,6 +400,18 @@ struct DiagAcc {
   void reset() { *this = DiagAcc(); }
 };
 
+// Does the accumulated diagonal act on qubit q?  A 2x2 gate on q commutes
+// with every diagonal factor that does not.
+bool involves(const DiagAcc& a, int q) {
+  if (!a.any) return false;
+  if (a.zero || (a.w[q] & 7) || ((a.pmask >> q) & 1)) return true;
+  for (const auto& kv : a.cz) {
+    if ((kv.second >> q) & 1) return true;
+    if (q >= kv.first && ((kv.second >> (q - kv.first)) & 1)) return true;
+  }
+  return false;
+}
+
 void flush(DiagAcc& a, std::vector<DevOp>& out) {
   if (!a.any) return;
   std::vector<std::pair<int, uint64_t>> dl;
@@ -501,7 +513,9 @@ bool encode_ops(const Side& s, const std::vector<int>& ops, const std::vector<in
     const HOp& o = s.ops[i];
     switch (o.kind) {
       case OP_MAT: {
-        flush(acc, out);
+        // the pending diagonal goes out first only if it touches the gate's
+        // qubit; otherwise the gate is moved ahead of it
+        if (involves(acc, o.q0)) flush(acc, out);
         int w = work_of[o.q0];
         if (w < 0) {
           err = "internal: non-diagonal gate outside the working bits";

@@ -71,7 +71,8 @@ bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, Side
 
 // Encode a sequence of half ops as kernel ops; `work_of` maps a local qubit to
 // the working bit of a MAT op (-1 if the qubit is not a working bit, which is
-// an error for MAT ops).  Diagonal ops between MATs are merged.
+// an error for MAT ops).  Diagonal ops are merged into one DIAG op until a MAT
+// acts on a qubit they touch; MATs on other qubits move ahead of them.
 // transpose = true encodes the transposed operator of the list: the caller
 // passes the ops in reverse order and every 2x2 matrix is transposed.
 // reg_bits (optional): the state bits of a wave-tile pass's register bits, for

@@ -94,6 +94,9 @@ def main() -> int:
     ap.add_argument("--cpu-copies", type=int, default=256)
     ap.add_argument("--autotune", action="store_true",
                     help="time a grid of schedule knobs first and run with the fastest")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="run the two halves one after the other on one stream (as the "
+                         "per-kernel timing does) instead of concurrently")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="after the steps, copy a tensor of this size (for counter calibration)")
     a = ap.parse_args()
@@ -126,7 +129,7 @@ def main() -> int:
         from paper_1802_06952_amd.autotune import autotune
         tuned = autotune(text, w.upper_mask, bits, k0, k1, budget_s=90.0, extra_levels=(4, 5, 6, 7))
         knobs = tuned["opts"]
-    plan = Q.Plan(text, w.upper_mask, **knobs)
+    plan = Q.Plan(text, w.upper_mask, one_stream=a.one_stream, **knobs)
     stream = torch.cuda.current_stream()
     d_out = torch.empty(2 * m, dtype=torch.float32, device="cuda")
     d_sums = torch.zeros(2, dtype=torch.float64, device="cuda")
@@ -153,13 +156,31 @@ def main() -> int:
     ms_per_step = (t1 - t0) * 1000.0 / a.steps
     value = m / (ms_per_step / 1000.0)
 
-    # per-kernel-family device time with HIP events on the launch stream
-    plan.set_timing(True)
-    for _ in range(a.steps):
-        step(prec)
+    # Per-kernel-family device time with HIP events on the launch stream, on a
+    # plan that runs the halves one after the other: every kernel then runs
+    # alone and its average launch time is its own (concurrent halves share
+    # the GPU).  Same kernels and work as the timed region.
+    tplan = Q.Plan(text, w.upper_mask, one_stream=True, **knobs)
+
+    def tstep(p):
+        tplan.reset(keep_bitstrings=True)
+        tplan.run_halves(k0, k1, None, stream)
+        tplan.amplitudes_device(p, d_out.data_ptr(), d_sums.data_ptr(), stream)
+
+    tplan.run_halves(k0, k1, bits, stream)
+    tplan.amplitudes_device(prec, d_out.data_ptr(), d_sums.data_ptr(), stream)
+    for _ in range(a.warmup):
+        tstep(prec)
     torch.cuda.synchronize()
-    tm = plan.timing()
-    plan.set_timing(False)
+    tplan.set_timing(True)
+    ts0 = time.perf_counter()
+    for _ in range(a.steps):
+        tstep(prec)
+    torch.cuda.synchronize()
+    ms_one_stream = (time.perf_counter() - ts0) * 1000.0 / a.steps
+    tm = tplan.timing()
+    tplan.set_timing(False)
+    tplan.close()
     fam_ms = {"pass": tm["pass_ms"], "tail": tm["tail_ms"], "gemm": tm["gemm_ms"], "other": tm["other_ms"]}
     per_step = {k: v / a.steps for k, v in fam_ms.items()}
     launches = {"pass": tm["pass_launches"] / a.steps, "tail": tm["tail_launches"] / a.steps,
@@ -235,6 +256,8 @@ def main() -> int:
         "setup_s": round(setup_s, 3),
         "roofline": roof,
         "roofline_by_family": roofs,
+        "schedule": "halves on one stream" if a.one_stream else "halves on two streams, concurrent",
+        "ms_per_step_one_stream_timed": round(ms_one_stream, 4),
         "knobs": knobs or "cost model defaults",
     }
     if tuned:

@@ -72,6 +72,10 @@ typedef struct {
                              simulated from |0> on its own (no shared prefix), one gate per
                              full-state pass, full leaf states then a gather */
   size_t mem_budget;      /* bytes of device memory the plan may hold for states */
+  int one_stream;         /* 1 = run the two halves one after the other on hip_stream; 0 = the
+                             lower half on a stream of the plan (default priority), ordered
+                             after the work queued on hip_stream by an event and joined back
+                             into hip_stream by another before the assembly */
 } qs_options;
 
 /* Message describing the last failed call on this thread ("" if none). */

@@ -41,7 +41,8 @@ class QSError(RuntimeError):
 
 class qs_options(C.Structure):
     _fields_ = [("tile_bits", C.c_int), ("coalesce_bits", C.c_int), ("tail_max_qubits", C.c_int),
-                ("materialize_level", C.c_int), ("plain", C.c_int), ("mem_budget", C.c_size_t)]
+                ("materialize_level", C.c_int), ("plain", C.c_int), ("mem_budget", C.c_size_t),
+                ("one_stream", C.c_int)]
 
 
 def _load() -> C.CDLL:
@@ -218,10 +219,10 @@ class Plan:
 
     def __init__(self, circuit_text: str, upper_mask: int, tile_bits: int = 0,
                  coalesce_bits: int = 0, tail_max_qubits: int = 0, materialize_level: int = -1,
-                 plain: bool = False, mem_budget: int = 0):
+                 plain: bool = False, mem_budget: int = 0, one_stream: bool = False):
         self._circ = qs_load_circuit(circuit_text)
         opts = qs_options(tile_bits, coalesce_bits, tail_max_qubits, materialize_level,
-                          1 if plain else 0, mem_budget)
+                          1 if plain else 0, mem_budget, 1 if one_stream else 0)
         try:
             self._plan = qs_partition(self._circ, upper_mask, opts)
         except Exception:

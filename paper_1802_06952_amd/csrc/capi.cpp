@@ -29,19 +29,27 @@ qs_status fail(qs_status s, const std::string& m) {
 }
 
 // Device buffers of a plan, recycled between calls of the same size.
+// Device buffers of a plan, reused across calls.  The two halves of a copy
+// block run on two streams; a released buffer is reused only by the stream
+// that released it until settle(), called where the streams are ordered by
+// events, makes every idle buffer usable by either.
 struct Pool {
   struct Ent {
     void* p;
     size_t bytes;
     bool used;
+    bool any;      // idle and usable by either stream
+    void* owner;   // stream that released it
   };
   std::vector<Ent> ents;
   size_t held = 0;
-  void* get(size_t bytes) {
+  void* get(size_t bytes, void* stream) {
     if (bytes == 0) bytes = 256;
     Ent* best = nullptr;
     for (Ent& e : ents)
-      if (!e.used && e.bytes >= bytes && (!best || e.bytes < best->bytes)) best = &e;
+      if (!e.used && (e.any || e.owner == stream) && e.bytes >= bytes &&
+          (!best || e.bytes < best->bytes))
+        best = &e;
     if (best && best->bytes <= 2 * bytes + (1 << 20)) {
       best->used = true;
       return best->p;
@@ -56,15 +64,34 @@ struct Pool {
         return nullptr;
       }
     }
-    ents.push_back(Ent{p, bytes, true});
+    ents.push_back(Ent{p, bytes, true, false, stream});
     held += bytes;
     return p;
   }
-  void put(void* p) {
+  void put(void* p, void* stream) {
     for (Ent& e : ents)
-      if (e.p == p) e.used = false;
+      if (e.p == p) {
+        e.used = false;
+        e.any = false;
+        e.owner = stream;
+      }
+  }
+  // released outside any stream order: reusable after the next settle()
+  void put_unordered(void* p) {
+    for (Ent& e : ents)
+      if (e.p == p) {
+        e.used = false;
+        e.any = false;
+        e.owner = &ents;  // matches no stream
+      }
+  }
+  void settle() {
+    for (Ent& e : ents)
+      if (!e.used) e.any = true;
   }
   void trim() {
+    // idle buffers may still be read by queued kernels
+    (void)hipDeviceSynchronize();
     std::vector<Ent> keep;
     for (Ent& e : ents) {
       if (e.used) keep.push_back(e);
@@ -140,6 +167,9 @@ struct qs_plan {
   // per copy block: device table nu_U -> nu_L and the upper half's nu -> copy
   std::map<std::pair<uint64_t, int>, std::pair<uint32_t*, std::shared_ptr<std::vector<uint32_t>>>>
       perms;
+  // the lower half runs on aux, forked from and joined into the caller's stream
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool timing = false;
   std::vector<EvRec> events;
   double tms[4] = {0, 0, 0, 0};
@@ -154,6 +184,9 @@ struct qs_plan {
     cache.clear();
     for (auto& kv : perms) (void)hipFree(kv.second.first);
     pool.release_all();
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (aux) (void)hipStreamDestroy(aux);
   }
 };
 
@@ -486,15 +519,15 @@ qs_status run_side(qs_plan* P, int sidx, const Prepared& pr, float2* X, hipStrea
       const uint32_t nl = last ? pr.n_list : 0;
       if (pp.init) {
         cur_nodes = 1;
-        cur = (float2*)P->pool.get(SB);
+        cur = (float2*)P->pool.get(SB, st);
         if (!cur) return fail(QS_ERR_OOM, "root state");
       }
       if (pp.branch) {
         const uint64_t on = sp.nodes[pp.level_in + 1];
-        float2* nxt = (float2*)P->pool.get(SB * on);
+        float2* nxt = (float2*)P->pool.get(SB * on, st);
         if (!nxt) return fail(QS_ERR_OOM, "tree level states");
         HIPCHECK(launch_pass(pr.pds[pi], dd, d_ops, cur, nxt, cur_nodes, tl, nl, st));
-        P->pool.put(cur);
+        P->pool.put(cur, st);
         cur = nxt;
         cur_nodes = on;
       } else {
@@ -510,7 +543,7 @@ qs_status run_side(qs_plan* P, int sidx, const Prepared& pr, float2* X, hipStrea
     const size_t per_s = tail_w_bytes(pr.td, 1);
     int chunk = (int)std::max<size_t>(1, ((size_t)512 << 20) / per_s);
     chunk = std::min({chunk, S, 65535});
-    float2* W = (float2*)P->pool.get(per_s * chunk);
+    float2* W = (float2*)P->pool.get(per_s * chunk, st);
     if (!W) return fail(QS_ERR_OOM, "leaf rows");
     for (int s0 = 0; s0 < S; s0 += chunk) {
       const int ns = std::min(chunk, S - s0);
@@ -518,11 +551,11 @@ qs_status run_side(qs_plan* P, int sidx, const Prepared& pr, float2* X, hipStrea
                            (const uint32_t*)(pr.dev + pr.o_sv), s0, ns, W, X, st));
       tm.launches += 2;
     }
-    P->pool.put(W);
+    P->pool.put(W, st);
     if (P->timing) P->tail_flops += pr.tail_flops;
   }
   // later users of these buffers are ordered after the kernels above by the stream
-  P->pool.put(cur);
+  P->pool.put(cur, st);
   return QS_OK;
 }
 
@@ -558,10 +591,13 @@ qs_status register_bits(qs_plan* P, const uint64_t* bits, size_t m) {
   }
   const double prod = (double)vals[0].size() * (double)vals[1].size();
   P->list_mode = prod > 4.0 * (double)m + 1024.0;
+  // every queued kernel is done before buffers change hands here
+  (void)hipDeviceSynchronize();
+  P->pool.settle();
   for (int sidx = 0; sidx < 2; ++sidx) {
     const size_t bytes = vals[sidx].size() * sizeof(uint32_t);
-    uint32_t* dv = (uint32_t*)P->pool.get(bytes);
-    int* di = (int*)P->pool.get(m * sizeof(int));
+    uint32_t* dv = (uint32_t*)P->pool.get(bytes, nullptr);
+    int* di = (int*)P->pool.get(m * sizeof(int), nullptr);
     if (!dv || !di) return fail(QS_ERR_OOM, "value tables");
     HIPCHECK(hipMemcpy(dv, vals[sidx].data(), bytes, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(di, idx[sidx].data(), m * sizeof(int), hipMemcpyHostToDevice));
@@ -584,7 +620,7 @@ qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_s
   const int M = (int)plan->vals[0].size(), N = (int)plan->vals[1].size();
   const size_t m = plan->bits.size();
   const int nb = prob_partial_blocks(m);
-  double* d_part = (double*)plan->pool.get((2 * (size_t)nb + 2) * sizeof(double));
+  double* d_part = (double*)plan->pool.get((2 * (size_t)nb + 2) * sizeof(double), st);
   if (!d_part) return fail(QS_ERR_OOM, "assembly buffers");
   if (plan->list_mode) {
     // the bitstrings are far from a product set: one sum over the copies per
@@ -600,7 +636,7 @@ qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_s
       first = false;
     }
   } else {
-    float2* C = (float2*)plan->pool.get((size_t)M * N * sizeof(float2));
+    float2* C = (float2*)plan->pool.get((size_t)M * N * sizeof(float2), st);
     if (!C) return fail(QS_ERR_OOM, "assembly buffers");
     {
       Timer tm(plan, st, 2);
@@ -608,10 +644,10 @@ qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_s
       for (BlockRes& b : plan->blocks) {
         const int K = (int)(b.k1 - b.k0);
         const size_t wb = zgemm_workspace_bytes((int)prec, M, N, K);
-        void* work = plan->pool.get(wb);
+        void* work = plan->pool.get(wb, st);
         if (!work) return fail(QS_ERR_OOM, "assembly workspace");
         HIPCHECK(launch_zgemm_tn((int)prec, M, N, K, b.X[0], K, b.X[1], K, C, N, first ? 0 : 1, work, st));
-        plan->pool.put(work);
+        plan->pool.put(work, st);
         tm.launches += prec == QS_PREC_FP32 ? 2 : 4;
         if (plan->timing) plan->gemm_flops += 8.0 * M * N * (double)K;
         first = false;
@@ -620,14 +656,14 @@ qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_s
     Timer tm(plan, st, 3);
     HIPCHECK(launch_gather_amps(C, N, plan->d_idx[0], plan->d_idx[1], m, d_amps, st));
     tm.launches += 1;
-    plan->pool.put(C);
+    plan->pool.put(C, st);
   }
   {
     Timer tm(plan, st, 3);
     HIPCHECK(launch_prob_sums(d_amps, m, d_part, d_sums ? d_sums : d_part + 2 * nb, st));
     tm.launches += 2;
   }
-  plan->pool.put(d_part);
+  plan->pool.put(d_part, st);
   return QS_OK;
 }
 
@@ -738,13 +774,13 @@ void qs_plan_free(qs_plan* plan) { delete plan; }
 qs_status qs_plan_reset(qs_plan* plan, int keep_bitstrings) {
   if (!plan) return fail(QS_ERR_ARG, "null plan");
   for (BlockRes& b : plan->blocks)
-    for (int k = 0; k < 2; ++k) plan->pool.put(b.X[k]);
+    for (int k = 0; k < 2; ++k) plan->pool.put_unordered(b.X[k]);
   plan->blocks.clear();
   plan->ranges.clear();
   if (!keep_bitstrings) {
     for (int k = 0; k < 2; ++k) {
-      if (plan->d_vals[k]) plan->pool.put(plan->d_vals[k]);
-      if (plan->d_idx[k]) plan->pool.put(plan->d_idx[k]);
+      if (plan->d_vals[k]) plan->pool.put_unordered(plan->d_vals[k]);
+      if (plan->d_idx[k]) plan->pool.put_unordered(plan->d_idx[k]);
       plan->d_vals[k] = nullptr;
       plan->d_idx[k] = nullptr;
       plan->vals[k].clear();
@@ -803,22 +839,42 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
       pit = plan->perms.emplace(pkey, std::make_pair(d, std::make_shared<std::vector<uint32_t>>(ku))).first;
     }
     br.nu_to_k = pit->second.second;
+    // the halves are independent until the assembly: the upper one runs on
+    // the caller's stream, the lower one on the plan's second stream, forked
+    // after the work already queued on st and joined back before the permute
+    hipStream_t ss[2] = {st, st};
+    if (!plan->opts.one_stream && !plan->opts.plain) {
+      if (!plan->aux) {
+        HIPCHECK(hipStreamCreateWithFlags(&plan->aux, hipStreamNonBlocking));
+        HIPCHECK(hipEventCreateWithFlags(&plan->ev_fork, hipEventDisableTiming));
+        HIPCHECK(hipEventCreateWithFlags(&plan->ev_join, hipEventDisableTiming));
+      }
+      ss[1] = plan->aux;
+      HIPCHECK(hipEventRecord(plan->ev_fork, st));
+      HIPCHECK(hipStreamWaitEvent(plan->aux, plan->ev_fork, 0));
+    }
+    plan->pool.settle();
     for (int sidx = 0; sidx < 2; ++sidx) {
       const size_t bytes = Kb * plan->vals[sidx].size() * sizeof(float2);
-      br.X[sidx] = (float2*)plan->pool.get(bytes);
+      br.X[sidx] = (float2*)plan->pool.get(bytes, ss[sidx]);
       if (!br.X[sidx]) return fail(QS_ERR_OOM, "gathered half amplitudes");
-      s = run_side(plan, sidx, *prs[sidx], br.X[sidx], st);
+      s = run_side(plan, sidx, *prs[sidx], br.X[sidx], ss[sidx]);
       if (s != QS_OK) return s;
     }
+    if (ss[1] != st) {
+      HIPCHECK(hipEventRecord(plan->ev_join, ss[1]));
+      HIPCHECK(hipStreamWaitEvent(st, plan->ev_join, 0));
+    }
+    plan->pool.settle();
     {
       const size_t bytes = Kb * plan->vals[1].size() * sizeof(float2);
-      float2* XL = (float2*)plan->pool.get(bytes);
+      float2* XL = (float2*)plan->pool.get(bytes, st);
       if (!XL) return fail(QS_ERR_OOM, "gathered half amplitudes");
       Timer tm(plan, st, 3);
       HIPCHECK(launch_permute_cols(br.X[1], XL, pit->second.first, (int)plan->vals[1].size(),
                                    (int)Kb, st));
       ++tm.launches;
-      plan->pool.put(br.X[1]);
+      plan->pool.put(br.X[1], st);
       br.X[1] = XL;
     }
     plan->blocks.push_back(br);
@@ -841,8 +897,8 @@ qs_status qs_amplitudes(qs_plan* plan, const uint64_t* bitstrings, size_t m, qs_
     qs_status s = qs_run_halves(plan, 0, 1ULL << plan->cuts.size(), bitstrings, m, hip_stream);
     if (s != QS_OK) return s;
   }
-  float2* amps = (float2*)plan->pool.get(m * sizeof(float2));
-  double* sums = (double*)plan->pool.get(2 * sizeof(double));
+  float2* amps = (float2*)plan->pool.get(m * sizeof(float2), st);
+  double* sums = (double*)plan->pool.get(2 * sizeof(double), st);
   if (!amps || !sums) return fail(QS_ERR_OOM, "output buffers");
   qs_status s = assemble(plan, prec, amps, sums, st);
   if (s != QS_OK) return s;
@@ -856,8 +912,8 @@ qs_status qs_amplitudes(qs_plan* plan, const uint64_t* bitstrings, size_t m, qs_
     out_stats[1] = std::ldexp(h[0] / (double)m, (int)n);
     out_stats[2] = std::ldexp(h[1] / (double)m, (int)(2 * n));
   }
-  plan->pool.put(amps);
-  plan->pool.put(sums);
+  plan->pool.put(amps, st);
+  plan->pool.put(sums, st);
   return QS_OK;
 }
 

@@ -99,6 +99,38 @@ def test_schedule_knobs_same_result(kw):
     assert relerr(amp, ref) < 1e-5
 
 
+def test_two_streams_match_one_stream():
+    """The halves on two streams (the default) give bit-identical amplitudes to
+    the serial order, over repeated runs of one plan (buffers change streams
+    between runs) and several copy blocks."""
+    Q = _lib()
+    import torch
+    w = workload("grid6x6_d16")
+    text = w.circuit_text()
+    bits, _, _ = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
+    say("case one stream")
+    p = Q.Plan(text, w.upper_mask, one_stream=True)
+    total = 1 << p.n_cuts
+    p.run_halves(0, total // 2, bits)
+    p.run_halves(total // 2, total, bits)
+    ref, _ = p.amplitudes(bits)
+    p.close()
+    assert relerr(ref, _golden(w.name)["amp"]) < 1e-5
+    p = Q.Plan(text, w.upper_mask)
+    stream = torch.cuda.Stream()
+    d_out = torch.empty(2 * bits.size, dtype=torch.float32, device="cuda")
+    for rep in range(3):
+        say(f"case two streams, run {rep}")
+        p.reset(keep_bitstrings=rep > 0)
+        p.run_halves(0, total // 2, bits if rep == 0 else None, stream)
+        p.run_halves(total // 2, total, None, stream)
+        p.amplitudes_device(0, d_out.data_ptr(), None, stream)
+        stream.synchronize()
+        got = d_out.cpu().numpy().view(np.complex64)
+        assert np.array_equal(got, ref), rep
+    p.close()
+
+
 def test_copy_slices_partial_sums():
     Q = _lib()
     text = W.random_grid_circuit(4, 4, 12, 5)

@@ -350,14 +350,25 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
       tl.bnops = (int)(tops.size() - before);
     }
   }
-  // copy-index contribution of each leaf path below the materialised level
+  {
+    int acc = 0;
+    for (int l = 0; l < td.nlev; ++l) {
+      td.lev[l].pos = acc;
+      acc += td.lev[l].m;
+    }
+  }
+  td.fused = tail_fused_ok(td) ? 1 : 0;
+  // copy-index contribution of each leaf path below the materialised level,
+  // indexed the way the leaf evaluation writes its output (lam, or the
+  // emission index of the fused kernel)
   pr->leaf_k.assign((size_t)1 << td.M, 0);
   for (size_t lam = 0; lam < pr->leaf_k.size(); ++lam) {
     uint64_t k = 0;
     for (int l = 0; l < td.nlev; ++l) {
       const TailLevel& tl = td.lev[l];
+      const int at = td.fused ? tl.pos : tl.shift;
       for (int i = 0; i < tl.m; ++i)
-        if ((lam >> (tl.shift + tl.m - 1 - i)) & 1) k |= tl.kbit[i];
+        if ((lam >> (at + tl.m - 1 - i)) & 1) k |= tl.kbit[i];
     }
     pr->leaf_k[lam] = k;
   }
@@ -541,17 +552,20 @@ qs_status run_side(qs_plan* P, int sidx, const Prepared& pr, float2* X, hipStrea
     Timer tm(P, st, 1);
     const int S = (int)P->vals[sidx].size();
     const size_t per_s = tail_w_bytes(pr.td, 1);
-    int chunk = (int)std::max<size_t>(1, ((size_t)512 << 20) / per_s);
+    int chunk = pr.td.fused ? S : (int)std::max<size_t>(1, ((size_t)512 << 20) / per_s);
     chunk = std::min({chunk, S, 65535});
-    float2* W = (float2*)P->pool.get(per_s * chunk, st);
-    if (!W) return fail(QS_ERR_OOM, "leaf rows");
+    float2* W = nullptr;  // the fused leaf evaluation keeps its rows on chip
+    if (!pr.td.fused) {
+      W = (float2*)P->pool.get(per_s * chunk, st);
+      if (!W) return fail(QS_ERR_OOM, "leaf rows");
+    }
     for (int s0 = 0; s0 < S; s0 += chunk) {
       const int ns = std::min(chunk, S - s0);
       HIPCHECK(launch_tail(pr.td, (const TailDesc*)(pr.dev + pr.o_td), d_ops, cur,
                            (const uint32_t*)(pr.dev + pr.o_sv), s0, ns, W, X, st));
-      tm.launches += 2;
+      tm.launches += pr.td.fused ? 1 : 2;
     }
-    P->pool.put(W, st);
+    if (W) P->pool.put(W, st);
     if (P->timing) P->tail_flops += pr.tail_flops;
   }
   // later users of these buffers are ordered after the kernels above by the stream

@@ -21,6 +21,10 @@ hipError_t launch_pass(const PassDesc& h_desc, const PassDesc* d_desc, const Dev
 // backward rows into W (tail_w_bytes(h, ns) bytes), then the contraction with
 // the materialised node states into X[k * ldx + s_index].
 size_t tail_w_bytes(const TailDesc& h, int ns);
+// Whether the leaf evaluation of h can run as one fused kernel (rows and
+// contraction of a value in one workgroup; then W is not used and the output
+// leaf paths come in emission order, see TailDesc::fused).
+bool tail_fused_ok(const TailDesc& h);
 hipError_t launch_tail(const TailDesc& h_desc, const TailDesc* d_desc, const DevOp* d_ops,
                        const float2* states, const uint32_t* svals, int s0, int ns, float2* W,
                        float2* X, hipStream_t st);

@@ -687,6 +687,252 @@ k_tail_mm(const TailDesc* __restrict__ tdp, const float2* __restrict__ W,
       }
 }
 
+// k_tail_fused: the rows and the contraction of one requested value s in one
+// workgroup, without the rows passing through HBM.  The 2^M leaf paths are
+// taken in emission order j (the digit of level l at bit pos(l) =
+// sum_{l' < l} m_l'); wave w owns j in [w 2^M/4, (w+1) 2^M/4) and walks it as
+// a depth-first traversal whose stack (u_D: the vector after depth D's ops,
+// before its cut factor) stays in registers, so consecutive paths redo only
+// the levels whose digit changed.  Every chunk of kFusedRows rows (8 per
+// wave) goes to LDS, then the four waves contract it with the materialised
+// node states on FP32 MFMA (three real products per complex one).  The
+// light cone must be on state bits 0..q-1 (x(s, y) = base + y).
+
+constexpr int kFusedRows = 32;
+constexpr int kFusedDepth = 8;
+constexpr int kFusedPadQ = 2;    // complex padding after each quarter of a row
+constexpr int kFusedPadRow = 28; // more padding per row (row stride = 4 mod 32 complex)
+
+__host__ __device__ constexpr int fused_row_stride(int K) {
+  return 4 * (K / 4 + kFusedPadQ) + kFusedPadRow;
+}
+
+// One contraction unit of k_tail_fused: node tile `at` (16 nodes) against
+// NBT column tiles of the chunk starting at tile b0.  Lane group gq = lane/16
+// takes y in [gq K/4, (gq+1) K/4) as the MFMA k index; the node amplitudes
+// come from global memory (L2) in double-buffered batches of 4 x 16 bytes.
+// Nodes past the last one read a valid row and are not written.
+template <int R, int NBT>
+__device__ __forceinline__ void fused_unit(const TailDesc& T, const float2* __restrict__ states,
+                                           uint32_t base, const float2* wl, int at, int b0, int ch,
+                                           uint32_t J4, int si, uint32_t s,
+                                           float2* __restrict__ X) {
+  constexpr int K = 64 * R, KQ = K / 4, RS = fused_row_stride(K);
+  constexpr int TB = KQ / 2 < 4 ? KQ / 2 : 4;  // float4 (two y) per batch
+  constexpr int NBATCH = KQ / 2 / TB;
+  const int lane = threadIdx.x & 63, gq = lane >> 4, li = lane & 15;
+  const int Nn = T.n_nodes, M = T.M, ne = T.n_end;
+  const size_t N = (size_t)1 << T.n;
+  const int node = at * 16 + li;
+  const float4* arow =
+      (const float4*)(states + (size_t)min(node, Nn - 1) * N + base + gq * KQ);
+  const float2* brow[NBT];
+#pragma unroll
+  for (int bb = 0; bb < NBT; ++bb) brow[bb] = wl + ((b0 + bb) * 16 + li) * RS + gq * (KQ + kFusedPadQ);
+  floatx4 p1[NBT], p2[NBT], p3[NBT];
+#pragma unroll
+  for (int bb = 0; bb < NBT; ++bb) {
+    p1[bb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    p2[bb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    p3[bb] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  float4 a0[TB], a1[TB];
+  auto load = [&](float4 (&dst)[TB], int bt) {
+#pragma unroll
+    for (int i = 0; i < TB; ++i) dst[i] = arow[bt * TB + i];
+  };
+  auto mma = [&](const float4 (&src)[TB], int bt) {
+#pragma unroll
+    for (int i = 0; i < TB; ++i) {
+      const float4 av = src[i];
+      const int t = 2 * (bt * TB + i);
+#pragma unroll
+      for (int bb = 0; bb < NBT; ++bb) {
+        const float4 bv = *(const float4*)(brow[bb] + t);
+        p1[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, p1[bb], 0, 0, 0);
+        p2[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, p2[bb], 0, 0, 0);
+        p3[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x + av.y, bv.x + bv.y, p3[bb], 0, 0, 0);
+        p1[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, p1[bb], 0, 0, 0);
+        p2[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, p2[bb], 0, 0, 0);
+        p3[bb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z + av.w, bv.z + bv.w, p3[bb], 0, 0, 0);
+      }
+    }
+  };
+  // batches alternate between a0 and a1: the next batch loads while the
+  // current one feeds the MFMAs
+  // (the scheduling barriers keep each prefetch ahead of the MFMAs it overlaps)
+  // (the last pair prefetches batch 0 again, unused, to keep the loop branch-free)
+  static_assert(NBATCH % 2 == 0, "batches come in pairs");
+  load(a0, 0);
+#pragma unroll 1
+  for (int bt = 0; bt < NBATCH; bt += 2) {
+    load(a1, bt + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a0, bt);
+    __builtin_amdgcn_sched_barrier(0);
+    load(a0, bt + 2 < NBATCH ? bt + 2 : 0);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a1, bt + 1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int bb = 0; bb < NBT; ++bb) {
+    // LDS row col = w * 8 + ci * 4 + st holds path w J4 + ci J4/2 + ch * 4 + st
+    const int col = (b0 + bb) * 16 + li;
+    const uint32_t j = (uint32_t)(col >> 3) * J4 + (uint32_t)((col >> 2) & 1) * (J4 / 2) +
+                       (uint32_t)(ch * 4 + (col & 3));
+#pragma unroll
+    for (int e4 = 0; e4 < 4; ++e4) {
+      const int rn = at * 16 + 4 * gq + e4;
+      if (rn >= Nn) continue;
+      const float re = p1[bb][e4] - p2[bb][e4];
+      const float im = p3[bb][e4] - p1[bb][e4] - p2[bb][e4];
+      float2* dst = X + (size_t)si * T.ldx + ((((size_t)rn << M) + j) << ne);
+      for (int e = 0; e < (1 << ne); ++e) {
+        float2 f = make_float2(re, im);
+        for (int i = 0; i < ne; ++i) {
+          const uint32_t eb = (e >> (ne - 1 - i)) & 1;
+          const uint32_t sb = (s >> T.eq[i]) & 1;
+          if (T.upper) {
+            if (eb != sb) f = make_float2(0.f, 0.f);
+          } else if (eb & sb) {
+            f = make_float2(-f.x, -f.y);
+          }
+        }
+        dst[e] = f;
+      }
+    }
+  }
+}
+
+bool tail_fused_ok(const TailDesc& h) {
+  if (h.q < 6 || h.q > 8 || h.nlev < 1 || h.nlev > kFusedDepth || h.M < 5) return false;
+  for (int i = 0; i < h.q; ++i)
+    if (h.Q[i] != i) return false;
+  return true;
+}
+
+template <int R>
+__global__ void __launch_bounds__(kTailThreads)
+k_tail_fused(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
+             const float2* __restrict__ states, const uint32_t* __restrict__ svals, int s0,
+             float2* __restrict__ X) {
+  constexpr int K = 64 * R, KQ = K / 4;
+  constexpr int RS = fused_row_stride(K);
+  __shared__ __attribute__((aligned(16))) float2 wl[kFusedRows * RS];  // rows of the chunk
+  __shared__ float2 tab[kPhaseEntries];
+  init_phase_table(tab);
+  const TailDesc& T = *tdp;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int si = s0 + blockIdx.x;
+  const uint32_t s = svals[si];
+  const uint32_t qmask = (1u << T.q) - 1u;
+  const uint32_t base = s & ~qmask, ys = s & qmask;
+  // Two traversal chains per wave, over the first and the second half of the
+  // wave's paths, advance in lockstep: they redo the same depths at the same
+  // time, so every op is applied to both at once (the chain index acts as one
+  // more register bit that no op touches: state bit mask 0, no phase terms).
+  constexpr int C = 2, RC = R * C;
+  TailCtx<RC> c;
+  c.g = lane;
+  c.lg = 6;
+  c.sub = 0;
+  c.tab = tab;
+#pragma unroll
+  for (int k = 0; k < TailCtx<RC>::NB; ++k) c.RB[k] = k < TailCtx<R>::NB ? 1u << (6 + k) : 0u;
+#pragma unroll
+  for (int r = 0; r < RC; ++r) c.xs[r] = base | (uint32_t)(lane + 64 * (r % R));
+  const int nlev = T.nlev, M = T.M;
+  const uint32_t J4 = 1u << (M - 2);  // paths per wave
+  const uint32_t JC = J4 / C;         // paths per chain
+  const uint32_t jw = (uint32_t)wave * J4;
+  constexpr int kSteps = kFusedRows / 4 / C;  // steps of a chain per chunk
+  const int nchunks = (int)(JC / kSteps);
+  const int nat = (T.n_nodes + 15) >> 4;
+  float2 u[kFusedDepth][RC];
+  uint32_t jprev = 0;
+  for (int ch = 0; ch < nchunks; ++ch) {
+    // ---- rows of this chunk: wave w, chain ci, step st -> LDS row w * 8 + ci * kSteps + st
+    for (int st = 0; st < kSteps; ++st) {
+      const uint32_t jl = (uint32_t)(ch * kSteps + st);  // path index inside a chain
+      int d0 = -1;  // u[0..d0] still hold
+      if (jl > 0) {
+        // chain offsets are multiples of JC > jl: the changed digits are jl's
+        const int hb = 31 - __builtin_clz(jl ^ jprev);
+        int lh = 0;
+        while (lh + 1 < nlev && T.lev[lh + 1].pos <= hb) ++lh;
+        d0 = nlev - 1 - lh;
+      }
+      jprev = jl;
+      float2 v[RC];
+#pragma unroll
+      for (int D = 0; D < kFusedDepth; ++D) {
+        if (D < nlev) {
+          const int l = nlev - 1 - D;
+          if (D > d0) {
+            if (D == 0) {
+#pragma unroll
+              for (int r = 0; r < RC; ++r)
+                v[r] = ((uint32_t)(lane + 64 * (r % R)) == ys) ? make_float2(1.f, 0.f)
+                                                                : make_float2(0.f, 0.f);
+            } else {
+              const TailLevel& L = T.lev[l + 1];
+#pragma unroll
+              for (int ci = 0; ci < C; ++ci) {
+                const uint32_t j = jw + (uint32_t)ci * JC + jl;
+                const int b = (int)((j >> L.pos) & ((1u << L.m) - 1u));
+                uint32_t cmask, cval, zmask;
+                cut_factors(L.bq, L.m, b, T.upper, cmask, cval, zmask);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                  float2 a = u[D - 1][ci * R + r];
+                  if ((c.xs[r] & cmask) != cval) a = make_float2(0.f, 0.f);
+                  if (__popc(c.xs[r] & zmask) & 1) a = make_float2(-a.x, -a.y);
+                  v[ci * R + r] = a;
+                }
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < RC; ++r) u[D][r] = v[r];
+            tail_apply_ops<RC>(u[D], c, ops + T.lev[l].bop0, T.lev[l].bnops);
+          }
+          if (D == nlev - 1) {
+            const TailLevel& L = T.lev[0];
+#pragma unroll
+            for (int ci = 0; ci < C; ++ci) {
+              const uint32_t j = jw + (uint32_t)ci * JC + jl;
+              const int b = (int)((j >> L.pos) & ((1u << L.m) - 1u));
+              uint32_t cmask, cval, zmask;
+              cut_factors(L.bq, L.m, b, T.upper, cmask, cval, zmask);
+              float2* row = wl + (wave * (kFusedRows / 4) + ci * kSteps + st) * RS;
+#pragma unroll
+              for (int r = 0; r < R; ++r) {
+                float2 a = u[D][ci * R + r];
+                if ((c.xs[r] & cmask) != cval) a = make_float2(0.f, 0.f);
+                if (__popc(c.xs[r] & zmask) & 1) a = make_float2(-a.x, -a.y);
+                const int y = lane + 64 * r;
+                row[(y / KQ) * (KQ + kFusedPadQ) + (y % KQ)] = a;
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- contraction: C[node][col] = sum_y v_node[base + y] W[col][y]; a unit
+    // is one 16-node tile with both 16-column tiles (or one, when there are
+    // fewer than four node tiles)
+    if (nat >= 4) {
+      for (int un = wave; un < nat; un += 4)
+        fused_unit<R, 2>(T, states, base, wl, un, 0, ch, J4, si, s, X);
+    } else {
+      for (int un = wave; un < 2 * nat; un += 4)
+        fused_unit<R, 1>(T, states, base, wl, un >> 1, un & 1, ch, J4, si, s, X);
+    }
+    __syncthreads();
+  }
+}
+
 size_t tail_w_bytes(const TailDesc& h, int ns) {
   return (size_t)ns * ((size_t)1 << h.M) * ((size_t)1 << h.q) * sizeof(float2);
 }
@@ -695,6 +941,24 @@ hipError_t launch_tail(const TailDesc& h, const TailDesc* d_desc, const DevOp* d
                        const float2* states, const uint32_t* svals, int s0, int ns, float2* W,
                        float2* X, hipStream_t st) {
   if (ns <= 0) return hipSuccess;
+  if (h.fused) {
+    const int R = 1 << (h.q - 6);
+    if (!tail_fused_ok(h)) return hipErrorInvalidValue;
+    dim3 g((unsigned)ns), b(kTailThreads);
+    switch (R) {
+      case 1:
+        hipLaunchKernelGGL(k_tail_fused<1>, g, b, 0, st, d_desc, d_ops, states, svals, s0, X);
+        break;
+      case 2:
+        hipLaunchKernelGGL(k_tail_fused<2>, g, b, 0, st, d_desc, d_ops, states, svals, s0, X);
+        break;
+      case 4:
+        hipLaunchKernelGGL(k_tail_fused<4>, g, b, 0, st, d_desc, d_ops, states, svals, s0, X);
+        break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   const int lg = h.q < 6 ? h.q : 6;
   const uint64_t threads = ((uint64_t)ns << h.split_bits) << lg;
   const uint64_t blocks = (threads + kTailThreads - 1) / kTailThreads;

@@ -124,6 +124,7 @@ struct TailLevel {
   int bq[kMaxBranch];    // state bit of each cut qubit (bit 0 = MSB of b)
   int bop0, bnops;       // the level's ops reversed, MATs transposed (targets are Q indices)
   int shift;             // position of the level's branch bits in the leaf index
+  int pos;               // position of the level's branch bits in the emission index
   uint64_t kbit[kMaxBranch];  // copy-index contribution of each branch bit
 };
 
@@ -153,6 +154,10 @@ struct TailDesc {
   int n_nodes;          // materialised nodes
   int S;                // requested values
   int ldx;              // leading dimension (row stride) of the output X[k][s]
+  // 1: rows and contraction fused in one kernel; the leaf paths of the output
+  // then come in emission order j (the digit of level l at bit sum_{l'<l} m_l')
+  // instead of lam (the digit of level l at bit lev[l].shift)
+  int fused;
 };
 
 }  // namespace qs

@@ -192,9 +192,9 @@ def main() -> int:
     t = per_step["tail"] / 1000.0
     if t > 0:
         achieved = tm["tail_flops"] / a.steps / t / 1e12
-        roofs["tail"] = {"kernel": "k_tail_bwd + k_tail_mm", "bound": "alu", "achieved": round(achieved, 3),
+        roofs["tail"] = {"kernel": "k_tail_fused", "bound": "alu", "achieved": round(achieved, 3),
                          "peak": 157.3, "unit": "TFLOP/s", "frac": round(achieved / 157.3, 4),
-                         "traffic": _traffic_from_profile("k_tail_bwd", w.name),
+                         "traffic": _traffic_from_profile("k_tail_fused", w.name),
                          "note": "14 flops per amplitude per 2x2 gate on the light-cone rows, "
                                  "8 per complex multiply-add in the per-value contraction"}
     # layer and branch passes: algorithmic bytes = 8 B read + 8 B written per
@@ -277,7 +277,7 @@ def main() -> int:
         torch.cuda.synchronize()
 
     # host-API rate: bitstrings from host memory, amplitudes back to host memory
-    hp = Q.Plan(text, w.upper_mask)
+    hp = Q.Plan(text, w.upper_mask, one_stream=a.one_stream)
     hp.run_halves(k0, k1, bits)
     hp.amplitudes(bits, prec)
     th0 = time.perf_counter()

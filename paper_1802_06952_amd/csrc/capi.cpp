@@ -875,22 +875,24 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
       s = run_side(plan, sidx, *prs[sidx], br.X[sidx], ss[sidx]);
       if (s != QS_OK) return s;
     }
+    {
+      // the lower half's columns onto the upper half's copy order, still on
+      // the lower half's stream
+      const size_t bytes = Kb * plan->vals[1].size() * sizeof(float2);
+      float2* XL = (float2*)plan->pool.get(bytes, ss[1]);
+      if (!XL) return fail(QS_ERR_OOM, "gathered half amplitudes");
+      Timer tm(plan, ss[1], 3);
+      HIPCHECK(launch_permute_cols(br.X[1], XL, pit->second.first, (int)plan->vals[1].size(),
+                                   (int)Kb, ss[1]));
+      ++tm.launches;
+      plan->pool.put(br.X[1], ss[1]);
+      br.X[1] = XL;
+    }
     if (ss[1] != st) {
       HIPCHECK(hipEventRecord(plan->ev_join, ss[1]));
       HIPCHECK(hipStreamWaitEvent(st, plan->ev_join, 0));
     }
     plan->pool.settle();
-    {
-      const size_t bytes = Kb * plan->vals[1].size() * sizeof(float2);
-      float2* XL = (float2*)plan->pool.get(bytes, st);
-      if (!XL) return fail(QS_ERR_OOM, "gathered half amplitudes");
-      Timer tm(plan, st, 3);
-      HIPCHECK(launch_permute_cols(br.X[1], XL, pit->second.first, (int)plan->vals[1].size(),
-                                   (int)Kb, st));
-      ++tm.launches;
-      plan->pool.put(br.X[1], st);
-      br.X[1] = XL;
-    }
     plan->blocks.push_back(br);
     k = br.k1;
   }

@@ -1442,15 +1442,30 @@ k_prob_partial(const float2* __restrict__ amps, size_t m, double* __restrict__ p
   }
 }
 
-__global__ void k_prob_final(const double* __restrict__ partial, int nb, double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One workgroup: thread t sums partials t, t + 256, ... in order, then a
+// fixed tree over the threads (the order does not depend on scheduling).
+__global__ void __launch_bounds__(kProbThreads)
+k_prob_final(const double* __restrict__ partial, int nb, double* __restrict__ out) {
+  __shared__ double s1[kProbThreads], s2[kProbThreads];
   double a1 = 0, a2 = 0;
-  for (int b = 0; b < nb; ++b) {
+  for (int b = threadIdx.x; b < nb; b += kProbThreads) {
     a1 += partial[2 * b];
     a2 += partial[2 * b + 1];
   }
-  out[0] = a1;
-  out[1] = a2;
+  s1[threadIdx.x] = a1;
+  s2[threadIdx.x] = a2;
+  __syncthreads();
+  for (int w = kProbThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = s1[0];
+    out[1] = s2[0];
+  }
 }
 
 hipError_t launch_prob_sums(const float2* amps, size_t m, double* partial, double* out,
@@ -1458,7 +1473,7 @@ hipError_t launch_prob_sums(const float2* amps, size_t m, double* partial, doubl
   const int nb = prob_partial_blocks(m);
   if (nb == 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_prob_partial, dim3(nb), dim3(kProbThreads), 0, st, amps, m, partial);
-  hipLaunchKernelGGL(k_prob_final, dim3(1), dim3(64), 0, st, partial, nb, out);
+  hipLaunchKernelGGL(k_prob_final, dim3(1), dim3(kProbThreads), 0, st, partial, nb, out);
   return hipGetLastError();
 }
 

@@ -116,6 +116,17 @@ struct BlockRes {
   // permuted onto it), so both sides share the contraction index
   float2* X[2] = {nullptr, nullptr};
   std::shared_ptr<std::vector<uint32_t>> nu_to_k;  // copy (block-local) of each nu
+  // Lower end cuts folded into the upper operand (ne > 0): Ut[sig][s][nu'] is
+  // X[0] transformed over the end bits (positions pos[] of nu), X[1] holds
+  // only the lower copies with end bits 0, as rows sorted by sig with columns
+  // nu' (nu without the end bits); rows goff[sig] .. goff[sig+1] - 1 of X[1]
+  // are the lower values d_rows[...] (original value indices).
+  int ne = 0;
+  int pos[4] = {0, 0, 0, 0};
+  float2* Ut = nullptr;
+  const uint32_t* d_rows = nullptr;
+  std::vector<int> goff;
+  std::shared_ptr<std::vector<uint32_t>> rows, sig;  // host copies (value order, sig per value)
 };
 
 }  // namespace
@@ -132,6 +143,11 @@ struct Prepared {
   char* dev = nullptr;  // descriptors, tail desc, ops, node copy indices (owned)
   size_t o_pd = 0, o_td = 0, o_ops = 0, o_nk = 0, o_lk = 0, o_sv = 0, o_tl = 0;
   uint32_t n_list = 0;  // tiles of the last pass that the leaf evaluation reads (0 = all)
+  // lower half with end_base: the end-cut bits sig of every requested value,
+  // the values sorted by sig (rows) and the group starts (goff); d_rows in the blob
+  std::shared_ptr<std::vector<uint32_t>> sig, rows;
+  std::vector<int> goff;
+  size_t o_rows = 0;
   std::vector<uint64_t> leaf_k;
   std::vector<uint32_t> nu_to_k;  // block-local copy index of each natural position nu
   double pass_bytes = 0;  // algorithmic bytes of the passes
@@ -139,6 +155,17 @@ struct Prepared {
   ~Prepared() {
     if (dev) (void)hipFree(dev);
   }
+};
+
+// Per copy block: device table nu_U -> nu_L and the upper half's nu -> copy;
+// with lower end cuts folded into the assembly, also their positions in the
+// upper half's copy order and the table nu' -> nu0_L.
+struct BlockMaps {
+  uint32_t* d_perm = nullptr;
+  std::shared_ptr<std::vector<uint32_t>> nu_to_k;
+  int ne = 0;
+  int pos[4] = {0, 0, 0, 0};
+  uint32_t* d_colsel = nullptr;
 };
 
 struct EvRec {
@@ -165,8 +192,7 @@ struct qs_plan {
   std::vector<std::pair<uint64_t, uint64_t>> ranges;
   std::map<std::tuple<int, uint64_t, int>, std::unique_ptr<Prepared>> cache;
   // per copy block: device table nu_U -> nu_L and the upper half's nu -> copy
-  std::map<std::pair<uint64_t, int>, std::pair<uint32_t*, std::shared_ptr<std::vector<uint32_t>>>>
-      perms;
+  std::map<std::pair<uint64_t, int>, BlockMaps> perms;
   // the lower half runs on aux, forked from and joined into the caller's stream
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -182,7 +208,10 @@ struct qs_plan {
       (void)hipEventDestroy(e.b);
     }
     cache.clear();
-    for (auto& kv : perms) (void)hipFree(kv.second.first);
+    for (auto& kv : perms) {
+      (void)hipFree(kv.second.d_perm);
+      if (kv.second.d_colsel) (void)hipFree(kv.second.d_colsel);
+    }
     pool.release_all();
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
@@ -404,6 +433,13 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   td.n_nodes = (int)sp.nodes[sp.lstar];
   td.S = S;
   td.ldx = 1 << (c - blk.p);  // row stride of X[s][nu]: the block's copies
+  // lower half, product-set assembly: write only the copies with end bits 0
+  // (the assembly folds the end cuts' signs into the upper operand)
+  td.end_base = (!s.upper && !P->list_mode && !P->opts.plain && td.n_end >= 1 && td.n_end <= 4 &&
+                 (td.ldx >> td.n_end) >= 1)
+                    ? 1
+                    : 0;
+  if (td.end_base) td.ldx >>= td.n_end;
   ops.insert(ops.end(), tops.begin(), tops.end());
   // copy-index contribution of each materialised node
   std::vector<int> ncuts;
@@ -447,6 +483,27 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
     sv[i] = w;
   }
   const size_t b_sv = (size_t)S * sizeof(uint32_t);
+  std::vector<uint32_t> rows_v;
+  if (td.end_base) {
+    auto sig = std::make_shared<std::vector<uint32_t>>(S);
+    for (int i = 0; i < S; ++i) {
+      uint32_t g = 0;
+      for (int e = 0; e < td.n_end; ++e) g |= ((sv[i] >> td.eq[e]) & 1u) << e;
+      (*sig)[i] = g;
+    }
+    rows_v.resize(S);
+    for (int i = 0; i < S; ++i) rows_v[i] = (uint32_t)i;
+    std::stable_sort(rows_v.begin(), rows_v.end(),
+                     [&](uint32_t a, uint32_t b) { return (*sig)[a] < (*sig)[b]; });
+    pr->goff.assign((1 << td.n_end) + 1, 0);
+    for (int i = 0; i < S; ++i) ++pr->goff[(*sig)[i] + 1];
+    for (int g = 0; g < (1 << td.n_end); ++g) pr->goff[g + 1] += pr->goff[g];
+    pr->sig = sig;
+    pr->rows = std::make_shared<std::vector<uint32_t>>(rows_v);
+  }
+  if (td.end_base)
+    for (int g : pr->goff) rows_v.push_back((uint32_t)g);  // the group starts follow the rows
+  const size_t b_rows = rows_v.size() * sizeof(uint32_t);
   // The leaf evaluation reads the last materialised states only at the
   // requested values with their light-cone bits free, so the last pass need
   // only produce the tiles whose outer bits agree with some requested value
@@ -483,8 +540,8 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   pr->n_list = (uint32_t)tl.size();
   const size_t b_tl = tl.size() * sizeof(uint32_t);
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t total =
-      al(b_pd) + al(b_td) + al(b_ops) + al(b_nk) + al(b_lk) + al(b_sv) + al(b_tl);
+  const size_t total = al(b_pd) + al(b_td) + al(b_ops) + al(b_nk) + al(b_lk) + al(b_sv) +
+                       al(b_tl) + al(b_rows);
   std::vector<char> host(total, 0);
   pr->o_pd = 0;
   pr->o_td = al(b_pd);
@@ -493,6 +550,7 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   pr->o_lk = pr->o_nk + al(b_nk);
   pr->o_sv = pr->o_lk + al(b_lk);
   pr->o_tl = pr->o_sv + al(b_sv);
+  pr->o_rows = pr->o_tl + al(b_tl);
   if (b_pd) std::memcpy(host.data() + pr->o_pd, pr->pds.data(), b_pd);
   std::memcpy(host.data() + pr->o_td, &td, b_td);
   if (!ops.empty()) std::memcpy(host.data() + pr->o_ops, ops.data(), ops.size() * sizeof(DevOp));
@@ -500,6 +558,7 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   std::memcpy(host.data() + pr->o_lk, pr->leaf_k.data(), b_lk);
   std::memcpy(host.data() + pr->o_sv, sv.data(), b_sv);
   if (b_tl) std::memcpy(host.data() + pr->o_tl, tl.data(), b_tl);
+  if (b_rows) std::memcpy(host.data() + pr->o_rows, rows_v.data(), b_rows);
   if (hipMalloc(&pr->dev, total) != hipSuccess) {
     (void)hipGetLastError();
     pr->dev = nullptr;
@@ -621,9 +680,15 @@ qs_status register_bits(qs_plan* P, const uint64_t* bits, size_t m) {
     P->idx[sidx] = std::move(idx[sidx]);
   }
   P->bits.assign(bits, bits + m);
-  // a new value set changes the leaf evaluation: drop cached block plans
+  // a new value set changes the leaf evaluation (and, through the cost model,
+  // possibly the trees): drop cached block plans and copy tables
   (void)hipDeviceSynchronize();
   P->cache.clear();
+  for (auto& kv : P->perms) {
+    (void)hipFree(kv.second.d_perm);
+    if (kv.second.d_colsel) (void)hipFree(kv.second.d_colsel);
+  }
+  P->perms.clear();
   P->registered = true;
   return QS_OK;
 }
@@ -657,13 +722,48 @@ qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_s
       bool first = true;
       for (BlockRes& b : plan->blocks) {
         const int K = (int)(b.k1 - b.k0);
-        const size_t wb = zgemm_workspace_bytes((int)prec, M, N, K);
-        void* work = plan->pool.get(wb, st);
-        if (!work) return fail(QS_ERR_OOM, "assembly workspace");
-        HIPCHECK(launch_zgemm_tn((int)prec, M, N, K, b.X[0], K, b.X[1], K, C, N, first ? 0 : 1, work, st));
-        plan->pool.put(work, st);
-        tm.launches += prec == QS_PREC_FP32 ? 2 : 4;
-        if (plan->timing) plan->gemm_flops += 8.0 * M * N * (double)K;
+        if (b.ne > 0 && prec == QS_PREC_FP32) {
+          // one product per end-cut pattern sig over K >> ne copies (the
+          // transformed upper operand for sig against the lower values with
+          // that pattern, scattered to their columns of C), all in one launch
+          const int K0 = K >> b.ne, ng = 1 << b.ne;
+          int maxn = 1;
+          for (int g = 0; g < ng; ++g) maxn = std::max(maxn, b.goff[g + 1] - b.goff[g]);
+          const size_t wb = zgemm_grouped_workspace_bytes(M, N, maxn, K0, ng);
+          void* work = plan->pool.get(wb, st);
+          if (!work) return fail(QS_ERR_OOM, "assembly workspace");
+          HIPCHECK(launch_zgemm_grouped(M, N, maxn, K0, ng, (const int*)(b.d_rows + N), b.Ut,
+                                        (size_t)M * K0, b.X[1], C, N, first ? 0 : 1, work, st,
+                                        b.d_rows));
+          plan->pool.put(work, st);
+          tm.launches += 2;
+          if (plan->timing) plan->gemm_flops += 8.0 * M * N * (double)K0;
+        } else if (b.ne > 0) {
+          // split-BF16: one product per end-cut pattern
+          const int K0 = K >> b.ne;
+          const size_t wb = zgemm_workspace_bytes((int)prec, M, N, K0);
+          void* work = plan->pool.get(wb, st);
+          if (!work) return fail(QS_ERR_OOM, "assembly workspace");
+          for (int g = 0; g < (1 << b.ne); ++g) {
+            const int ng = b.goff[g + 1] - b.goff[g];
+            if (ng == 0) continue;
+            HIPCHECK(launch_zgemm_tn((int)prec, M, ng, K0, b.Ut + (size_t)g * M * K0, K0,
+                                     b.X[1] + (size_t)b.goff[g] * K0, K0, C, N, first ? 0 : 1,
+                                     work, st, b.d_rows + b.goff[g]));
+            tm.launches += prec == QS_PREC_FP32 ? 2 : 4;
+            if (plan->timing) plan->gemm_flops += 8.0 * M * ng * (double)K0;
+          }
+          plan->pool.put(work, st);
+        } else {
+          const size_t wb = zgemm_workspace_bytes((int)prec, M, N, K);
+          void* work = plan->pool.get(wb, st);
+          if (!work) return fail(QS_ERR_OOM, "assembly workspace");
+          HIPCHECK(launch_zgemm_tn((int)prec, M, N, K, b.X[0], K, b.X[1], K, C, N, first ? 0 : 1,
+                                   work, st));
+          plan->pool.put(work, st);
+          tm.launches += prec == QS_PREC_FP32 ? 2 : 4;
+          if (plan->timing) plan->gemm_flops += 8.0 * M * N * (double)K;
+        }
         first = false;
       }
     }
@@ -787,8 +887,11 @@ void qs_plan_free(qs_plan* plan) { delete plan; }
 
 qs_status qs_plan_reset(qs_plan* plan, int keep_bitstrings) {
   if (!plan) return fail(QS_ERR_ARG, "null plan");
-  for (BlockRes& b : plan->blocks)
+  for (BlockRes& b : plan->blocks) {
     for (int k = 0; k < 2; ++k) plan->pool.put_unordered(b.X[k]);
+    if (b.Ut) plan->pool.put_unordered(b.Ut);
+    if (b.d_rows) plan->pool.put_unordered((void*)b.d_rows);
+  }
   plan->blocks.clear();
   plan->ranges.clear();
   if (!keep_bitstrings) {
@@ -844,15 +947,45 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
       std::vector<uint32_t> inv(Kb), perm(Kb);
       for (uint64_t nu = 0; nu < Kb; ++nu) inv[kl[nu]] = (uint32_t)nu;
       for (uint64_t nu = 0; nu < Kb; ++nu) perm[nu] = inv[ku[nu]];
-      uint32_t* d = nullptr;
-      if (hipMalloc(&d, Kb * sizeof(uint32_t)) != hipSuccess) {
+      BlockMaps bm;
+      if (hipMalloc(&bm.d_perm, Kb * sizeof(uint32_t)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(QS_ERR_OOM, "copy permutation");
       }
-      HIPCHECK(hipMemcpy(d, perm.data(), Kb * sizeof(uint32_t), hipMemcpyHostToDevice));
-      pit = plan->perms.emplace(pkey, std::make_pair(d, std::make_shared<std::vector<uint32_t>>(ku))).first;
+      HIPCHECK(hipMemcpy(bm.d_perm, perm.data(), Kb * sizeof(uint32_t), hipMemcpyHostToDevice));
+      bm.nu_to_k = std::make_shared<std::vector<uint32_t>>(ku);
+      const TailDesc& tl = prs[1]->td;
+      if (tl.end_base) {
+        // nu_U -> copy is linear in the bits of nu: find the bit of each lower
+        // end cut, then nu' (nu without those bits) -> the lower copy with end bits 0
+        bm.ne = tl.n_end;
+        for (int i = 0; i < bm.ne; ++i) {
+          bm.pos[i] = -1;
+          for (int b = 0; (1ULL << b) < Kb; ++b)
+            if ((uint64_t)ku[(size_t)1 << b] == tl.ekbit[i]) bm.pos[i] = b;
+          if (bm.pos[i] < 0) return fail(QS_ERR_UNSUPPORTED, "internal: end cut outside the copy order");
+        }
+        std::vector<int> asc(bm.pos, bm.pos + bm.ne);
+        std::sort(asc.begin(), asc.end());
+        const uint64_t K0 = Kb >> bm.ne;
+        std::vector<uint32_t> colsel(K0);
+        for (uint64_t v = 0; v < K0; ++v) {
+          uint64_t nu = v;
+          for (int p : asc) nu = ((nu >> p) << (p + 1)) | (nu & ((1ULL << p) - 1));
+          const uint32_t nl = inv[ku[nu]];
+          if (nl & ((1u << bm.ne) - 1)) return fail(QS_ERR_UNSUPPORTED, "internal: end bits do not match");
+          colsel[v] = nl >> bm.ne;
+        }
+        if (hipMalloc(&bm.d_colsel, K0 * sizeof(uint32_t)) != hipSuccess) {
+          (void)hipGetLastError();
+          return fail(QS_ERR_OOM, "copy permutation");
+        }
+        HIPCHECK(hipMemcpy(bm.d_colsel, colsel.data(), K0 * sizeof(uint32_t), hipMemcpyHostToDevice));
+      }
+      pit = plan->perms.emplace(pkey, bm).first;
     }
-    br.nu_to_k = pit->second.second;
+    br.nu_to_k = pit->second.nu_to_k;
+    const BlockMaps& bmap = pit->second;
     // the halves are independent until the assembly: the upper one runs on
     // the caller's stream, the lower one on the plan's second stream, forked
     // after the work already queued on st and joined back before the permute
@@ -868,8 +1001,11 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
       HIPCHECK(hipStreamWaitEvent(plan->aux, plan->ev_fork, 0));
     }
     plan->pool.settle();
+    const int ne = bmap.ne;
+    const uint64_t K0 = Kb >> ne;
+    const int NL = (int)plan->vals[1].size();
     for (int sidx = 0; sidx < 2; ++sidx) {
-      const size_t bytes = Kb * plan->vals[sidx].size() * sizeof(float2);
+      const size_t bytes = (sidx == 1 ? K0 : Kb) * plan->vals[sidx].size() * sizeof(float2);
       br.X[sidx] = (float2*)plan->pool.get(bytes, ss[sidx]);
       if (!br.X[sidx]) return fail(QS_ERR_OOM, "gathered half amplitudes");
       s = run_side(plan, sidx, *prs[sidx], br.X[sidx], ss[sidx]);
@@ -877,16 +1013,41 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
     }
     {
       // the lower half's columns onto the upper half's copy order, still on
-      // the lower half's stream
-      const size_t bytes = Kb * plan->vals[1].size() * sizeof(float2);
+      // the lower half's stream (with folded end cuts: rows sorted by their
+      // end-cut bits, columns nu')
+      const size_t bytes = K0 * NL * sizeof(float2);
       float2* XL = (float2*)plan->pool.get(bytes, ss[1]);
       if (!XL) return fail(QS_ERR_OOM, "gathered half amplitudes");
       Timer tm(plan, ss[1], 3);
-      HIPCHECK(launch_permute_cols(br.X[1], XL, pit->second.first, (int)plan->vals[1].size(),
-                                   (int)Kb, ss[1]));
+      if (ne > 0) {
+        const size_t nr = (size_t)NL + (1u << ne) + 1;  // rows, then group starts
+        uint32_t* dr = (uint32_t*)plan->pool.get(nr * sizeof(uint32_t), ss[1]);
+        if (!dr) return fail(QS_ERR_OOM, "row order");
+        HIPCHECK(hipMemcpyAsync(dr, prs[1]->dev + prs[1]->o_rows, nr * sizeof(uint32_t),
+                                hipMemcpyDeviceToDevice, ss[1]));
+        HIPCHECK(launch_gather_rows_cols(br.X[1], XL, dr, bmap.d_colsel, NL, (int)K0, (int)K0,
+                                         ss[1]));
+        br.d_rows = dr;
+        br.ne = ne;
+        for (int i = 0; i < ne; ++i) br.pos[i] = bmap.pos[i];
+        br.goff = prs[1]->goff;
+        br.rows = prs[1]->rows;
+        br.sig = prs[1]->sig;
+      } else {
+        HIPCHECK(launch_permute_cols(br.X[1], XL, bmap.d_perm, NL, (int)Kb, ss[1]));
+      }
       ++tm.launches;
       plan->pool.put(br.X[1], ss[1]);
       br.X[1] = XL;
+    }
+    if (ne > 0) {
+      // the upper operand transformed over the lower end cuts' bits
+      const int MU = (int)plan->vals[0].size();
+      br.Ut = (float2*)plan->pool.get(Kb * MU * sizeof(float2), st);
+      if (!br.Ut) return fail(QS_ERR_OOM, "transformed upper amplitudes");
+      Timer tm(plan, st, 3);
+      HIPCHECK(launch_end_wht(br.X[0], MU, (int)Kb, ne, br.pos, br.Ut, st));
+      ++tm.launches;
     }
     if (ss[1] != st) {
       HIPCHECK(hipEventRecord(plan->ev_join, ss[1]));
@@ -954,12 +1115,43 @@ qs_status qs_half_amplitudes(qs_plan* plan, int side, uint64_t copy_begin, uint6
   if (cap < cnt) return fail(QS_ERR_ARG, "output capacity too small");
   hipStream_t st = (hipStream_t)hip_stream;
   const size_t Kb = (size_t)(copy_end - copy_begin);
+  const std::vector<uint32_t>& nk = *hit->nu_to_k;
+  float2* o = (float2*)out_c64;
+  if (side == 1 && hit->ne > 0) {
+    // stored: rows sorted by end-cut pattern, the copies with end bits 0 in
+    // the order nu'; the copy with end bits e is that one times (-1)^popc(e & sig)
+    const int ne = hit->ne;
+    const size_t K0 = Kb >> ne;
+    std::vector<float2> tmp(S * K0);
+    HIPCHECK(hipMemcpyAsync(tmp.data(), hit->X[1], tmp.size() * sizeof(float2),
+                            hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    std::vector<int> asc(hit->pos, hit->pos + ne);
+    std::sort(asc.begin(), asc.end());
+    const std::vector<uint32_t>& rows = *hit->rows;
+    const std::vector<uint32_t>& sig = *hit->sig;
+    for (size_t r = 0; r < S; ++r) {
+      const uint32_t l = rows[r];
+      for (size_t nu = 0; nu < Kb; ++nu) {
+        uint32_t e = 0;
+        for (int i = 0; i < ne; ++i) e |= (uint32_t)((nu >> hit->pos[i]) & 1) << i;
+        size_t v = 0, vb = 0;
+        for (int b = 0; (1ULL << b) < Kb; ++b) {
+          if (std::find(asc.begin(), asc.end(), b) != asc.end()) continue;
+          v |= ((nu >> b) & 1) << vb++;
+        }
+        float2 a = tmp[r * K0 + v];
+        if (__builtin_popcount(e & sig[l]) & 1) a = make_float2(-a.x, -a.y);
+        o[(size_t)nk[nu] * S + l] = a;
+      }
+    }
+    *n_values = S;
+    return QS_OK;
+  }
   std::vector<float2> tmp(cnt);
   HIPCHECK(hipMemcpyAsync(tmp.data(), hit->X[side], cnt * sizeof(float2), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
   // stored as [s][nu] in the upper half's natural copy order; returned as [k][s]
-  const std::vector<uint32_t>& nk = *hit->nu_to_k;
-  float2* o = (float2*)out_c64;
   for (size_t si = 0; si < S; ++si)
     for (size_t nu = 0; nu < Kb; ++nu) o[(size_t)nk[nu] * S + si] = tmp[si * Kb + nu];
   *n_values = S;

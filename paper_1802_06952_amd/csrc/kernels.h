@@ -37,10 +37,31 @@ hipError_t launch_permute_cols(const float2* in, float2* out, const uint32_t* pe
 // FP32 MFMA; prec 1: split-BF16 (three bf16 products, FP32 accumulation).
 // `work` must hold zgemm_workspace_bytes(prec, M, N, K) bytes (split-K
 // partials and, for prec 1, the split operands).
+// cmap (optional): column j of the product goes to column cmap[j] of C.
 size_t zgemm_workspace_bytes(int prec, int M, int N, int K);
 hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int lda,
                            const float2* B, int ldb, float2* C, int ldc, int accumulate,
-                           void* work, hipStream_t st);
+                           void* work, hipStream_t st, const uint32_t* cmap = nullptr);
+
+// Grouped FP32 product: for every group g < ngroups, columns
+// d_goff[g] .. d_goff[g+1]-1 of C (through cmap) (+)= A_g B_g^T, where A_g =
+// A + g a_gstride (M rows of K) and B_g = rows d_goff[g] .. of B (K each);
+// maxn bounds the columns of a group.  One launch for all groups.
+size_t zgemm_grouped_workspace_bytes(int M, int Ntot, int maxn, int K, int ngroups);
+hipError_t launch_zgemm_grouped(int M, int Ntot, int maxn, int K, int ngroups, const int* d_goff,
+                                const float2* A, size_t a_gstride, const float2* B, float2* C,
+                                int ldc, int accumulate, void* work, hipStream_t st,
+                                const uint32_t* cmap);
+
+// out[r][j] = in[rowsel[r]][colsel[j]].
+hipError_t launch_gather_rows_cols(const float2* in, float2* out, const uint32_t* rowsel,
+                                   const uint32_t* colsel, int rows, int Kin, int Kout,
+                                   hipStream_t st);
+
+// Walsh-Hadamard transform of X (rows x K) over the ne <= 4 copy-order bit
+// positions pos[i]: out[sig][u][nu'] for sig < 2^ne, nu' < K >> ne.
+hipError_t launch_end_wht(const float2* X, int rows, int K, int ne, const int* pos, float2* out,
+                          hipStream_t st);
 
 // amps[t] (+)= sum_k A[iu[t]*lda + k] * B[il[t]*ldb + k] (one wavefront per t).
 hipError_t launch_gathered_dot(int K, const float2* A, int lda, const float2* B, int ldb,

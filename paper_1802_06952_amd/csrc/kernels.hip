@@ -670,6 +670,10 @@ k_tail_mm(const TailDesc* __restrict__ tdp, const float2* __restrict__ W,
         if (lam >= Lam || rr >= Nn) continue;
         const float re = p1[a][b][e4] - p2[a][b][e4];
         const float im = p3[a][b][e4] - p1[a][b][e4] - p2[a][b][e4];
+        if (T.end_base) {
+          X[(size_t)si * T.ldx + (((size_t)rr << T.M) + lam)] = make_float2(re, im);
+          continue;
+        }
         float2* dst = X + (size_t)si * T.ldx + ((((size_t)rr << T.M) + lam) << ne);
         for (int e = 0; e < (1 << ne); ++e) {
           float2 f = make_float2(re, im);
@@ -787,6 +791,10 @@ __device__ __forceinline__ void fused_unit(const TailDesc& T, const float2* __re
       if (rn >= Nn) continue;
       const float re = p1[bb][e4] - p2[bb][e4];
       const float im = p3[bb][e4] - p1[bb][e4] - p2[bb][e4];
+      if (T.end_base) {
+        X[(size_t)si * T.ldx + (((size_t)rn << M) + j)] = make_float2(re, im);
+        continue;
+      }
       float2* dst = X + (size_t)si * T.ldx + ((((size_t)rn << M) + j) << ne);
       for (int e = 0; e < (1 << ne); ++e) {
         float2 f = make_float2(re, im);
@@ -1038,7 +1046,7 @@ template <int TM, int TN>
 __global__ void __launch_bounds__(kGemmThreads)
 k_zgemm_nt_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int lda,
                const float2* __restrict__ B, int ldb, float2* __restrict__ out, int ldo,
-               size_t split_stride) {
+               size_t split_stride, const int* __restrict__ goff, int nsplit, size_t a_gstride) {
   constexpr int BM = 32 * TM, BN = 32 * TN;
   __shared__ float2 As[2][kFK][BM + kFPad];
   __shared__ float2 Bs[2][kFK][BN + kFPad];
@@ -1046,6 +1054,19 @@ k_zgemm_nt_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int 
   const int lane = tid & 63, wave = tid >> 6;
   int bx, by, bz;
   gemm_block(bx, by, bz);
+  if (goff) {
+    // grouped: z = group * nsplit + split; group g multiplies its own A
+    // (a_gstride apart) with B rows goff[g] .. goff[g+1]-1 into the same
+    // columns of the partial tile
+    const int g = bz / nsplit;
+    bz -= g * nsplit;
+    const int c0 = goff[g];
+    N = goff[g + 1] - c0;
+    A += (size_t)g * a_gstride;
+    B += (size_t)c0 * ldb;
+    out += c0;
+  }
+  if (bx * BN >= N) return;  // a column tile past a group's end (the whole workgroup)
   const int i_blk = by * BM, j_blk = bx * BN;
   const int wi = (wave >> 1) * (16 * TM), wj = (wave & 1) * (16 * TN);
   const int kb = bz * kper;
@@ -1131,14 +1152,17 @@ k_zgemm_nt_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int 
 }
 
 // C[i][j] = (accumulate ? C[i][j] : 0) + sum over splits of P[z][i][j], in split order.
+// (column j goes to C column cmap[j] when cmap is given)
 __global__ void k_zgemm_reduce(int M, int N, int splits, const float2* __restrict__ P,
-                               size_t split_stride, float2* __restrict__ C, int ldc, int accumulate) {
+                               size_t split_stride, float2* __restrict__ C, int ldc, int accumulate,
+                               const uint32_t* __restrict__ cmap) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (size_t)M * N) return;
-  const int i = (int)(t / N), j = (int)(t % N);
+  const int i = (int)(t / N), jj = (int)(t % N);
+  const int j = cmap ? (int)cmap[jj] : jj;
   float2 acc = accumulate ? C[(size_t)i * ldc + j] : make_float2(0.f, 0.f);
   for (int z = 0; z < splits; ++z) {
-    const float2 p = P[(size_t)z * split_stride + (size_t)i * N + j];
+    const float2 p = P[(size_t)z * split_stride + (size_t)i * N + jj];
     acc.x += p.x;
     acc.y += p.y;
   }
@@ -1300,7 +1324,7 @@ size_t zgemm_workspace_bytes(int prec, int M, int N, int K) {
 
 hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int lda,
                            const float2* B, int ldb, float2* C, int ldc, int accumulate,
-                           void* work, hipStream_t st) {
+                           void* work, hipStream_t st, const uint32_t* cmap) {
   if (M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
   const int kstep = prec == 0 ? kFK : kBK;
   const int Kp = prec == 0 ? K : round_up(K, kBK);
@@ -1310,7 +1334,7 @@ hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int l
   dim3 grid((N + g.bn - 1) / g.bn, (M + g.bm - 1) / g.bm, g.splits);
   if (prec == 0) {
     hipLaunchKernelGGL((k_zgemm_nt_f32<4, kF32TN>), grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper,
-                       A, lda, B, ldb, P, N, ss);
+                       A, lda, B, ldb, P, N, ss, (const int*)nullptr, 1, (size_t)0);
   } else {
     const int Mp = round_up(M, kGBM), Np = round_up(N, kGBN);
     char* base = (char*)work + (size_t)g.splits * ss * sizeof(float2);
@@ -1327,7 +1351,52 @@ hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int l
   }
   const size_t tot = ss;
   hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, N,
-                     g.splits, P, ss, C, ldc, accumulate);
+                     g.splits, P, ss, C, ldc, accumulate, cmap);
+  return hipGetLastError();
+}
+
+namespace {
+
+// Groups hold about N / ngroups columns each, a few more or fewer: 64-wide
+// column tiles waste less on the last, partly filled tile of a group than
+// 128-wide ones (three resident workgroups per CU at this tile size).
+constexpr int kGroupTN = 2;
+
+GemmShape grouped_shape(int M, int maxn, int K, int ngroups) {
+  GemmShape g;
+  g.bm = 128;
+  g.bn = 32 * kGroupTN;
+  g.tiles = ((M + g.bm - 1) / g.bm) * ((maxn + g.bn - 1) / g.bn) * ngroups;
+  const int wgs = 256 * 3;
+  const int want = std::max(1, wgs / std::max(1, g.tiles));
+  const int maxsplit = std::max(1, K / (4 * kFK));
+  g.splits = std::max(1, std::min({want, maxsplit, 64}));
+  g.kper = round_up((K + g.splits - 1) / g.splits, kFK);
+  g.splits = (K + g.kper - 1) / g.kper;
+  return g;
+}
+
+}  // namespace
+
+size_t zgemm_grouped_workspace_bytes(int M, int Ntot, int maxn, int K, int ngroups) {
+  const GemmShape g = grouped_shape(M, maxn, K, ngroups);
+  return (size_t)g.splits * M * Ntot * sizeof(float2);
+}
+
+hipError_t launch_zgemm_grouped(int M, int Ntot, int maxn, int K, int ngroups, const int* d_goff,
+                                const float2* A, size_t a_gstride, const float2* B, float2* C,
+                                int ldc, int accumulate, void* work, hipStream_t st,
+                                const uint32_t* cmap) {
+  if (M <= 0 || Ntot <= 0 || K <= 0 || ngroups <= 0 || maxn <= 0) return hipErrorInvalidValue;
+  const GemmShape g = grouped_shape(M, maxn, K, ngroups);
+  const size_t ss = (size_t)M * Ntot;
+  float2* P = (float2*)work;
+  dim3 grid((maxn + g.bn - 1) / g.bn, (M + g.bm - 1) / g.bm, ngroups * g.splits);
+  if (grid.z > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_zgemm_nt_f32<4, kGroupTN>), grid, dim3(kGemmThreads), 0, st, M, Ntot, K,
+                     g.kper, A, K, B, K, P, Ntot, ss, d_goff, g.splits, a_gstride);
+  hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((ss + 255) / 256)), dim3(256), 0, st, M, Ntot,
+                     g.splits, P, ss, C, ldc, accumulate, cmap);
   return hipGetLastError();
 }
 
@@ -1342,6 +1411,105 @@ __global__ void k_permute_cols(const float2* __restrict__ in, float2* __restrict
   const size_t row = t / K;
   const int j = (int)(t % K);
   out[t] = in[row * K + perm[j]];
+}
+
+// out[r][j] = in[rowsel[r]][colsel[j]] (in: rows of Kin, out: rows of Kout).
+__global__ void k_gather_rows_cols(const float2* __restrict__ in, float2* __restrict__ out,
+                                   const uint32_t* __restrict__ rowsel,
+                                   const uint32_t* __restrict__ colsel, int rows, int Kin,
+                                   int Kout) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)rows * Kout) return;
+  const size_t r = t / Kout;
+  const int j = (int)(t % Kout);
+  out[t] = in[(size_t)rowsel[r] * Kin + colsel[j]];
+}
+
+hipError_t launch_gather_rows_cols(const float2* in, float2* out, const uint32_t* rowsel,
+                                   const uint32_t* colsel, int rows, int Kin, int Kout,
+                                   hipStream_t st) {
+  const size_t tot = (size_t)rows * Kout;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rows_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     in, out, rowsel, colsel, rows, Kin, Kout);
+  return hipGetLastError();
+}
+
+// Walsh-Hadamard transform of the upper operand over the lower half's end
+// cuts: out[sig][u][nu'] = sum_e (-1)^popc(e & sig) X[u][nu(nu', e)], where
+// nu(nu', e) puts bit i of e at copy-order position pos[i] and the bits of
+// nu' at the other positions (ascending).  The lower half's copy (nu', e) is
+// its copy (nu', 0) times (-1)^popc(e & sig(l)), sig(l) = the lower value's
+// bits on the end cuts' qubits, so the sum over copies becomes, for each sig,
+// a product over nu' alone.
+template <int NE>
+__global__ void k_end_wht(const float2* __restrict__ X, int rows, int K, uint32_t pos_packed,
+                          float2* __restrict__ out) {
+  constexpr int E = 1 << NE;
+  const int K0 = K >> NE;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)rows * K0) return;
+  const size_t u = t / K0;
+  const uint32_t v0 = (uint32_t)(t % K0);
+  int pos[NE];
+#pragma unroll
+  for (int i = 0; i < NE; ++i) pos[i] = (int)((pos_packed >> (5 * i)) & 31);
+  // nu' -> nu with zeros at the end positions, taken in ascending order
+  uint32_t nu = v0;
+#pragma unroll
+  for (int a = 0; a < NE; ++a) {
+    int p = 32;  // a-th smallest position
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      int rank = 0;
+#pragma unroll
+      for (int i2 = 0; i2 < NE; ++i2) rank += pos[i2] < pos[i] ? 1 : 0;
+      if (rank == a) p = pos[i];
+    }
+    nu = ((nu >> p) << (p + 1)) | (nu & ((1u << p) - 1u));
+  }
+  float2 x[E];
+  const float2* row = X + u * (size_t)K;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    uint32_t o = nu;
+#pragma unroll
+    for (int i = 0; i < NE; ++i)
+      if ((e >> i) & 1) o |= 1u << pos[i];
+    x[e] = row[o];
+  }
+#pragma unroll
+  for (int h = 1; h < E; h <<= 1)
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (!(e & h)) {
+        const float2 a = x[e], b = x[e | h];
+        x[e] = make_float2(a.x + b.x, a.y + b.y);
+        x[e | h] = make_float2(a.x - b.x, a.y - b.y);
+      }
+  const size_t plane = (size_t)rows * K0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) out[(size_t)e * plane + t] = x[e];
+}
+
+hipError_t launch_end_wht(const float2* X, int rows, int K, int ne, const int* pos, float2* out,
+                          hipStream_t st) {
+  if (ne < 1 || ne > 4 || (K >> ne) < 1) return hipErrorInvalidValue;
+  uint32_t pk = 0;
+  for (int i = 0; i < ne; ++i) {
+    if (pos[i] < 0 || pos[i] > 30) return hipErrorInvalidValue;
+    pk |= (uint32_t)pos[i] << (5 * i);
+  }
+  const size_t tot = (size_t)rows * (size_t)(K >> ne);
+  if (tot == 0) return hipSuccess;
+  dim3 g((unsigned)((tot + 255) / 256)), b(256);
+  switch (ne) {
+    case 1: hipLaunchKernelGGL(k_end_wht<1>, g, b, 0, st, X, rows, K, pk, out); break;
+    case 2: hipLaunchKernelGGL(k_end_wht<2>, g, b, 0, st, X, rows, K, pk, out); break;
+    case 3: hipLaunchKernelGGL(k_end_wht<3>, g, b, 0, st, X, rows, K, pk, out); break;
+    case 4: hipLaunchKernelGGL(k_end_wht<4>, g, b, 0, st, X, rows, K, pk, out); break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_permute_cols(const float2* in, float2* out, const uint32_t* perm, int rows,

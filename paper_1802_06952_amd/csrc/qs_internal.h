@@ -158,6 +158,11 @@ struct TailDesc {
   // then come in emission order j (the digit of level l at bit sum_{l'<l} m_l')
   // instead of lam (the digit of level l at bit lev[l].shift)
   int fused;
+  // 1: write only the copies whose end bits are all 0, without end factors,
+  // at nu0 = node * 2^M + lam (ldx = copies of the block >> n_end).  Used for
+  // lower halves: the other copies differ from these by the signs of the end
+  // cuts' Z, which the assembly applies to the upper operand instead.
+  int end_base;
 };
 
 }  // namespace qs

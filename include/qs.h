@@ -115,6 +115,41 @@ qs_status qs_plan_dump(const qs_plan* plan, uint64_t copy_begin, uint64_t copy_e
 
 void qs_plan_free(qs_plan* plan);
 
+/* Cost of a bipartition, before any simulation (host only).  The paper
+ * estimates a partition's time by Eq. 2 (Sec. 2.2: gates per layer times the
+ * number of half circuits) and its memory by the equivalent qubits N_e
+ * (Sec. 3); this library's own schedule is cheaper than that flat count. */
+typedef struct {
+  int n_cuts;            /* c: CZ gates between the halves (copies = 2^c) */
+  int n_upper, n_lower;  /* qubits of the halves */
+  int equivalent_qubits; /* N_e (Sec. 3): the larger half plus c + 1 */
+  double flat_updates;   /* Eq. 2's work in gate-amplitude updates: every copy runs every gate of
+                            each half on its full state, 2^c (G_up 2^n_upper + G_lo 2^n_lower),
+                            G counting the half's H, one-qubit and internal CZ gates plus one per
+                            cut gate */
+  double plan_cost;      /* this library's schedule of all 2^c copies with n_values requested
+                            values per half: the planner's estimate in HBM byte-equivalents
+                            (full-state passes, leaf evaluation, launches; both halves) plus
+                            the product-set assembly of n_values x n_values amplitudes
+                            (FP32 MFMA flops at 8 TB/s per 157.3 TFLOP/s) */
+} qs_cut_score;
+
+/* Score the bipartition upper_mask of circ for n_values requested values per
+ * half (>= 1).  Errors: QS_ERR_ARG (null pointers, n_values < 1, and the mask
+ * errors of qs_partition), QS_ERR_UNSUPPORTED (more than 40 cut gates, or no
+ * schedule the kernels can run). */
+qs_status qs_score_cut(const qs_circuit* circ, uint64_t upper_mask, int n_values,
+                       qs_cut_score* out);
+
+/* Choose among n_masks candidate bipartitions the one with the smallest
+ * criterion (0: flat_updates, the paper's Eq. 2 accounting; 1: plan_cost, this
+ * library's schedule); masks that qs_score_cut rejects are skipped, ties go to
+ * the first.  *best receives the index into masks, *best_score (may be NULL)
+ * its score.  Errors: QS_ERR_ARG (null pointers, n_masks 0, n_values < 1,
+ * unknown criterion), QS_ERR_UNSUPPORTED (no candidate can be scored). */
+qs_status qs_choose_cut(const qs_circuit* circ, const uint64_t* masks, size_t n_masks,
+                        int n_values, int criterion, size_t* best, qs_cut_score* best_score);
+
 /* Simulate the copies k in [copy_begin, copy_end) of both halves on the GPU
  * and keep, for each, the half amplitudes at the upper and lower parts of the
  * m bitstrings (host array).  The first call registers the bitstrings (they

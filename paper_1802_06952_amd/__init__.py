@@ -30,13 +30,22 @@ _STATUS = {0: "QS_OK", -1: "QS_ERR_ARG", -2: "QS_ERR_PARSE", -3: "QS_ERR_UNSUPPO
 EXPORTED = ("qs_last_error", "qs_load_circuit", "qs_circuit_info", "qs_circuit_free",
             "qs_partition", "qs_plan_info", "qs_plan_dump", "qs_plan_free", "qs_run_halves",
             "qs_amplitudes", "qs_amplitudes_device", "qs_half_amplitudes", "qs_plan_reset",
-            "qs_get_timing", "qs_set_timing")
+            "qs_get_timing", "qs_set_timing", "qs_score_cut", "qs_choose_cut")
 
 
 class QSError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{_STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+class qs_cut_score(C.Structure):
+    _fields_ = [("n_cuts", C.c_int), ("n_upper", C.c_int), ("n_lower", C.c_int),
+                ("equivalent_qubits", C.c_int), ("flat_updates", C.c_double),
+                ("plan_cost", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class qs_options(C.Structure):
@@ -57,6 +66,9 @@ def _load() -> C.CDLL:
     lib.qs_circuit_free.restype = None
     lib.qs_partition.argtypes = [vp, C.c_uint64, C.POINTER(qs_options), C.POINTER(vp)]
     lib.qs_plan_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.qs_score_cut.argtypes = [vp, C.c_uint64, C.c_int, C.POINTER(qs_cut_score)]
+    lib.qs_choose_cut.argtypes = [vp, u64p, C.c_size_t, C.c_int, C.c_int,
+                                  C.POINTER(C.c_size_t), C.POINTER(qs_cut_score)]
     lib.qs_plan_dump.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_char_p, C.c_size_t,
                                  C.POINTER(C.c_size_t)]
     lib.qs_plan_free.argtypes = [vp]
@@ -130,6 +142,22 @@ def qs_partition(circ, upper_mask: int, opts: qs_options | None = None) -> C.c_v
     _check(_lib.qs_partition(circ, C.c_uint64(upper_mask), C.byref(opts) if opts else None,
                              C.byref(h)))
     return h
+
+
+def qs_score_cut(circ, upper_mask: int, n_values: int) -> dict:
+    sc = qs_cut_score()
+    _check(_lib.qs_score_cut(circ, upper_mask, n_values, C.byref(sc)))
+    return sc.as_dict()
+
+
+def qs_choose_cut(circ, masks, n_values: int, criterion: int = 0) -> tuple[int, dict]:
+    """Index of the best candidate mask (criterion 0: Eq. 2 flat updates, 1: plan cost) and its score."""
+    arr = np.ascontiguousarray(np.asarray(masks, dtype=np.uint64))
+    best = C.c_size_t()
+    sc = qs_cut_score()
+    _check(_lib.qs_choose_cut(circ, arr.ctypes.data_as(C.POINTER(C.c_uint64)), arr.size, n_values,
+                              criterion, C.byref(best), C.byref(sc)))
+    return best.value, sc.as_dict()
 
 
 def qs_plan_info(plan) -> tuple[int, int, int]:

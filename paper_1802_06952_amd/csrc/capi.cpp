@@ -844,6 +844,90 @@ qs_status qs_partition(const qs_circuit* circ, uint64_t upper_mask, const qs_opt
   return QS_OK;
 }
 
+namespace {
+
+qs_status score_cut(const Circuit& circ, uint64_t upper_mask, int n_values, qs_cut_score& sc) {
+  std::vector<Cut> cuts;
+  Side up, lo;
+  std::string err;
+  if (!build_partition(circ, upper_mask, cuts, up, lo, err)) return fail(QS_ERR_ARG, err);
+  if (up.n > 32 || lo.n > 32) return fail(QS_ERR_ARG, "a half has more than 32 qubits");
+  const int c = (int)cuts.size();
+  if (c > 40) return fail(QS_ERR_UNSUPPORTED, "more than 40 cut gates");
+  // gates touching each half (a cut CZ touches both)
+  double g[2] = {0, 0};
+  for (const Gate& gt : circ.gates) {
+    const bool u0 = (upper_mask >> gt.q0) & 1;
+    g[u0 ? 0 : 1] += 1;
+    if (gt.q1 >= 0) {
+      const bool u1 = (upper_mask >> gt.q1) & 1;
+      if (u1 != u0) g[u1 ? 0 : 1] += 1;
+    }
+  }
+  sc.n_cuts = c;
+  sc.n_upper = up.n;
+  sc.n_lower = lo.n;
+  sc.equivalent_qubits = std::max(up.n, lo.n) + c + 1;
+  sc.flat_updates = std::ldexp(g[0], c + up.n) + std::ldexp(g[1], c + lo.n);
+  PlanKnobs kn;
+  kn.S = n_values;
+  Block blk;
+  double cost = 0;
+  int ne_lower = 0;
+  for (const Side* sd : {&up, &lo}) {
+    SidePlan sp;
+    if (!plan_side(*sd, c, blk, kn, sp, err)) return fail(QS_ERR_UNSUPPORTED, err);
+    cost += sp.cost_bytes;
+    if (!sd->upper) ne_lower = std::min(4, (int)sp.tree.end_cuts.size());
+  }
+  // assembly over n_values x n_values values: three real products per complex
+  // one over 2^c copies (2^(c - ne) with the lower end cuts folded), priced
+  // at the FP32 MFMA rate in HBM byte-equivalents (8 TB/s against 157.3 TFLOP/s)
+  const double flops = 6.0 * (double)n_values * (double)n_values * std::ldexp(1.0, c - ne_lower);
+  cost += flops * (8.0 / 157.3);
+  sc.plan_cost = cost;
+  return QS_OK;
+}
+
+}  // namespace
+
+qs_status qs_score_cut(const qs_circuit* circ, uint64_t upper_mask, int n_values,
+                       qs_cut_score* out) {
+  if (!circ || !out) return fail(QS_ERR_ARG, "null pointer");
+  if (n_values < 1) return fail(QS_ERR_ARG, "n_values must be at least 1");
+  qs_cut_score sc{};
+  const qs_status s = score_cut(circ->c, upper_mask, n_values, sc);
+  if (s != QS_OK) return s;
+  *out = sc;
+  return QS_OK;
+}
+
+qs_status qs_choose_cut(const qs_circuit* circ, const uint64_t* masks, size_t n_masks,
+                        int n_values, int criterion, size_t* best, qs_cut_score* best_score) {
+  if (!circ || !masks || !best) return fail(QS_ERR_ARG, "null pointer");
+  if (n_masks == 0) return fail(QS_ERR_ARG, "no candidate masks");
+  if (n_values < 1) return fail(QS_ERR_ARG, "n_values must be at least 1");
+  if (criterion != 0 && criterion != 1) return fail(QS_ERR_ARG, "unknown criterion");
+  bool found = false;
+  size_t bi = 0;
+  qs_cut_score bs{};
+  for (size_t i = 0; i < n_masks; ++i) {
+    qs_cut_score sc{};
+    if (score_cut(circ->c, masks[i], n_values, sc) != QS_OK) continue;
+    const double v = criterion == 0 ? sc.flat_updates : sc.plan_cost;
+    const double bv = criterion == 0 ? bs.flat_updates : bs.plan_cost;
+    if (!found || v < bv) {
+      found = true;
+      bi = i;
+      bs = sc;
+    }
+  }
+  if (!found) return fail(QS_ERR_UNSUPPORTED, "no candidate mask can be scored");
+  *best = bi;
+  if (best_score) *best_score = bs;
+  return QS_OK;
+}
+
 qs_status qs_plan_info(const qs_plan* plan, int* n_upper, int* n_lower, int* n_cuts) {
   if (!plan) return fail(QS_ERR_ARG, "null plan");
   if (n_upper) *n_upper = plan->side[0].n;

@@ -151,6 +151,11 @@ struct Prepared {
   std::vector<uint64_t> leaf_k;
   std::vector<uint32_t> nu_to_k;  // block-local copy index of each natural position nu
   double pass_bytes = 0;  // algorithmic bytes of the passes
+  // The kernels apply the unit-entry part of every 2x2 gate, and each pass
+  // (and the leaf evaluation) multiplies by an exact power of two: the true
+  // amplitudes are the computed ones times phi = 2^(-carry/2) omega^A (A the
+  // number of sqrt X and sqrt Y gates, carry the odd half power left over).
+  double phi_re = 1, phi_im = 0;
   double tail_flops = 0;  // 2x2-gate flops of the leaf evaluation
   ~Prepared() {
     if (dev) (void)hipFree(dev);
@@ -188,6 +193,7 @@ struct qs_plan {
   uint32_t* d_vals[2] = {nullptr, nullptr};
   int* d_idx[2] = {nullptr, nullptr};
   bool list_mode = false;  // bitstrings far from a product set: per-bitstring sums
+  double phi[2][2] = {{1, 0}, {1, 0}};  // per half: the constant of its unit-entry gates (Prepared)
   std::vector<BlockRes> blocks;
   std::vector<std::pair<uint64_t, uint64_t>> ranges;
   std::map<std::tuple<int, uint64_t, int>, std::unique_ptr<Prepared>> cache;
@@ -275,6 +281,8 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   auto it = P->cache.find(key);
   if (it != P->cache.end()) {
     *out = it->second.get();
+    P->phi[sidx][0] = (*out)->phi_re;
+    P->phi[sidx][1] = (*out)->phi_im;
     return QS_OK;
   }
   if (P->cache.size() > 4096) {
@@ -301,6 +309,14 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   const double SB = std::ldexp(8.0, s.n);
   std::vector<DevOp> ops;
   double last_bytes = 0;
+  int carry = 0, n_omega = 0;
+  auto mat_counts = [&](const std::vector<int>& lst, int& k, int& w) {
+    for (int i : lst)
+      if (s.ops[i].kind == OP_MAT) {
+        ++k;
+        if (s.ops[i].mat == 1 || s.ops[i].mat == 2) ++w;
+      }
+  };
   for (const PassPlan& pp : sp.passes) {
     PassDesc d{};
     d.wave = s.n >= 7 ? 1 : 0;
@@ -341,6 +357,13 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
     }
     pr->pass_bytes += last_bytes;
     d.upper = s.upper ? 1 : 0;
+    {
+      int k = 0;
+      mat_counts(pp.ops_in, k, n_omega);
+      if (pp.branch) mat_counts(pp.ops_out, k, n_omega);
+      d.scale = std::ldexp(1.0f, -((k + carry) >> 1));
+      carry = (k + carry) & 1;
+    }
     pr->pds.push_back(d);
   }
   TailDesc& td = pr->td;
@@ -413,6 +436,18 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
       pr->tail_flops += (double)S * paths * 14.0 * nmat * K;
       paths *= std::ldexp(1.0, (int)tr.levels[l].cuts.size());
     }
+  }
+  {
+    int k = 0;
+    for (int l = sp.lstar + 1; l <= L; ++l) mat_counts(tr.levels[l].ops, k, n_omega);
+    td.tscale = std::ldexp(1.0f, -((k + carry) >> 1));
+    carry = (k + carry) & 1;
+    const double mag = carry ? std::sqrt(0.5) : 1.0;
+    const double ang = (n_omega & 7) * (M_PI / 4.0);
+    pr->phi_re = mag * std::cos(ang);
+    pr->phi_im = mag * std::sin(ang);
+    P->phi[sidx][0] = pr->phi_re;
+    P->phi[sidx][1] = pr->phi_im;
   }
   td.n_end = (int)tr.end_cuts.size();
   for (int i = 0; i < td.n_end; ++i) {
@@ -695,6 +730,12 @@ qs_status register_bits(qs_plan* P, const uint64_t* bits, size_t m) {
 
 // Assembly of every run block into C, then the amplitudes of the registered
 // bitstrings into d_amps and their FP64 sums into d_sums.  Asynchronous.
+// The product of the two halves' constants (see Prepared::phi).
+float2 phi_of(const qs_plan* plan) {
+  const double a = plan->phi[0][0], b = plan->phi[0][1], c = plan->phi[1][0], d = plan->phi[1][1];
+  return make_float2((float)(a * c - b * d), (float)(a * d + b * c));
+}
+
 qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_sums, hipStream_t st) {
   const int M = (int)plan->vals[0].size(), N = (int)plan->vals[1].size();
   const size_t m = plan->bits.size();
@@ -709,7 +750,7 @@ qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_s
     for (BlockRes& b : plan->blocks) {
       const int K = (int)(b.k1 - b.k0);
       HIPCHECK(launch_gathered_dot(K, b.X[0], K, b.X[1], K, plan->d_idx[0], plan->d_idx[1], m,
-                                   d_amps, first ? 0 : 1, st));
+                                   d_amps, first ? 0 : 1, phi_of(plan), st));
       ++tm.launches;
       if (plan->timing) plan->gemm_flops += 8.0 * (double)m * (double)K;
       first = false;
@@ -768,7 +809,7 @@ qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_s
       }
     }
     Timer tm(plan, st, 3);
-    HIPCHECK(launch_gather_amps(C, N, plan->d_idx[0], plan->d_idx[1], m, d_amps, st));
+    HIPCHECK(launch_gather_amps(C, N, plan->d_idx[0], plan->d_idx[1], m, d_amps, phi_of(plan), st));
     tm.launches += 1;
     plan->pool.put(C, st);
   }
@@ -1201,6 +1242,10 @@ qs_status qs_half_amplitudes(qs_plan* plan, int side, uint64_t copy_begin, uint6
   const size_t Kb = (size_t)(copy_end - copy_begin);
   const std::vector<uint32_t>& nk = *hit->nu_to_k;
   float2* o = (float2*)out_c64;
+  const double pr_ = plan->phi[side][0], pi_ = plan->phi[side][1];
+  auto ph = [&](float2 a) {
+    return make_float2((float)(a.x * pr_ - a.y * pi_), (float)(a.x * pi_ + a.y * pr_));
+  };
   if (side == 1 && hit->ne > 0) {
     // stored: rows sorted by end-cut pattern, the copies with end bits 0 in
     // the order nu'; the copy with end bits e is that one times (-1)^popc(e & sig)
@@ -1226,7 +1271,7 @@ qs_status qs_half_amplitudes(qs_plan* plan, int side, uint64_t copy_begin, uint6
         }
         float2 a = tmp[r * K0 + v];
         if (__builtin_popcount(e & sig[l]) & 1) a = make_float2(-a.x, -a.y);
-        o[(size_t)nk[nu] * S + l] = a;
+        o[(size_t)nk[nu] * S + l] = ph(a);
       }
     }
     *n_values = S;
@@ -1237,7 +1282,7 @@ qs_status qs_half_amplitudes(qs_plan* plan, int side, uint64_t copy_begin, uint6
   HIPCHECK(hipStreamSynchronize(st));
   // stored as [s][nu] in the upper half's natural copy order; returned as [k][s]
   for (size_t si = 0; si < S; ++si)
-    for (size_t nu = 0; nu < Kb; ++nu) o[(size_t)nk[nu] * S + si] = tmp[si * Kb + nu];
+    for (size_t nu = 0; nu < Kb; ++nu) o[(size_t)nk[nu] * S + si] = ph(tmp[si * Kb + nu]);
   *n_values = S;
   return QS_OK;
 }

@@ -63,14 +63,14 @@ hipError_t launch_gather_rows_cols(const float2* in, float2* out, const uint32_t
 hipError_t launch_end_wht(const float2* X, int rows, int K, int ne, const int* pos, float2* out,
                           hipStream_t st);
 
-// amps[t] (+)= sum_k A[iu[t]*lda + k] * B[il[t]*ldb + k] (one wavefront per t).
+// amps[t] (+)= phi * sum_k A[iu[t]*lda + k] * B[il[t]*ldb + k] (one wavefront per t).
 hipError_t launch_gathered_dot(int K, const float2* A, int lda, const float2* B, int ldb,
                                const int* iu, const int* il, size_t m, float2* amps,
-                               int accumulate, hipStream_t st);
+                               int accumulate, float2 phi, hipStream_t st);
 
-// amps[t] = C[iu[t] * ldc + il[t]].
+// amps[t] = phi * C[iu[t] * ldc + il[t]].
 hipError_t launch_gather_amps(const float2* C, int ldc, const int* iu, const int* il, size_t m,
-                              float2* amps, hipStream_t st);
+                              float2* amps, float2 phi, hipStream_t st);
 
 // FP64 sums over m amplitudes: out[0] = sum |a|^2, out[1] = sum |a|^4.
 // `partial` must hold 2 * prob_partial_blocks(m) doubles.

@@ -53,9 +53,30 @@ __device__ __forceinline__ void mat_apply(const float* m, float2 a, float2 b, fl
                    m[4] * a.y + m[5] * a.x + m[6] * b.y + m[7] * b.x);
 }
 
+// The unit-entry gates (MatKind) on a pair (a0, a1) = amplitudes with the
+// target bit 0 and 1: out0 = m00 a0 + m01 a1, out1 = m10 a0 + m11 a1, all
+// entries 0, +-1, +-i, so additions only.
+template <int MK>
+__device__ __forceinline__ void unit_pair(float2& a0, float2& a1) {
+  const float2 x = a0, y = a1;
+  if constexpr (MK == MK_X) {  // [[1, -i], [-i, 1]]
+    a0 = make_float2(x.x + y.y, x.y - y.x);
+    a1 = make_float2(x.y + y.x, y.y - x.x);
+  } else if constexpr (MK == MK_Y) {  // [[1, -1], [1, 1]]
+    a0 = make_float2(x.x - y.x, x.y - y.y);
+    a1 = make_float2(x.x + y.x, x.y + y.y);
+  } else if constexpr (MK == MK_YT) {  // [[1, 1], [-1, 1]]
+    a0 = make_float2(x.x + y.x, x.y + y.y);
+    a1 = make_float2(y.x - x.x, y.y - x.y);
+  } else {  // MK_H: [[1, 1], [1, -1]]
+    a0 = make_float2(x.x + y.x, x.y + y.y);
+    a1 = make_float2(x.x - y.x, x.y - y.y);
+  }
+}
+
 // Register-pair 2x2 gate: pairs (r, r | 2^rb) of a per-lane register array.
 template <int R>
-__device__ __forceinline__ void tail_mat_reg(float2 (&v)[R], const float* m, int rb) {
+__device__ __forceinline__ void tail_mat_reg_m(float2 (&v)[R], const float* m, int rb) {
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (r & (1 << rb)) continue;
@@ -64,6 +85,26 @@ __device__ __forceinline__ void tail_mat_reg(float2 (&v)[R], const float* m, int
     mat_apply(m, v[r], v[r1], oa, ob);
     v[r] = oa;
     v[r1] = ob;
+  }
+}
+
+template <int R, int MK>
+__device__ __forceinline__ void tail_mat_reg_u(float2 (&v)[R], int rb) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r & (1 << rb)) continue;
+    unit_pair<MK>(v[r], v[r | (1 << rb)]);
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void tail_mat_reg(float2 (&v)[R], const DevOp& op, int rb) {
+  switch (__builtin_amdgcn_readfirstlane(op.mk)) {
+    case MK_X: tail_mat_reg_u<R, MK_X>(v, rb); break;
+    case MK_Y: tail_mat_reg_u<R, MK_Y>(v, rb); break;
+    case MK_YT: tail_mat_reg_u<R, MK_YT>(v, rb); break;
+    case MK_H: tail_mat_reg_u<R, MK_H>(v, rb); break;
+    default: tail_mat_reg_m<R>(v, op.m, rb); break;
   }
 }
 
@@ -132,10 +173,11 @@ k_pass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops,
   }
   __syncthreads();
   lds_apply_ops(A, ops + P.op_in, P.n_in, t, tbit, outer);
+  const float sc = P.scale;
   if (P.m == 0) {
     for (int i = threadIdx.x; i < size; i += kPassThreads) {
       const uint32_t x = outer | deposit_tile(i, tbit, t);
-      out[node * N + x] = A[i];
+      out[node * N + x] = make_float2(A[i].x * sc, A[i].y * sc);
     }
     return;
   }
@@ -161,7 +203,7 @@ k_pass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops,
     const uint64_t child = (node << m) | (uint64_t)b;
     for (int i = threadIdx.x; i < size; i += kPassThreads) {
       const uint32_t x = outer | deposit_tile(i, tbit, t);
-      out[child * N + x] = Bb[i];
+      out[child * N + x] = make_float2(Bb[i].x * sc, Bb[i].y * sc);
     }
     __syncthreads();
   }
@@ -229,6 +271,58 @@ __device__ __forceinline__ void init_phase_table(float2* tab) {
 
 __device__ __forceinline__ float uniform_f(float x) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+// Lane-pair 2x2 gate from the matrix entries m[] (any 2x2 matrix).
+template <int R>
+__device__ __forceinline__ void lane_mat_m(float2 (&v)[R], const DevOp& op, int w, bool bit) {
+  float m[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) m[i] = uniform_f(op.m[i]);
+  const float sr = bit ? m[6] : m[0], si = bit ? m[7] : m[1];
+  const float pr = bit ? m[4] : m[2], pi = bit ? m[5] : m[3];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float px = __shfl_xor(v[r].x, 1 << w);
+    const float py = __shfl_xor(v[r].y, 1 << w);
+    const float2 a = v[r];
+    v[r] = make_float2(sr * a.x - si * a.y + pr * px - pi * py,
+                       sr * a.y + si * a.x + pr * py + pi * px);
+  }
+}
+
+// Lane-pair 2x2 gate on lane bit w: bit = this lane's value of the target
+// bit, p = the partner lane's amplitude.  Unit-entry kinds: X gives
+// a - i p on both sides; Y gives a -+ p; its transpose a +- p; H +-a + p.
+template <int R>
+__device__ __forceinline__ void lane_mat(float2 (&v)[R], const DevOp& op, int w, bool bit) {
+  const int mk = __builtin_amdgcn_readfirstlane(op.mk);
+  if (mk == MK_X) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float px = __shfl_xor(v[r].x, 1 << w);
+      const float py = __shfl_xor(v[r].y, 1 << w);
+      v[r] = make_float2(v[r].x + py, v[r].y - px);
+    }
+  } else if (mk == MK_Y || mk == MK_YT) {
+    const float sg = (bit == (mk == MK_Y)) ? 1.f : -1.f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float px = __shfl_xor(v[r].x, 1 << w);
+      const float py = __shfl_xor(v[r].y, 1 << w);
+      v[r] = make_float2(fmaf(sg, px, v[r].x), fmaf(sg, py, v[r].y));
+    }
+  } else if (mk == MK_H) {
+    const float sg = bit ? -1.f : 1.f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float px = __shfl_xor(v[r].x, 1 << w);
+      const float py = __shfl_xor(v[r].y, 1 << w);
+      v[r] = make_float2(fmaf(sg, v[r].x, px), fmaf(sg, v[r].y, py));
+    }
+  } else {
+    lane_mat_m<R>(v, op, w, bit);
+  }
 }
 
 template <int R>
@@ -305,27 +399,14 @@ __device__ __forceinline__ void wave_apply_ops(float2 (&v)[1 << R], const DevOp*
     if (op.kind == 0) {
       const int w = op.target;
       if (w < 6) {
-        const bool bit = (lane >> w) & 1;
-        float m[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) m[i] = uniform_f(op.m[i]);
-        const float sr = bit ? m[6] : m[0], si = bit ? m[7] : m[1];
-        const float pr = bit ? m[4] : m[2], pi = bit ? m[5] : m[3];
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-          const float px = __shfl_xor(v[r].x, 1 << w);
-          const float py = __shfl_xor(v[r].y, 1 << w);
-          const float2 a = v[r];
-          v[r] = make_float2(sr * a.x - si * a.y + pr * px - pi * py,
-                             sr * a.y + si * a.x + pr * py + pi * px);
-        }
+        lane_mat<E>(v, op, w, (lane >> w) & 1);
       } else {
         const int k = w - 6;
-        if constexpr (R >= 1) { if (k == 0) tail_mat_reg<E>(v, op.m, 0); }
-        if constexpr (R >= 2) { if (k == 1) tail_mat_reg<E>(v, op.m, 1); }
-        if constexpr (R >= 3) { if (k == 2) tail_mat_reg<E>(v, op.m, 2); }
-        if constexpr (R >= 4) { if (k == 3) tail_mat_reg<E>(v, op.m, 3); }
-        if constexpr (R >= 5) { if (k == 4) tail_mat_reg<E>(v, op.m, 4); }
+        if constexpr (R >= 1) { if (k == 0) tail_mat_reg<E>(v, op, 0); }
+        if constexpr (R >= 2) { if (k == 1) tail_mat_reg<E>(v, op, 1); }
+        if constexpr (R >= 3) { if (k == 2) tail_mat_reg<E>(v, op, 2); }
+        if constexpr (R >= 4) { if (k == 3) tail_mat_reg<E>(v, op, 3); }
+        if constexpr (R >= 5) { if (k == 4) tail_mat_reg<E>(v, op, 4); }
       }
     } else {
       diag_regs<R>(v, op, F, RB, tab);
@@ -376,10 +457,12 @@ k_wpass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops, const f
     for (int r = 0; r < E; ++r) v[r] = src[F | reg_index<R>(r, RB)];
   }
   wave_apply_ops<R>(v, ops + P.op_in, P.n_in, F, RB, lane, tab);
+  const float sc = P.scale;
   if (P.m == 0) {
     float2* dst = out + node * N;
 #pragma unroll
-    for (int r = 0; r < E; ++r) dst[F | reg_index<R>(r, RB)] = v[r];
+    for (int r = 0; r < E; ++r)
+      dst[F | reg_index<R>(r, RB)] = make_float2(v[r].x * sc, v[r].y * sc);
     return;
   }
   const int m = P.m;
@@ -398,7 +481,8 @@ k_wpass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops, const f
     wave_apply_ops<R>(w, ops + P.op_out, P.n_out, F, RB, lane, tab);
     float2* dst = out + ((node << m) | (uint64_t)b) * N;
 #pragma unroll
-    for (int r = 0; r < E; ++r) dst[F | reg_index<R>(r, RB)] = w[r];
+    for (int r = 0; r < E; ++r)
+      dst[F | reg_index<R>(r, RB)] = make_float2(w[r].x * sc, w[r].y * sc);
   }
 }
 
@@ -474,27 +558,16 @@ __device__ __forceinline__ void tail_apply_ops(float2 (&v)[R], const TailCtx<R>&
     const DevOp& op = ops[o];
     if (op.kind == 0) {
       const int w = op.target;
+      // the general form: one code path per gate keeps the unrolled leaf
+      // kernels small (a branch per gate kind there costs more than it saves)
       if (w < c.lg) {
-        const bool bit = (c.g >> w) & 1;
-        float m[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) m[i] = uniform_f(op.m[i]);
-        const float sr = bit ? m[6] : m[0], si = bit ? m[7] : m[1];
-        const float pr = bit ? m[4] : m[2], pi = bit ? m[5] : m[3];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const float px = __shfl_xor(v[r].x, 1 << w);
-          const float py = __shfl_xor(v[r].y, 1 << w);
-          const float2 a = v[r];
-          v[r] = make_float2(sr * a.x - si * a.y + pr * px - pi * py,
-                             sr * a.y + si * a.x + pr * py + pi * px);
-        }
+        lane_mat_m<R>(v, op, w, (c.g >> w) & 1);
       } else {
         const int rb = w - c.lg;
-        if constexpr (R >= 2) { if (rb == 0) tail_mat_reg<R>(v, op.m, 0); }
-        if constexpr (R >= 4) { if (rb == 1) tail_mat_reg<R>(v, op.m, 1); }
-        if constexpr (R >= 8) { if (rb == 2) tail_mat_reg<R>(v, op.m, 2); }
-        if constexpr (R >= 16) { if (rb == 3) tail_mat_reg<R>(v, op.m, 3); }
+        if constexpr (R >= 2) { if (rb == 0) tail_mat_reg_m<R>(v, op.m, 0); }
+        if constexpr (R >= 4) { if (rb == 1) tail_mat_reg_m<R>(v, op.m, 1); }
+        if constexpr (R >= 8) { if (rb == 2) tail_mat_reg_m<R>(v, op.m, 2); }
+        if constexpr (R >= 16) { if (rb == 3) tail_mat_reg_m<R>(v, op.m, 3); }
       }
     } else {
       diag_regs<TailCtx<R>::NB>(v, op, c.xs[0], c.RB, c.tab);
@@ -581,7 +654,7 @@ k_tail_bwd(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
     uint32_t x = base;
     for (int i = 0; i < T.q; ++i) x |= ((y >> i) & 1u) << T.Q[i];
     c.xs[r] = x;
-    v[r] = (y == ys) ? make_float2(1.f, 0.f) : make_float2(0.f, 0.f);
+    v[r] = (y == ys) ? make_float2(T.tscale, 0.f) : make_float2(0.f, 0.f);
   }
   const size_t K = (size_t)G * R;
   float2* Wrow = W + gid * ((size_t)1 << T.M) * K;
@@ -881,7 +954,7 @@ k_tail_fused(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
             if (D == 0) {
 #pragma unroll
               for (int r = 0; r < RC; ++r)
-                v[r] = ((uint32_t)(lane + 64 * (r % R)) == ys) ? make_float2(1.f, 0.f)
+                v[r] = ((uint32_t)(lane + 64 * (r % R)) == ys) ? make_float2(T.tscale, 0.f)
                                                                 : make_float2(0.f, 0.f);
             } else {
               const TailLevel& L = T.lev[l + 1];
@@ -1526,7 +1599,7 @@ hipError_t launch_permute_cols(const float2* in, float2* out, const uint32_t* pe
 __global__ void __launch_bounds__(256)
 k_gathered_dot(int K, const float2* __restrict__ A, int lda, const float2* __restrict__ B, int ldb,
                const int* __restrict__ iu, const int* __restrict__ il, size_t m,
-               float2* __restrict__ amps, int accumulate) {
+               float2* __restrict__ amps, int accumulate, float2 phi) {
   const size_t t = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (t >= m) return;
@@ -1542,7 +1615,7 @@ k_gathered_dot(int K, const float2* __restrict__ A, int lda, const float2* __res
     im += __shfl_xor(im, w);
   }
   if (lane == 0) {
-    float2 o = make_float2(re, im);
+    float2 o = cmul(make_float2(re, im), phi);
     if (accumulate) {
       o.x += amps[t].x;
       o.y += amps[t].y;
@@ -1553,25 +1626,26 @@ k_gathered_dot(int K, const float2* __restrict__ A, int lda, const float2* __res
 
 hipError_t launch_gathered_dot(int K, const float2* A, int lda, const float2* B, int ldb,
                                const int* iu, const int* il, size_t m, float2* amps,
-                               int accumulate, hipStream_t st) {
+                               int accumulate, float2 phi, hipStream_t st) {
   if (m == 0 || K <= 0) return hipSuccess;
   const size_t blocks = (m * 64 + 255) / 256;
   hipLaunchKernelGGL(k_gathered_dot, dim3((unsigned)blocks), dim3(256), 0, st, K, A, lda, B, ldb,
-                     iu, il, m, amps, accumulate);
+                     iu, il, m, amps, accumulate, phi);
   return hipGetLastError();
 }
 
 __global__ void k_gather_amps(const float2* __restrict__ C, int ldc, const int* __restrict__ iu,
-                              const int* __restrict__ il, size_t m, float2* __restrict__ amps) {
+                              const int* __restrict__ il, size_t m, float2* __restrict__ amps,
+                              float2 phi) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < m) amps[t] = C[(size_t)iu[t] * ldc + il[t]];
+  if (t < m) amps[t] = cmul(C[(size_t)iu[t] * ldc + il[t]], phi);
 }
 
 hipError_t launch_gather_amps(const float2* C, int ldc, const int* iu, const int* il, size_t m,
-                              float2* amps, hipStream_t st) {
+                              float2* amps, float2 phi, hipStream_t st) {
   if (m == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_amps, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, C, ldc,
-                     iu, il, m, amps);
+                     iu, il, m, amps, phi);
   return hipGetLastError();
 }
 

@@ -451,19 +451,20 @@ void flush(DiagAcc& a, std::vector<DevOp>& out) {
 }
 
 void set_mat(DevOp& op, int mat) {
-  const float r = 0.70710678118654752f;
-  float m[8];
-  if (mat == 0) {  // H
-    float v[8] = {r, 0, r, 0, r, 0, -r, 0};
-    std::copy(v, v + 8, m);
-  } else if (mat == 1) {  // sqrt X = 1/2 [[1+i, 1-i], [1-i, 1+i]]
-    float v[8] = {0.5f, 0.5f, 0.5f, -0.5f, 0.5f, -0.5f, 0.5f, 0.5f};
-    std::copy(v, v + 8, m);
-  } else {  // sqrt Y = 1/2 [[1+i, -1-i], [1+i, 1+i]]
-    float v[8] = {0.5f, 0.5f, -0.5f, -0.5f, 0.5f, 0.5f, 0.5f, 0.5f};
-    std::copy(v, v + 8, m);
+  // the unit-entry part of the gate (the scalar goes to the half's constant)
+  if (mat == 0) {  // H = 1/sqrt 2 [[1, 1], [1, -1]]
+    const float v[8] = {1, 0, 1, 0, 1, 0, -1, 0};
+    std::copy(v, v + 8, op.m);
+    op.mk = MK_H;
+  } else if (mat == 1) {  // sqrt X = (1+i)/2 [[1, -i], [-i, 1]]
+    const float v[8] = {1, 0, 0, -1, 0, -1, 1, 0};
+    std::copy(v, v + 8, op.m);
+    op.mk = MK_X;
+  } else {  // sqrt Y = (1+i)/2 [[1, -1], [1, 1]]
+    const float v[8] = {1, 0, -1, 0, 1, 0, 1, 0};
+    std::copy(v, v + 8, op.m);
+    op.mk = MK_Y;
   }
-  std::copy(m, m + 8, op.m);
 }
 
 }  // namespace
@@ -528,6 +529,7 @@ bool encode_ops(const Side& s, const std::vector<int>& ops, const std::vector<in
         if (transpose) {
           std::swap(op.m[2], op.m[4]);
           std::swap(op.m[3], op.m[5]);
+          if (op.mk == MK_Y) op.mk = MK_YT;  // X and H are symmetric
         }
         out.push_back(op);
         break;

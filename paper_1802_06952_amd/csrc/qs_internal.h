@@ -76,11 +76,25 @@ constexpr int kMaxTileBits = 14;
 // index bit `target` of the kernel's working index space.
 constexpr int kMaxRegBits = 5;
 
+// The 2x2 gates of the circuits are a scalar times a matrix of entries 0, +-1,
+// +-i: sqrt X = (1+i)/2 [[1,-i],[-i,1]], sqrt Y = (1+i)/2 [[1,-1],[1,1]],
+// H = 1/sqrt 2 [[1,1],[1,-1]].  The kernels apply the unit-entry matrix (two
+// additions per amplitude); the scalars of all gates of a half multiply to one
+// constant, which the passes keep in range by exact powers of two and the
+// assembly applies once (see Prepared::phi).
+enum MatKind : int {
+  MK_GENERIC = 0,  // m[] as given
+  MK_X = 1,        // [[1, -i], [-i, 1]]
+  MK_Y = 2,        // [[1, -1], [1, 1]]
+  MK_YT = 3,       // [[1, 1], [-1, 1]]
+  MK_H = 4         // [[1, 1], [1, -1]]
+};
+
 struct DevOp {
   int kind;    // 0 = MAT, 1 = DIAG
   int target;  // MAT: working bit
   int nd;      // DIAG: number of (d, M) pairs
-  int pad;
+  int mk;      // MAT: MatKind (m[] holds the same matrix)
   float m[8];  // MAT: m00 m01 m10 m11 as (re, im)
   uint64_t t0, t1, t2, pmask, pval;
   int d[kMaxDiagDist];
@@ -117,6 +131,7 @@ struct PassDesc {
   int m;             // branch bits (0 = no branch)
   int bq[kMaxBranch];  // state bit of the cut qubit of branch bit i (bit i = MSB first)
   int upper;         // 1: P_b factors, 0: Z^b factors
+  float scale;       // exact power of two applied at the store (keeps unit-entry gates in range)
 };
 
 struct TailLevel {
@@ -163,6 +178,7 @@ struct TailDesc {
   // lower halves: the other copies differ from these by the signs of the end
   // cuts' Z, which the assembly applies to the upper operand instead.
   int end_base;
+  float tscale;         // value of the unit vector the backward rows start from (a power of two)
 };
 
 }  // namespace qs

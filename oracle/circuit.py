@@ -1,7 +1,9 @@
 """Circuit text parser of the oracle (its own; the HIP library has a separate C++ one).
 
 A circuit is the layered form of Supp. A: a sequence of layers (cycles), each a
-set of gates on disjoint qubits; an edge of the layer graph is a CZ.
+set of gates on disjoint qubits; an edge of the layer graph is a CZ.  The
+controlled gates of Supp. Eq. 1 with U = X and U = Y ("cx", "cy") list the
+control qubit first.
 """
 
 from __future__ import annotations
@@ -9,7 +11,7 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 
 ONE_QUBIT = ("h", "t", "sx", "sy")
-TWO_QUBIT = ("cz",)
+TWO_QUBIT = ("cz", "cx", "cy")
 
 
 @dataclass

@@ -30,6 +30,11 @@ def embed_cz(n: int, a: int, b: int) -> np.ndarray:
     return np.diag(d)
 
 
+def embed_controlled(n: int, c: int, t: int, u: np.ndarray) -> np.ndarray:
+    """P0 x I + P1 x u on (control c, target t), Supp. Eq. 1, as Kronecker sums."""
+    return embed_1q(n, c, G.P0) + embed_1q(n, c, G.P1) @ embed_1q(n, t, u)
+
+
 def unitary(circ: Circuit) -> np.ndarray:
     n = circ.n
     if n > 10:
@@ -38,6 +43,8 @@ def unitary(circ: Circuit) -> np.ndarray:
     for _, name, qs in circ.gates:
         if name == "cz":
             g = embed_cz(n, qs[0], qs[1])
+        elif name in G.CONTROLLED_U:
+            g = embed_controlled(n, qs[0], qs[1], G.CONTROLLED_U[name])
         else:
             g = embed_1q(n, qs[0], G.ONE_QUBIT[name])
         u = g @ u

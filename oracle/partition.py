@@ -3,10 +3,12 @@
 Steps, in the paper's order:
 
 1. Split the qubits into an upper set V1 and a lower set V2 (Supp. A, the
-   division of V_t into V_{1,t} and V_{2,t}).  The CZ gates with one end in
-   each set form E_int (the cut gates); the others stay inside a half.
+   division of V_t into V_{1,t} and V_{2,t}).  The two-qubit gates with one
+   end in each set form E_int (the cut gates); the others stay inside a half.
 2. Rewrite every cut CZ as P0 x I + P1 x Z (Eq. 1 / Supp. Eq. 2): P_b goes on
-   the upper endpoint and Z^b on the lower endpoint.  With c cut gates the
+   the upper endpoint and Z^b on the lower endpoint.  A cut controlled-U with
+   U = X or Y ("cx", "cy") is rewritten by Supp. Eq. 1: P_b on the control,
+   U^b on the target, whichever half each is in.  With c cut gates the
    circuit becomes the sum of 2^c copies, each the tensor product of an upper
    and a lower half circuit (Supp. Eq. 7-8).
 3. Simulate every copy's two halves from H on |0...0>.  States shared by
@@ -39,6 +41,8 @@ class Cut:
     cycle: int
     upper: int
     lower: int
+    gate: str = "cz"   # the cut two-qubit gate
+    control: int = -1  # its control qubit (cx, cy); -1 for cz
 
 
 def half_qubits(n: int, mask: int) -> list[int]:
@@ -46,18 +50,30 @@ def half_qubits(n: int, mask: int) -> list[int]:
 
 
 def find_cuts(circ: Circuit, upper_mask: int) -> list[Cut]:
-    """The CZ gates of E_int (one endpoint in each half), in cut order."""
+    """The two-qubit gates of E_int (one endpoint in each half), in cut order."""
     raw = []
     for t, name, qs in circ.gates:
-        if name != "cz":
+        if len(qs) != 2:
             continue
         a, b = qs
         ia, ib = (upper_mask >> a) & 1, (upper_mask >> b) & 1
         if ia != ib:
             up, lo = (a, b) if ia else (b, a)
-            raw.append((t, up, lo))
+            raw.append((t, up, lo, name, -1 if name == "cz" else a))
     raw.sort()
-    return [Cut(j, t, up, lo) for j, (t, up, lo) in enumerate(raw)]
+    return [Cut(j, *r) for j, r in enumerate(raw)]
+
+
+def cut_factor(cut: Cut, upper: bool, b: int) -> str:
+    """The one-qubit factor of copy bit b that cut gate ``cut`` puts on the
+    endpoint in the given half: Eq. 1 (CZ: P_b upper, Z^b lower) or Supp. Eq. 1
+    (controlled-U: P_b on the control, U^b on the target)."""
+    if cut.gate == "cz":
+        return ("p1" if b else "p0") if upper else ("z" if b else "i")
+    on_control = (cut.upper if upper else cut.lower) == cut.control
+    if on_control:
+        return "p1" if b else "p0"
+    return {"cx": "x", "cy": "y"}[cut.gate] if b else "i"
 
 
 def copy_bit(k: int, j: int, c: int) -> int:
@@ -67,8 +83,8 @@ def copy_bit(k: int, j: int, c: int) -> int:
 def half_program(circ: Circuit, upper_mask: int, upper: bool):
     """Ops of one half as (cycle, name, local qubits, cut index or None).
 
-    Cut CZs appear as ``cut`` ops on the half's endpoint; they become P_b on
-    the upper half and Z^b on the lower half once the copy fixes b.
+    Cut gates appear as ``cut`` ops on the half's endpoint; once the copy
+    fixes b they become the factor ``cut_factor`` names (P_b, Z^b or U^b).
     """
     n = circ.n
     full = (1 << n) - 1
@@ -82,21 +98,17 @@ def half_program(circ: Circuit, upper_mask: int, upper: bool):
         inside = [q for q in gq if q in loc]
         if not inside:
             continue
-        if name == "cz" and len(inside) == 1:
+        if len(gq) == 2 and len(inside) == 1:
             prog.append((t, "cut", (loc[inside[0]],), cut_of[(t, inside[0])]))
         else:
             prog.append((t, name, tuple(loc[q] for q in gq), None))
     return len(qs), prog
 
 
-def _apply_op(psi, op, upper: bool, bits: dict) -> None:
+def _apply_op(psi, op, upper: bool, bits: dict, cuts) -> None:
     t, name, lq, j = op
     if name == "cut":
-        b = bits[j]
-        if upper:
-            SV.apply_gate(psi, "p1" if b else "p0", lq)
-        else:
-            SV.apply_gate(psi, "z" if b else "i", lq)
+        SV.apply_gate(psi, cut_factor(cuts[j], upper, bits[j]), lq)
     else:
         SV.apply_gate(psi, name, lq)
 
@@ -104,11 +116,12 @@ def _apply_op(psi, op, upper: bool, bits: dict) -> None:
 def half_state_plain(circ: Circuit, upper_mask: int, upper: bool, k: int) -> np.ndarray:
     """One copy's half state, simulated from scratch (no prefix reuse)."""
     nloc, prog = half_program(circ, upper_mask, upper)
-    c = len(find_cuts(circ, upper_mask))
+    cuts = find_cuts(circ, upper_mask)
+    c = len(cuts)
     bits = {j: copy_bit(k, j, c) for j in range(c)}
     psi = SV.zero_state(nloc)
     for op in prog:
-        _apply_op(psi, op, upper, bits)
+        _apply_op(psi, op, upper, bits, cuts)
     return psi
 
 
@@ -123,7 +136,8 @@ def half_states(circ: Circuit, upper_mask: int, upper: bool, select=None,
     holds cuts into one child per assignment of that layer's cut bits.
     """
     nloc, prog = half_program(circ, upper_mask, upper)
-    c = len(find_cuts(circ, upper_mask))
+    cuts = find_cuts(circ, upper_mask)
+    c = len(cuts)
     total = 1 << c
     if copy_end is None:
         copy_end = total
@@ -154,11 +168,11 @@ def half_states(circ: Circuit, upper_mask: int, upper: bool, select=None,
                         child_bits[j] = (b >> (m - 1 - pos)) & 1
                     child = psi.copy()
                     for op in ops:
-                        _apply_op(child, op, upper, child_bits)
+                        _apply_op(child, op, upper, child_bits, cuts)
                     rec(child, ci + 1, child_bits, nassigned + m)
                 return
             for op in ops:
-                _apply_op(psi, op, upper, bits)
+                _apply_op(psi, op, upper, bits, cuts)
             ci += 1
         k = lo
         out[:, k - copy_begin] = psi[sel]

@@ -48,14 +48,36 @@ def apply_cz(psi: np.ndarray, a: int, b: int) -> None:
     v[:, 1, :, 1, :] *= -1
 
 
+def apply_controlled(psi: np.ndarray, c: int, t: int, u: np.ndarray) -> None:
+    """psi <- (P0 x I + P1 x u) psi on (control c, target t) (Supp. Eq. 1):
+    u acts on the target within the amplitudes whose control bit is 1."""
+    lo, hi = min(c, t), max(c, t)
+    v = _view(psi, -1, 2, 1 << (hi - lo - 1), 2, 1 << lo)
+    # axis 1 holds bit hi, axis 3 bit lo
+    sub = v.select(1, 1) if c == hi else v.select(3, 1)
+    ax = 2 if c == hi else 1  # the target's axis in sub
+    a = sub.select(ax, 0).clone()
+    b = sub.select(ax, 1).clone()
+    m = [[complex(u[i, j]) for j in range(2)] for i in range(2)]
+    sub.select(ax, 0).copy_(m[0][0] * a + m[0][1] * b)
+    sub.select(ax, 1).copy_(m[1][0] * a + m[1][1] * b)
+
+
 def apply_gate(psi: np.ndarray, name: str, qs) -> None:
     """Apply one gate by name.
 
     Besides the circuit gates this accepts the one-qubit factors of the cut
-    identity CZ = P0 x I + P1 x Z (Eq. 1): ``p0``, ``p1``, ``z`` and ``i``.
+    identity CZ = P0 x I + P1 x Z (Eq. 1) and of its controlled-U form (Supp.
+    Eq. 1): ``p0``, ``p1``, ``z``, ``x``, ``y`` and ``i``.
     """
     if name == "cz":
         apply_cz(psi, qs[0], qs[1])
+    elif name in ("cx", "cy"):
+        apply_controlled(psi, qs[0], qs[1], G.CONTROLLED_U[name])
+    elif name == "x":
+        apply_1q(psi, qs[0], G.X)
+    elif name == "y":
+        apply_1q(psi, qs[0], G.Y)
     elif name == "t":
         apply_diag1(psi, qs[0], 1.0, G.T[1, 1])
     elif name == "p0":

@@ -57,6 +57,14 @@ class qs_options(C.Structure):
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1802_06952_amd.build`")
+    # torch ships its own HIP runtime; loaded first, it is the one the library
+    # binds to (same soname).  Loading the library first would put a second
+    # HIP/HSA runtime into a process that later imports torch, and device
+    # allocations then fail.
+    try:
+        import torch  # noqa: F401
+    except ImportError:  # pragma: no cover - torch is part of the image
+        pass
     lib = C.CDLL(LIB_PATH)
     vp, u64p = C.c_void_p, C.POINTER(C.c_uint64)
     lib.qs_last_error.restype = C.c_char_p

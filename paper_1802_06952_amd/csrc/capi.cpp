@@ -856,7 +856,11 @@ qs_status qs_load_circuit(const char* text, size_t len, qs_circuit** out) {
 qs_status qs_circuit_info(const qs_circuit* circ, int* n_qubits, int* n_gates) {
   if (!circ) return fail(QS_ERR_ARG, "null circuit");
   if (n_qubits) *n_qubits = circ->c.n;
-  if (n_gates) *n_gates = (int)circ->c.gates.size();
+  if (n_gates) {
+    int k = 0;
+    for (const Gate& g : circ->c.gates) k += g.aux ? 0 : 1;
+    *n_gates = k;
+  }
   return QS_OK;
 }
 
@@ -895,9 +899,10 @@ qs_status score_cut(const Circuit& circ, uint64_t upper_mask, int n_values, qs_c
   if (up.n > 32 || lo.n > 32) return fail(QS_ERR_ARG, "a half has more than 32 qubits");
   const int c = (int)cuts.size();
   if (c > 40) return fail(QS_ERR_UNSUPPORTED, "more than 40 cut gates");
-  // gates touching each half (a cut CZ touches both)
+  // written gates touching each half (a cut two-qubit gate touches both)
   double g[2] = {0, 0};
   for (const Gate& gt : circ.gates) {
+    if (gt.aux) continue;
     const bool u0 = (upper_mask >> gt.q0) & 1;
     g[u0 ? 0 : 1] += 1;
     if (gt.q1 >= 0) {

@@ -1,5 +1,6 @@
 // Circuit text parser (host).  Format: "qubits <n>", optional "grid <r> <c>",
-// then "<layer> <gate> <q> [<q2>]" per line; '#' starts a comment.
+// then "<layer> <gate> <q> [<q2>]" per line; '#' starts a comment.  Gates: h,
+// sx, sy, t, cz, and the controlled gates cx and cy (control first).
 #include <cctype>
 #include <cstdlib>
 #include <cstring>
@@ -78,6 +79,7 @@ bool parse_circuit(const char* text, size_t len, Circuit& out, std::string& err)
     else if (name == "sy") g.kind = G_SY;
     else if (name == "t") g.kind = G_T;
     else if (name == "cz") { g.kind = G_CZ; want = 2; }
+    else if (name == "cx" || name == "cy") { g.kind = G_CZ; want = 2; }
     else return fail("unknown gate '" + name + "'");
     if ((int)tok.size() != 2 + want) return fail("gate '" + name + "' takes " + std::to_string(want) + " qubit(s)");
     int qv[2] = {-1, -1};
@@ -90,7 +92,20 @@ bool parse_circuit(const char* text, size_t len, Circuit& out, std::string& err)
     }
     g.q0 = qv[0];
     g.q1 = qv[1];
-    c.gates.push_back(g);
+    if (name == "cx" || name == "cy") {
+      // (I x V) CZ (I x V^dagger) on (control q0, target q1), in time order
+      const bool y = name == "cy";
+      Gate h{(int)t, G_H, qv[1], -1};
+      h.aux = true;
+      Gate sdg{(int)t, G_T, qv[1], -1, 6, true}, s2{(int)t, G_T, qv[1], -1, 2, true};
+      if (y) c.gates.push_back(sdg);
+      c.gates.push_back(h);
+      c.gates.push_back(g);
+      c.gates.push_back(h);
+      if (y) c.gates.push_back(s2);
+    } else {
+      c.gates.push_back(g);
+    }
     if (nl == all.size()) break;
   }
   if (!have_n) {

@@ -775,7 +775,7 @@ k_tail_mm(const TailDesc* __restrict__ tdp, const float2* __restrict__ W,
 // node states on FP32 MFMA (three real products per complex one).  The
 // light cone must be on state bits 0..q-1 (x(s, y) = base + y).
 
-constexpr int kFusedRows = 32;
+constexpr int kFusedRows = 32;  // 16 or 32
 constexpr int kFusedDepth = 8;
 constexpr int kFusedPadQ = 2;    // complex padding after each quarter of a row
 constexpr int kFusedPadRow = 28; // more padding per row (row stride = 4 mod 32 complex)
@@ -854,10 +854,12 @@ __device__ __forceinline__ void fused_unit(const TailDesc& T, const float2* __re
   }
 #pragma unroll
   for (int bb = 0; bb < NBT; ++bb) {
-    // LDS row col = w * 8 + ci * 4 + st holds path w J4 + ci J4/2 + ch * 4 + st
+    // LDS row col = w RW + ci kSt + st (RW = rows per wave, kSt = steps of a
+    // chain per chunk) holds path w J4 + ci J4/2 + ch kSt + st
+    constexpr int RW = kFusedRows / 4, kSt = RW / 2;
     const int col = (b0 + bb) * 16 + li;
-    const uint32_t j = (uint32_t)(col >> 3) * J4 + (uint32_t)((col >> 2) & 1) * (J4 / 2) +
-                       (uint32_t)(ch * 4 + (col & 3));
+    const uint32_t j = (uint32_t)(col / RW) * J4 + (uint32_t)((col % RW) / kSt) * (J4 / 2) +
+                       (uint32_t)(ch * kSt + col % kSt);
 #pragma unroll
     for (int e4 = 0; e4 < 4; ++e4) {
       const int rn = at * 16 + 4 * gq + e4;
@@ -933,7 +935,7 @@ k_tail_fused(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
   float2 u[kFusedDepth][RC];
   uint32_t jprev = 0;
   for (int ch = 0; ch < nchunks; ++ch) {
-    // ---- rows of this chunk: wave w, chain ci, step st -> LDS row w * 8 + ci * kSteps + st
+    // ---- rows of this chunk: wave w, chain ci, step st -> LDS row w * kFusedRows / 4 + ci * kSteps + st
     for (int st = 0; st < kSteps; ++st) {
       const uint32_t jl = (uint32_t)(ch * kSteps + st);  // path index inside a chain
       int d0 = -1;  // u[0..d0] still hold
@@ -1003,7 +1005,10 @@ k_tail_fused(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
     // ---- contraction: C[node][col] = sum_y v_node[base + y] W[col][y]; a unit
     // is one 16-node tile with both 16-column tiles (or one, when there are
     // fewer than four node tiles)
-    if (nat >= 4) {
+    if constexpr (kFusedRows == 16) {
+      for (int un = wave; un < nat; un += 4)
+        fused_unit<R, 1>(T, states, base, wl, un, 0, ch, J4, si, s, X);
+    } else if (nat >= 4) {
       for (int un = wave; un < nat; un += 4)
         fused_unit<R, 2>(T, states, base, wl, un, 0, ch, J4, si, s, X);
     } else {

@@ -78,7 +78,7 @@ bool build_partition(const Circuit& c, uint64_t upper_mask, std::vector<Cut>& cu
       } else {
         int a = loc[g.q0];
         if (a < 0) continue;
-        if (g.kind == G_T) ops.push_back(HOp{OP_T, a, -1, -1, 0, g.cycle});
+        if (g.kind == G_T) ops.push_back(HOp{OP_T, a, -1, -1, g.pw, g.cycle});
         else ops.push_back(HOp{OP_MAT, a, -1, -1, g.kind == G_H ? 0 : (g.kind == G_SX ? 1 : 2), g.cycle});
       }
     }
@@ -535,7 +535,7 @@ bool encode_ops(const Side& s, const std::vector<int>& ops, const std::vector<in
         break;
       }
       case OP_T:
-        acc.w[o.q0] += 1;
+        acc.w[o.q0] += o.mat;  // T^mat
         acc.any = true;
         break;
       case OP_CZ: {
@@ -586,8 +586,9 @@ std::string dump_json(const Circuit& c, uint64_t upper_mask, const std::vector<C
     o << "],\"ops\":[";
     for (size_t i = 0; i < s.ops.size(); ++i) {
       const HOp& h = s.ops[i];
-      const char* nm = h.kind == OP_MAT ? (h.mat == 0 ? "h" : h.mat == 1 ? "sx" : "sy")
-                       : h.kind == OP_T ? "t" : h.kind == OP_CZ ? "cz" : "cut";
+      std::string nm = h.kind == OP_MAT ? (h.mat == 0 ? "h" : h.mat == 1 ? "sx" : "sy")
+                       : h.kind == OP_T ? (h.mat == 1 ? "t" : "t" + std::to_string(h.mat))
+                       : h.kind == OP_CZ ? "cz" : "cut";
       o << (i ? "," : "") << "[\"" << nm << "\"," << h.q0 << "," << h.q1 << "," << h.cut << ","
         << h.cycle << "]";
     }

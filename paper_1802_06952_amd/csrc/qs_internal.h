@@ -17,7 +17,9 @@ enum GateKind : uint8_t { G_H = 0, G_SX = 1, G_SY = 2, G_T = 3, G_CZ = 4 };
 struct Gate {
   int cycle;
   GateKind kind;
-  int q0, q1;  // q1 = -1 for one-qubit gates
+  int q0, q1;    // q1 = -1 for one-qubit gates
+  int pw = 1;    // G_T: the gate is T^pw (phase omega^pw on |1>)
+  bool aux = false;  // a basis change added by the controlled-U rewrite (not a written gate)
 };
 
 struct Circuit {
@@ -25,7 +27,15 @@ struct Circuit {
   std::vector<Gate> gates;
 };
 
-// Parse the text format; on error returns false and fills err.
+// Parse the text format; on error returns false and fills err.  A controlled-U
+// with U = X or Y ("cx c t", "cy c t") is stored as a CZ between basis
+// changes on its target: U = V Z V^dagger gives P0 x I + P1 x U (Supp. Eq. 1)
+// = (I x V) CZ (I x V^dagger), with V = H for X and V = S H for Y (S = T^2).
+// Cutting that CZ puts P_b on its upper endpoint and Z^b on its lower one, so
+// a cut controlled-U whose control is in the upper half splits exactly as in
+// Supp. Eq. 1 (the target gets V Z^b V^dagger = U^b); with the control in
+// the lower half the copies are the mirrored split (V P_b V^dagger on the
+// target, Z^b on the control), with the same sum.
 bool parse_circuit(const char* text, size_t len, Circuit& out, std::string& err);
 
 // ---------------------------------------------------------------- partition
@@ -49,7 +59,7 @@ struct HOp {
   OpKind kind;
   int q0, q1;
   int cut;
-  int mat;    // OP_MAT: 0 = H, 1 = sqrt X, 2 = sqrt Y
+  int mat;    // OP_MAT: 0 = H, 1 = sqrt X, 2 = sqrt Y; OP_T: the power of T
   int cycle;
 };
 

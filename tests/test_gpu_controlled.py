@@ -1,0 +1,105 @@
+"""GPU parity for circuits with cut controlled-U gates (Supp. Eq. 1).
+
+The oracle splits a cut controlled-U literally: P_b on the control and U^b on
+the target, in whichever half each lies.  The library stores CNOT and CY as a
+CZ between basis changes on the target, so its copies equal the oracle's
+when every cut gate's control is in the upper half and are the mirrored split
+otherwise; the amplitudes (sums over all copies) agree in every case.  Error
+measure and bounds as in test_gpu_parity: norm-wise relative error, 1e-5 for
+FP32 and 1e-4 for the split-BF16 assembly.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import circuit as OC, partition as P, statevector as SV
+from workloads import circuits as W, product_bitstrings, workload
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TOL = {0: 1e-5, 1: 1e-4}
+
+
+def _lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1802_06952_amd as Q
+    return Q
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def relerr(a, ref):
+    return float(np.linalg.norm(a.astype(np.complex128) - ref) / np.linalg.norm(ref))
+
+
+@pytest.mark.parametrize("two_qubit,orient,seed,prec", [
+    ("cx", "random", 6, 0),
+    ("cy", "random", 5, 0),
+    ("mixed", "random", 2, 1),
+    ("mixed", "low", 3, 0),
+])
+def test_controlled_all_amplitudes(two_qubit, orient, seed, prec):
+    """All 2^20 amplitudes of a 4x5 grid against the full state vector."""
+    Q = _lib()
+    text = W.random_grid_circuit(4, 5, 16, seed, two_qubit, orient)
+    mask = W.grid_rows_mask(4, 5, [0, 1])
+    oc = OC.parse(text)
+    assert any(k.gate != "cz" for k in P.find_cuts(oc, mask))
+    bits = np.arange(1 << 20, dtype=np.uint64)
+    say(f"case controlled {two_qubit} {orient} seed={seed} prec={prec}")
+    p = Q.Plan(text, mask)
+    try:
+        amp, _ = p.amplitudes(bits, prec)
+    finally:
+        p.close()
+    assert relerr(amp, SV.simulate(oc)) < TOL[prec]
+
+
+def test_controlled_per_copy_half_amplitudes():
+    """Controls in the upper half: every copy's half amplitudes equal the
+    oracle's Supp. Eq. 1 split."""
+    Q = _lib()
+    text = W.random_grid_circuit(4, 5, 14, 4, "mixed", "low")
+    mask = W.grid_rows_mask(4, 5, [0, 1])
+    oc = OC.parse(text)
+    bits, uu, ll = product_bitstrings(20, mask, 32, 48, 7, 8)
+    say("case controlled per-copy halves")
+    p = Q.Plan(text, mask)
+    try:
+        total = 1 << p.n_cuts
+        p.run_halves(0, total, bits)
+        got = [p.half_amplitudes(side, 0, total, n) for side, n in ((0, 32), (1, 48))]
+    finally:
+        p.close()
+    A, B = P.gathered_halves(oc, mask, np.sort(uu.astype(np.int64)), np.sort(ll.astype(np.int64)))
+    for g, ref in zip(got, (A, B)):
+        assert relerr(g.T, ref) < 1e-5
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_grid6x6_d16_mixed_golden(prec):
+    """36 qubits with CZ, CNOT and CY drawn per gate and random controls."""
+    Q = _lib()
+    w = workload("grid6x6_d16_mixed")
+    path = os.path.join(GOLDEN, f"{w.name}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    g = np.load(path)
+    bits, u, l = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
+    assert np.array_equal(g["u"], u.astype(np.int64)) and np.array_equal(g["l"], l.astype(np.int64))
+    say(f"case grid6x6_d16_mixed prec={prec}")
+    p = Q.Plan(w.circuit_text(), w.upper_mask)
+    try:
+        amp, _ = p.amplitudes(bits, prec)
+    finally:
+        p.close()
+    assert relerr(amp, g["amp"]) < TOL[prec]

@@ -250,3 +250,81 @@ def test_fig1_example_counts():
     # an 8-qubit example with two cut CZ gates gives 4 copies, 8 half circuits
     # of 4 qubits and N_e = 7 (Sec. 2.1, Sec. 3)
     assert counting.equivalent_qubits(4, 2) == 7
+
+
+# ---------------------------------------------------------------- controlled-U cuts (Supp. Eq. 1)
+
+def test_supp_eq1_controlled_gates():
+    """P0 x I + P1 x U for U = X, Y, Z against the textbook 4x4 matrices in
+    the basis |control target> = 00, 01, 10, 11."""
+    cnot = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], dtype=complex)
+    cy = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, -1j], [0, 0, 1j, 0]])
+    cz = np.diag([1, 1, 1, -1]).astype(complex)
+    for name, ref in (("cx", cnot), ("cy", cy), ("cz", cz)):
+        got = np.kron(G.P0, G.I2) + np.kron(G.P1, G.CONTROLLED_U[name])
+        assert np.array_equal(got, ref), name
+
+
+def test_controlled_gates_in_statevector():
+    """CNOT on |+>|0> is the Bell state; CY maps |1>|0> to i|1>|1>; both are
+    involutions; the target may sit above or below the control."""
+    psi = SV.zero_state(2)
+    SV.apply_gate(psi, "h", (1,))
+    SV.apply_gate(psi, "cx", (1, 0))
+    assert np.allclose(psi, [2 ** -0.5, 0, 0, 2 ** -0.5], atol=1e-15)
+    psi = SV.zero_state(3)
+    SV.apply_gate(psi, "h", (0,))
+    SV.apply_gate(psi, "cx", (0, 2))
+    assert np.allclose(psi[[0, 5]], [2 ** -0.5, 2 ** -0.5], atol=1e-15)
+    psi = np.zeros(4, dtype=complex)
+    psi[0b01] = 1  # control (qubit 0) = 1, target (qubit 1) = 0
+    SV.apply_gate(psi, "cy", (0, 1))
+    assert np.allclose(psi, [0, 0, 0, 1j], atol=1e-15)
+    rng = np.random.default_rng(7)
+    for name in ("cx", "cy"):
+        v = rng.normal(size=32) + 1j * rng.normal(size=32)
+        w = v.copy()
+        SV.apply_gate(w, name, (3, 1))
+        assert not np.allclose(w, v)
+        SV.apply_gate(w, name, (3, 1))
+        assert np.allclose(w, v, atol=1e-14)
+
+
+@pytest.mark.parametrize("two_qubit,seed", [("cx", 0), ("cy", 1), ("mixed", 2)])
+def test_controlled_dense_bruteforce(two_qubit, seed):
+    c = OC.parse(W.random_grid_circuit(3, 3, 12, seed, two_qubit))
+    assert any(g[1] == two_qubit or (two_qubit == "mixed" and g[1] in ("cx", "cy")) for g in c.gates)
+    assert np.allclose(SV.simulate(c), dense.final_state(c), atol=1e-12)
+
+
+@pytest.mark.parametrize("rows,cols,depth,two_qubit,orient,seed,mask", [
+    (4, 4, 12, "cx", "random", 6, W.grid_rows_mask(4, 4, [0, 1])),
+    (4, 4, 12, "cy", "random", 5, W.grid_cols_mask(4, 4, [0, 1])),
+    (3, 5, 14, "mixed", "random", 5, W.grid_rows_mask(3, 5, [0]) | 0b11 << 5),
+    (4, 5, 10, "mixed", "low", 5, W.grid_rows_mask(4, 5, [0, 1])),
+])
+def test_partition_controlled_equals_full_state(rows, cols, depth, two_qubit, orient, seed, mask):
+    """Supp. Eq. 1 cuts (P_b on the control, U^b on the target, either half)
+    summed over copies give the full-state amplitudes."""
+    c = OC.parse(W.random_grid_circuit(rows, cols, depth, seed, two_qubit, orient))
+    cuts = P.find_cuts(c, mask)
+    assert any(k.gate != "cz" for k in cuts)
+    if orient == "random":
+        # both orientations occur among the cut gates
+        sides = {k.control == k.upper for k in cuts if k.gate != "cz"}
+        assert sides == {True, False}
+    n = rows * cols
+    x = np.arange(1 << n)
+    assert np.allclose(P.amplitudes(c, mask, x), SV.simulate(c), atol=1e-12)
+
+
+def test_controlled_prefix_recursion_equals_plain_copies():
+    c = OC.parse(W.random_grid_circuit(3, 4, 12, 6, "mixed"))
+    mask = W.grid_rows_mask(3, 4, [0])
+    ncut = len(P.find_cuts(c, mask))
+    assert ncut >= 3
+    for upper in (True, False):
+        tree = P.half_states(c, mask, upper)
+        for k in range(1 << ncut):
+            plain = P.half_state_plain(c, mask, upper, k)
+            assert np.allclose(tree[:, k], plain, atol=1e-13)

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import paper_1802_06952_amd as Q
-from oracle import circuit as OC, partition as P
+from oracle import circuit as OC, partition as P, statevector as SV
 from workloads import CONFIGS, circuits as W
 
 HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "qs.h")
@@ -96,8 +96,9 @@ def _apply(psi, n, op):
         a0, a1 = psi[i0].copy(), psi[i1].copy()
         psi[i0] = m[0, 0] * a0 + m[0, 1] * a1
         psi[i1] = m[1, 0] * a0 + m[1, 1] * a1
-    elif name == "t":
-        psi *= np.where(_bit(n, q0) == 1, (1 + 1j) * SQ, 1.0)
+    elif name[0] == "t":  # "t" or "t<k>" = T^k
+        k = int(name[1:]) if len(name) > 1 else 1
+        psi *= np.where(_bit(n, q0) == 1, ((1 + 1j) * SQ) ** k, 1.0)
     elif name == "cz":
         psi *= np.where((_bit(n, q0) & _bit(n, q1)) == 1, -1.0, 1.0)
     else:
@@ -171,3 +172,69 @@ def test_tree_schedule_replays_to_oracle(rows, cols, depth, mask):
         got = replay(side, d["cuts"], c)
         ref = P.half_states(oc, mask, upper)
         assert np.max(np.abs(got - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("rows,cols,depth,two_qubit,mask", [
+    (4, 4, 12, "cx", W.grid_rows_mask(4, 4, [0, 1])),
+    (4, 4, 14, "cy", W.grid_rows_mask(4, 4, [0])),
+    (3, 5, 16, "mixed", W.grid_rows_mask(3, 5, [0])),
+])
+def test_controlled_u_schedule_replays_to_oracle(rows, cols, depth, two_qubit, mask):
+    """Controlled-U cuts whose control is in the upper half: every copy of
+    both halves equals the oracle's Supp. Eq. 1 split."""
+    text = W.random_grid_circuit(rows, cols, depth, 4, two_qubit, "low")
+    p = Q.Plan(text, mask)
+    d = p.dump()
+    oc = OC.parse(text)
+    c = p.n_cuts
+    assert [tuple(x) for x in d["cuts"]] == [(k.cycle, k.upper, k.lower) for k in P.find_cuts(oc, mask)]
+    assert any(k.gate != "cz" for k in P.find_cuts(oc, mask))
+    for si, upper in enumerate((True, False)):
+        got = replay(d["sides"][si], d["cuts"], c)
+        ref = P.half_states(oc, mask, upper)
+        assert np.max(np.abs(got - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("two_qubit,mask", [
+    ("cx", W.grid_rows_mask(4, 4, [0, 1])),
+    ("mixed", W.grid_cols_mask(4, 4, [0, 1])),
+])
+def test_controlled_u_any_orientation_sums_to_oracle(two_qubit, mask):
+    """Controls on either side: the copies may differ from the oracle's split
+    (the mirrored one), their sum over copies may not."""
+    text = W.random_grid_circuit(4, 4, 12, 8, two_qubit, "random")
+    p = Q.Plan(text, mask)
+    d = p.dump()
+    oc = OC.parse(text)
+    c = p.n_cuts
+    U = replay(d["sides"][0], d["cuts"], c)
+    L = replay(d["sides"][1], d["cuts"], c)
+    x = np.arange(1 << 16)
+    u = P.pack_bits(x, P.half_qubits(16, mask))
+    lo = P.pack_bits(x, P.half_qubits(16, ((1 << 16) - 1) & ~mask))
+    amp = np.einsum("ik,ik->i", U[u], L[lo])
+    assert np.max(np.abs(amp - SV.simulate(oc))) < 1e-12
+
+
+def test_controlled_u_counts_written_gates():
+    c = Q.qs_load_circuit("qubits 3\n0 h 0\n1 cx 0 1\n2 cy 1 2\n")
+    try:
+        assert Q.qs_circuit_info(c) == (3, 3)
+    finally:
+        Q.qs_circuit_free(c)
+
+
+def test_binding_maps_one_hip_runtime():
+    """Importing the binding first (before torch) still leaves one HIP and one
+    HSA runtime in the process: torch's, which the library binds to."""
+    import subprocess
+    import sys
+    code = ("import paper_1802_06952_amd, torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}),"
+            " len({l.split()[-1] for l in maps if 'libhsa-runtime64' in l}))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["1", "1"]

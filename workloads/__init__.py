@@ -13,6 +13,8 @@ Circuit text format (one gate per line, ``#`` starts a comment)::
     <cycle> sx <q>              # square root of X
     <cycle> sy <q>              # square root of Y
     <cycle> cz <q0> <q1>
+    <cycle> cx <control> <target>   # controlled X (CNOT)
+    <cycle> cy <control> <target>   # controlled Y
 
 Cycles are non-decreasing integers; within a cycle every qubit appears at most
 once, so the gates of one cycle act on disjoint qubits.

@@ -18,13 +18,19 @@ prints no circuit, so the rules below are our reading of them:
 This reading reproduces the CZ counts of Table 2 and the CZ totals of Fig. 4
 exactly.  The one-qubit totals of Fig. 4 are not reproduced exactly (the
 figure, which fixes the pattern order, is missing from the text).
+
+CNOT-style variants (the controlled-U gates of Supp. Eq. 1): with
+``two_qubit`` = "cx" or "cy" every CZ of the pattern becomes that gate, with
+"mixed" each one is drawn from {cz, cx, cy}; ``orient`` = "random" draws
+which endpoint is the control, "low" makes it the smaller qubit id.  These
+draws use a second generator, so the CZ circuits are unchanged.
 """
 
 from __future__ import annotations
 
 import numpy as np
 
-GATE_NAMES = ("h", "t", "sx", "sy", "cz")
+GATE_NAMES = ("h", "t", "sx", "sy", "cz", "cx", "cy")
 
 
 def _hp(rows: int) -> int:
@@ -73,12 +79,16 @@ def cz_pattern(rows: int, cols: int, position: int) -> list[tuple[int, int]]:
     return pairs
 
 
-def random_grid_circuit_gates(rows: int, cols: int, depth: int, seed: int):
+def random_grid_circuit_gates(rows: int, cols: int, depth: int, seed: int,
+                              two_qubit: str = "cz", orient: str = "random"):
     """Return the gate list [(cycle, name, qubits...)] of the seeded circuit."""
     if rows < 2 or cols < 1:
         raise ValueError("grid needs at least 2 rows and 1 column")
+    if two_qubit not in ("cz", "cx", "cy", "mixed") or orient not in ("random", "low"):
+        raise ValueError("two_qubit must be cz, cx, cy or mixed; orient random or low")
     n = rows * cols
     rng = np.random.default_rng(seed)
+    rng2 = np.random.default_rng([seed, 1])
     gates: list[tuple] = [(0, "h", q) for q in range(n)]
     prev_busy: set[int] = set()
     last_1q: dict[int, str] = {}
@@ -96,7 +106,12 @@ def random_grid_circuit_gates(rows: int, cols: int, depth: int, seed: int):
                     last_1q[q] = g
                     gates.append((t, g, q))
         for a, b in pairs:
-            gates.append((t, "cz", a, b))
+            kind = two_qubit
+            if kind == "mixed":
+                kind = ("cz", "cx", "cy")[int(rng2.integers(3))]
+            if kind != "cz" and orient == "random" and int(rng2.integers(2)):
+                a, b = b, a
+            gates.append((t, kind, a, b))
         prev_busy = busy
     return gates
 
@@ -114,11 +129,13 @@ def gates_to_text(n: int, gates, rows: int | None = None, cols: int | None = Non
     return "\n".join(lines) + "\n"
 
 
-def random_grid_circuit(rows: int, cols: int, depth: int, seed: int = 0) -> str:
+def random_grid_circuit(rows: int, cols: int, depth: int, seed: int = 0,
+                        two_qubit: str = "cz", orient: str = "random") -> str:
     """Circuit text of the seeded universal random circuit on a rows x cols grid."""
-    gates = random_grid_circuit_gates(rows, cols, depth, seed)
+    gates = random_grid_circuit_gates(rows, cols, depth, seed, two_qubit, orient)
+    extra = "" if two_qubit == "cz" else f" {two_qubit} {orient}"
     return gates_to_text(rows * cols, gates, rows, cols,
-                         comment=f"random grid circuit {rows}x{cols} depth {depth} seed {seed}")
+                         comment=f"random grid circuit {rows}x{cols} depth {depth} seed {seed}{extra}")
 
 
 def grid_rows_mask(rows: int, cols: int, row_list) -> int:

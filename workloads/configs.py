@@ -28,13 +28,16 @@ class Workload:
     copy_begin: int = 0
     copy_end: int | None = None   # None = all copies
     note: str = ""
+    two_qubit: str = "cz"    # cz, or the controlled gates cx / cy / mixed
+    orient: str = "random"   # which endpoint of a controlled gate is the control
 
     @property
     def n(self) -> int:
         return self.rows * self.cols
 
     def circuit_text(self) -> str:
-        return random_grid_circuit(self.rows, self.cols, self.depth, self.seed)
+        return random_grid_circuit(self.rows, self.cols, self.depth, self.seed,
+                                   self.two_qubit, self.orient)
 
 
 def _all_upper_lower(rows, cols, upper_rows):
@@ -69,6 +72,12 @@ _add(Workload("grid6x8_d22_slice64", 6, 8, 22, 0, grid_rows_mask(6, 8, [0, 1, 2]
 _add(Workload("grid8x8_d22_slice64", 8, 8, 22, 0, grid_rows_mask(8, 8, [0, 1, 2, 3]), 1024, 1024,
               1005, 2005, copy_begin=0, copy_end=64,
               note="64 qubits, 32+32 halves, copies [0, 64) of 65536: partial amplitudes"))
+
+
+_add(Workload("grid6x6_d16_mixed", 6, 6, 16, 0, grid_rows_mask(6, 6, [0, 1, 2]), 256, 256,
+              1007, 2007, two_qubit="mixed", orient="random",
+              note="36 qubits, 18+18 halves, each two-qubit gate drawn from CZ, CNOT and CY with "
+                   "a random control (Supp. Eq. 1 cuts in both orientations)"))
 
 
 def workload(name: str) -> Workload:

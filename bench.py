@@ -80,6 +80,41 @@ def cpu_baseline(w, n_copies: int, n_values: int):
                       f"{dt:.2f} s, scaled by {total}/{k1} copies to the whole job of {m} amplitudes"}
 
 
+def controlled_variant(Q, w, bits, prec, k0, k1, a, stream, d_out, d_sums) -> dict:
+    """Amplitudes/s of the workload's grid, depth, cut and bitstrings with
+    every two-qubit gate drawn from CZ, CNOT and CY and a random control
+    (controlled-U cuts, Supp. Eq. 1)."""
+    import torch
+    from workloads.circuits import random_grid_circuit
+    m = int(bits.size)
+    ctext = random_grid_circuit(w.rows, w.cols, w.depth, w.seed, "mixed", "random")
+    cp = Q.Plan(ctext, w.upper_mask, one_stream=a.one_stream)
+    try:
+        ck1 = k1 if w.copy_end is not None else (1 << cp.n_cuts)
+
+        def cstep(p):
+            cp.reset(keep_bitstrings=True)
+            cp.run_halves(k0, ck1, None, stream)
+            cp.amplitudes_device(p, d_out.data_ptr(), d_sums.data_ptr(), stream)
+
+        cp.run_halves(k0, ck1, bits, stream)
+        cp.amplitudes_device(prec, d_out.data_ptr(), d_sums.data_ptr(), stream)
+        for _ in range(a.warmup):
+            cstep(prec)
+        torch.cuda.synchronize()
+        tc0 = time.perf_counter()
+        for _ in range(a.steps):
+            cstep(prec)
+        torch.cuda.synchronize()
+        cms = (time.perf_counter() - tc0) * 1000.0 / a.steps
+        return {"value": round(m / (cms / 1000.0), 1), "unit": "amplitudes/s",
+                "ms_per_step": round(cms, 4), "cuts": cp.n_cuts,
+                "workload": f"{w.name} with CZ, CNOT and CY drawn per gate, random controls "
+                            f"(same grid, depth, cut and bitstrings)"}
+    finally:
+        cp.close()
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +125,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-controlled", action="store_true",
+                    help="skip the controlled-U variant of the workload (CZ, CNOT and CY mixed)")
     ap.add_argument("--plain-copies", type=int, default=16)
     ap.add_argument("--cpu-copies", type=int, default=256)
     ap.add_argument("--autotune", action="store_true",
@@ -287,6 +324,18 @@ def main() -> int:
         amp_h, _ = hp.amplitudes(bits, prec)
     out["host_api_value"] = round(m / ((time.perf_counter() - th0) / 2), 1)
     hp.close()
+
+    # the same grid, depth, cut and bitstrings with every two-qubit gate drawn
+    # from CZ, CNOT and CY and a random control (controlled-U cuts, Supp. Eq. 1)
+    if not a.no_controlled and w.two_qubit == "cz":
+        try:
+            out["controlled_u"] = controlled_variant(Q, w, bits, prec, k0, k1, a, stream, d_out, d_sums)
+        except Q.QSError as e:  # reported, not fatal: the CZ workload is the metric
+            out["controlled_u"] = {"error": str(e)}
+        # the checked output below is the CZ workload's
+        step(prec)
+        torch.cuda.synchronize()
+
 
     if not a.no_check:
         gpath = os.path.join(ROOT, "tests", "golden", f"{w.name}.npz")

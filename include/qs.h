@@ -220,6 +220,55 @@ qs_status qs_plan_reset(qs_plan* plan, int keep_bitstrings);
 qs_status qs_get_timing(qs_plan* plan, double* out11);
 qs_status qs_set_timing(qs_plan* plan, int enable);
 
+/* ---------------------------------------------------------------- chain partitions
+ *
+ * Partitions into t parts (Sec. 3, Fig. 3): part_masks[0..t-1] are disjoint,
+ * non-empty, at most 32 qubits each and cover the circuit; every cut gate
+ * (a two-qubit gate with its endpoints in two parts) must join parts i and
+ * i+1, as row bands of a grid do.  A cut CZ is rewritten by Eq. (1) with P_b
+ * on its endpoint in the even-numbered part and Z^b on the one in the
+ * odd-numbered part; the 2^c copies are the products of t part circuits and
+ * an amplitude is the sum over copies of the product of the t part
+ * amplitudes, computed as a chain of t - 1 complex FP32 products over the
+ * cut bits that neighbouring parts share.  Each part runs the same kernels as
+ * a half of qs_partition (copy tree, full-state passes, leaf evaluation).
+ * Cut gates are numbered by (layer, endpoint in the lower-numbered part);
+ * part p sees only the cuts of links p-1 and p.
+ *
+ * The plan holds host copies of the circuit and masks and owns its device
+ * buffers; it is not thread-safe.  Errors: QS_ERR_ARG (null pointers, t
+ * outside 2..8, masks that overlap, leave a qubit out, are empty or exceed 32
+ * qubits), QS_ERR_UNSUPPORTED (a cut gate joins parts that are not
+ * neighbours, more than 40 cuts touch one part). */
+typedef struct qs_mplan qs_mplan;
+qs_status qs_partition_chain(const qs_circuit* circ, const uint64_t* part_masks, int t,
+                             const qs_options* opts, qs_mplan** out);
+
+/* *t, part_qubits[p] (t entries) and link_cuts[i] (t - 1 entries: cuts between
+ * parts i and i+1); any of them may be NULL. */
+qs_status qs_chain_info(const qs_mplan* plan, int* t, int* part_qubits, int* link_cuts);
+
+/* Register m >= 1 host bitstrings (bit q = qubit q).  The products run over
+ * the grid of distinct part values, which must stay within 2^28 amplitudes
+ * (QS_ERR_UNSUPPORTED otherwise): product sets over the parts fit best.
+ * Registering a different set on the same plan: QS_ERR_STATE. */
+qs_status qs_chain_register(qs_mplan* plan, const uint64_t* bitstrings, size_t m);
+
+/* All copies of every part, the chain of products, the gather of the m
+ * registered amplitudes into d_out_c64 (2m floats, device) and the FP64 sums
+ * [sum p, sum p^2] into d_out_sums (2 doubles, device, may be NULL), on
+ * hip_stream; asynchronous.  QS_ERR_STATE if nothing is registered. */
+qs_status qs_chain_amplitudes_device(qs_mplan* plan, float* d_out_c64, double* d_out_sums,
+                                     void* hip_stream);
+
+/* Register bitstrings (as qs_chain_register), compute, and copy the amplitudes
+ * to out_c64 (2m floats, host) and, when out_stats is not NULL, [sum p,
+ * 2^n mean p, 2^2n mean p^2] to out_stats; synchronises hip_stream. */
+qs_status qs_chain_amplitudes(qs_mplan* plan, const uint64_t* bitstrings, size_t m,
+                              float* out_c64, double* out_stats, void* hip_stream);
+
+void qs_chain_free(qs_mplan* plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -105,10 +105,11 @@ def half_program(circ: Circuit, upper_mask: int, upper: bool):
     return len(qs), prog
 
 
-def _apply_op(psi, op, upper: bool, bits: dict, cuts) -> None:
+def _apply_op(psi, op, bits: dict, factor) -> None:
+    """Apply one program op; ``factor(j, b)`` names cut j's factor for bit b."""
     t, name, lq, j = op
     if name == "cut":
-        SV.apply_gate(psi, cut_factor(cuts[j], upper, bits[j]), lq)
+        SV.apply_gate(psi, factor(j, bits[j]), lq)
     else:
         SV.apply_gate(psi, name, lq)
 
@@ -121,7 +122,7 @@ def half_state_plain(circ: Circuit, upper_mask: int, upper: bool, k: int) -> np.
     bits = {j: copy_bit(k, j, c) for j in range(c)}
     psi = SV.zero_state(nloc)
     for op in prog:
-        _apply_op(psi, op, upper, bits, cuts)
+        _apply_op(psi, op, bits, lambda j, b: cut_factor(cuts[j], upper, b))
     return psi
 
 
@@ -137,7 +138,15 @@ def half_states(circ: Circuit, upper_mask: int, upper: bool, select=None,
     """
     nloc, prog = half_program(circ, upper_mask, upper)
     cuts = find_cuts(circ, upper_mask)
-    c = len(cuts)
+    return tree_states(nloc, prog, len(cuts), lambda j, b: cut_factor(cuts[j], upper, b),
+                       select, copy_begin, copy_end)
+
+
+def tree_states(nloc: int, prog, c: int, factor, select=None, copy_begin: int = 0,
+                copy_end: int | None = None) -> np.ndarray:
+    """The prefix-reuse recursion of Sec. 2.3.2 over a program with c cut ops
+    (cut j's factor for bit b is ``factor(j, b)``); columns are copies
+    k = sum_j b_j 2^(c-1-j) in [copy_begin, copy_end)."""
     total = 1 << c
     if copy_end is None:
         copy_end = total
@@ -168,11 +177,11 @@ def half_states(circ: Circuit, upper_mask: int, upper: bool, select=None,
                         child_bits[j] = (b >> (m - 1 - pos)) & 1
                     child = psi.copy()
                     for op in ops:
-                        _apply_op(child, op, upper, child_bits, cuts)
+                        _apply_op(child, op, child_bits, factor)
                     rec(child, ci + 1, child_bits, nassigned + m)
                 return
             for op in ops:
-                _apply_op(psi, op, upper, bits, cuts)
+                _apply_op(psi, op, bits, factor)
             ci += 1
         k = lo
         out[:, k - copy_begin] = psi[sel]

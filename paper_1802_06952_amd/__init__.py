@@ -30,7 +30,9 @@ _STATUS = {0: "QS_OK", -1: "QS_ERR_ARG", -2: "QS_ERR_PARSE", -3: "QS_ERR_UNSUPPO
 EXPORTED = ("qs_last_error", "qs_load_circuit", "qs_circuit_info", "qs_circuit_free",
             "qs_partition", "qs_plan_info", "qs_plan_dump", "qs_plan_free", "qs_run_halves",
             "qs_amplitudes", "qs_amplitudes_device", "qs_half_amplitudes", "qs_plan_reset",
-            "qs_get_timing", "qs_set_timing", "qs_score_cut", "qs_choose_cut")
+            "qs_get_timing", "qs_set_timing", "qs_score_cut", "qs_choose_cut",
+            "qs_partition_chain", "qs_chain_info", "qs_chain_register", "qs_chain_amplitudes_device",
+            "qs_chain_amplitudes", "qs_chain_free")
 
 
 class QSError(RuntimeError):
@@ -90,6 +92,14 @@ def _load() -> C.CDLL:
     lib.qs_plan_reset.argtypes = [vp, C.c_int]
     lib.qs_get_timing.argtypes = [vp, C.POINTER(C.c_double)]
     lib.qs_set_timing.argtypes = [vp, C.c_int]
+    lib.qs_partition_chain.argtypes = [vp, u64p, C.c_int, C.POINTER(qs_options), C.POINTER(vp)]
+    lib.qs_chain_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.qs_chain_register.argtypes = [vp, u64p, C.c_size_t]
+    lib.qs_chain_amplitudes_device.argtypes = [vp, vp, vp, vp]
+    lib.qs_chain_amplitudes.argtypes = [vp, u64p, C.c_size_t, C.POINTER(C.c_float),
+                                        C.POINTER(C.c_double), vp]
+    lib.qs_chain_free.argtypes = [vp]
+    lib.qs_chain_free.restype = None
     for name in EXPORTED:
         if name != "qs_last_error" and getattr(lib, name).restype is not None:
             getattr(lib, name).restype = C.c_int
@@ -248,7 +258,91 @@ def qs_get_timing(plan) -> dict:
     return dict(zip(TIMING_FIELDS, out.tolist()))
 
 
+def qs_partition_chain(circ, part_masks, opts: qs_options | None = None) -> C.c_void_p:
+    masks = np.ascontiguousarray(np.asarray(part_masks, dtype=np.uint64))
+    out = C.c_void_p()
+    _check(_lib.qs_partition_chain(circ, masks.ctypes.data_as(C.POINTER(C.c_uint64)), masks.size,
+                                   C.byref(opts) if opts is not None else None, C.byref(out)))
+    return out
+
+
+def qs_chain_info(plan) -> tuple[int, list[int], list[int]]:
+    t = C.c_int()
+    _check(_lib.qs_chain_info(plan, C.byref(t), None, None))
+    pq = (C.c_int * t.value)()
+    lc = (C.c_int * max(1, t.value - 1))()
+    _check(_lib.qs_chain_info(plan, None, pq, lc))
+    return t.value, list(pq), list(lc)[: t.value - 1]
+
+
+def qs_chain_register(plan, bitstrings) -> None:
+    b = _bits(bitstrings)
+    _check(_lib.qs_chain_register(plan, b.ctypes.data_as(C.POINTER(C.c_uint64)), b.size))
+
+
+def qs_chain_amplitudes_device(plan, d_out_ptr: int, d_sums_ptr: int | None = None,
+                               stream=None) -> None:
+    _check(_lib.qs_chain_amplitudes_device(plan, C.c_void_p(d_out_ptr),
+                                           C.c_void_p(d_sums_ptr) if d_sums_ptr else None,
+                                           _stream_handle(stream)))
+
+
+def qs_chain_amplitudes(plan, bitstrings, stream=None):
+    """Returns (amplitudes as complex64 array, stats array of 3 float64)."""
+    b = _bits(bitstrings)
+    out = np.empty(2 * b.size, dtype=np.float32)
+    stats = np.zeros(3, dtype=np.float64)
+    _check(_lib.qs_chain_amplitudes(plan, b.ctypes.data_as(C.POINTER(C.c_uint64)), b.size,
+                                    out.ctypes.data_as(C.POINTER(C.c_float)),
+                                    stats.ctypes.data_as(C.POINTER(C.c_double)),
+                                    _stream_handle(stream)))
+    return out.view(np.complex64), stats
+
+
+def qs_chain_free(plan) -> None:
+    _lib.qs_chain_free(plan)
+
+
 # --------------------------------------------------------------- convenience
+
+
+class ChainPlan:
+    """Owns a circuit handle and a chain-partition plan (t parts)."""
+
+    def __init__(self, circuit_text: str, part_masks, tile_bits: int = 0, tail_max_qubits: int = 0,
+                 materialize_level: int = -1, mem_budget: int = 0):
+        self._circ = qs_load_circuit(circuit_text)
+        opts = qs_options(tile_bits, 0, tail_max_qubits, materialize_level, 0, mem_budget, 1)
+        try:
+            self._plan = qs_partition_chain(self._circ, part_masks, opts)
+        except Exception:
+            qs_circuit_free(self._circ)
+            self._circ = None  # close() must not free it again
+            raise
+        self.t, self.part_qubits, self.link_cuts = qs_chain_info(self._plan)
+
+    def register(self, bitstrings) -> None:
+        qs_chain_register(self._plan, bitstrings)
+
+    def amplitudes(self, bitstrings, stream=None):
+        return qs_chain_amplitudes(self._plan, bitstrings, stream)
+
+    def amplitudes_device(self, d_out_ptr: int, d_sums_ptr: int | None = None, stream=None) -> None:
+        qs_chain_amplitudes_device(self._plan, d_out_ptr, d_sums_ptr, stream)
+
+    def close(self) -> None:
+        if getattr(self, "_plan", None):
+            qs_chain_free(self._plan)
+            self._plan = None
+        if getattr(self, "_circ", None):
+            qs_circuit_free(self._circ)
+            self._circ = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 class Plan:
     """Owns a circuit handle and a plan handle."""
@@ -263,6 +357,7 @@ class Plan:
             self._plan = qs_partition(self._circ, upper_mask, opts)
         except Exception:
             qs_circuit_free(self._circ)
+            self._circ = None  # close() must not free it again
             raise
         self.n_upper, self.n_lower, self.n_cuts = qs_plan_info(self._plan)
 

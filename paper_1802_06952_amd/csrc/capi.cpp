@@ -193,6 +193,7 @@ struct qs_plan {
   uint32_t* d_vals[2] = {nullptr, nullptr};
   int* d_idx[2] = {nullptr, nullptr};
   bool list_mode = false;  // bitstrings far from a product set: per-bitstring sums
+  bool part_mode = false;  // one part of a chain partition (qs_mplan): side 0 only
   double phi[2][2] = {{1, 0}, {1, 0}};  // per half: the constant of its unit-entry gates (Prepared)
   std::vector<BlockRes> blocks;
   std::vector<std::pair<uint64_t, uint64_t>> ranges;
@@ -470,7 +471,8 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   td.ldx = 1 << (c - blk.p);  // row stride of X[s][nu]: the block's copies
   // lower half, product-set assembly: write only the copies with end bits 0
   // (the assembly folds the end cuts' signs into the upper operand)
-  td.end_base = (!s.upper && !P->list_mode && !P->opts.plain && td.n_end >= 1 && td.n_end <= 4 &&
+  td.end_base = (!s.upper && !P->list_mode && !P->opts.plain && !P->part_mode && td.n_end >= 1 &&
+                 td.n_end <= 4 &&
                  (td.ldx >> td.n_end) >= 1)
                     ? 1
                     : 0;
@@ -1322,6 +1324,291 @@ qs_status qs_set_timing(qs_plan* plan, int enable) {
   plan->timing = enable != 0;
   for (int i = 0; i < 4; ++i) plan->tms[i] = plan->counts[i] = 0;
   plan->pass_bytes = plan->gemm_flops = plan->tail_flops = 0;
+  return QS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ chain partitions
+//
+// t parts whose cut gates each join parts i and i+1 (Sec. 3, Fig. 3).  A cut
+// CZ puts P_b on its endpoint in the even-numbered part and Z^b on the one in
+// the odd-numbered part, so every part carries one kind of cut factor and
+// runs as side 0 of a one-sided plan over its own cuts (numbered in cut
+// order).  Part p's output X_p[v][k] (value v, local copy k) is permuted to
+// the column order (k_p major, k_{p-1} minor), k_i the bits of link i's
+// cuts; the sum over copies is then a chain of t - 1 products:
+//   T_0 = X_0,  T_p[(v_0..v_p)][k_p] = sum_{k_{p-1}} T_{p-1}[(v_0..v_{p-1})][k_{p-1}]
+//                                        X_p[v_p][k_p][k_{p-1}],
+//   amp[(v_0..v_{t-2})][v_{t-1}] = sum_k T_{t-2}[..][k] X_{t-1}[v_{t-1}][k].
+
+struct qs_mplan {
+  Circuit circ;
+  int t = 0;
+  std::vector<uint64_t> masks;
+  std::vector<int> link_c;                       // cuts of link i (parts i, i+1)
+  std::vector<std::unique_ptr<qs_plan>> parts;   // one-sided plans
+  std::vector<std::vector<int>> link_of;         // per part, per local cut: its link
+  Pool pool;
+  bool registered = false;
+  std::vector<uint64_t> bits;
+  std::vector<int> nvals;
+  int* d_iu = nullptr;   // grid row of each bitstring (values of parts 0..t-2)
+  int* d_il = nullptr;   // value index in the last part
+  std::vector<uint32_t*> d_perm;  // per part: natural column of each ordered column
+  ~qs_mplan() {
+    (void)hipDeviceSynchronize();
+    for (uint32_t* q : d_perm)
+      if (q) (void)hipFree(q);
+    pool.release_all();
+  }
+};
+
+extern "C" {
+
+qs_status qs_partition_chain(const qs_circuit* circ, const uint64_t* part_masks, int t,
+                             const qs_options* opts, qs_mplan** out) {
+  if (!circ || !part_masks || !out) return fail(QS_ERR_ARG, "null pointer");
+  if (t < 2 || t > 8) return fail(QS_ERR_ARG, "t must be 2..8 parts");
+  const Circuit& c = circ->c;
+  const int n = c.n;
+  const uint64_t full = n == 64 ? ~0ULL : ((1ULL << n) - 1);
+  std::vector<int> owner(n, -1);
+  uint64_t seen = 0;
+  for (int p = 0; p < t; ++p) {
+    const uint64_t m = part_masks[p];
+    if (m == 0 || (m & ~full) || (m & seen)) return fail(QS_ERR_ARG, "parts must be non-empty and disjoint");
+    if (__builtin_popcountll(m) > 32) return fail(QS_ERR_ARG, "a part has more than 32 qubits");
+    seen |= m;
+    for (int q = 0; q < n; ++q)
+      if ((m >> q) & 1) owner[q] = p;
+  }
+  if (seen != full) return fail(QS_ERR_ARG, "the parts must cover every qubit");
+  // cut gates in cut order: (cycle, endpoint in the lower-numbered part)
+  std::vector<std::tuple<int, int, int, int>> raw;  // cycle, q_lo, q_hi, link
+  for (const Gate& g : c.gates) {
+    if (g.kind != G_CZ || owner[g.q0] == owner[g.q1]) continue;
+    int a = g.q0, b = g.q1;
+    if (owner[a] > owner[b]) std::swap(a, b);
+    if (owner[b] != owner[a] + 1)
+      return fail(QS_ERR_UNSUPPORTED, "the parts do not form a chain (a cut gate skips a part)");
+    raw.emplace_back(g.cycle, a, b, owner[a]);
+  }
+  std::sort(raw.begin(), raw.end());
+  std::unique_ptr<qs_mplan> mp(new (std::nothrow) qs_mplan());
+  if (!mp) return fail(QS_ERR_OOM, "host allocation");
+  mp->circ = c;
+  mp->t = t;
+  mp->masks.assign(part_masks, part_masks + t);
+  mp->link_c.assign(t - 1, 0);
+  for (auto& r : raw) ++mp->link_c[std::get<3>(r)];
+  mp->link_of.resize(t);
+  mp->d_perm.assign(t, nullptr);
+  for (int p = 0; p < t; ++p) {
+    std::unique_ptr<qs_plan> pp(new (std::nothrow) qs_plan());
+    if (!pp) return fail(QS_ERR_OOM, "host allocation");
+    pp->circ = c;
+    pp->upper_mask = part_masks[p];
+    pp->part_mode = true;
+    if (opts) pp->opts = *opts;
+    else {
+      pp->opts = qs_options{};
+      pp->opts.materialize_level = -1;
+    }
+    pp->opts.one_stream = 1;
+    std::map<std::pair<int, int>, int> cut_of;
+    for (auto& r : raw) {
+      const int link = std::get<3>(r);
+      if (link != p && link != p - 1) continue;
+      const int q = link == p ? std::get<1>(r) : std::get<2>(r);  // this part's endpoint
+      const int j = (int)pp->cuts.size();
+      pp->cuts.push_back(Cut{j, std::get<0>(r), q, q});
+      cut_of[{std::get<0>(r), q}] = j;
+      mp->link_of[p].push_back(link);
+    }
+    if (pp->cuts.size() > 40) return fail(QS_ERR_UNSUPPORTED, "more than 40 cut gates on one part");
+    build_side(c, part_masks[p], p % 2 == 0, cut_of, pp->side[0]);
+    pp->side[1] = Side();
+    pp->side[1].upper = false;
+    mp->parts.push_back(std::move(pp));
+  }
+  *out = mp.release();
+  return QS_OK;
+}
+
+qs_status qs_chain_info(const qs_mplan* mp, int* t, int* part_qubits, int* link_cuts) {
+  if (!mp) return fail(QS_ERR_ARG, "null plan");
+  if (t) *t = mp->t;
+  for (int p = 0; p < mp->t; ++p) {
+    if (part_qubits) part_qubits[p] = mp->parts[p]->side[0].n;
+    if (link_cuts && p + 1 < mp->t) link_cuts[p] = mp->link_c[p];
+  }
+  return QS_OK;
+}
+
+void qs_chain_free(qs_mplan* mp) { delete mp; }
+
+qs_status qs_chain_register(qs_mplan* mp, const uint64_t* bits, size_t m) {
+  if (!mp || !bits || m == 0) return fail(QS_ERR_ARG, "no bitstrings");
+  if (mp->registered) {
+    if (m == mp->bits.size() && std::memcmp(bits, mp->bits.data(), m * 8) == 0) return QS_OK;
+    return fail(QS_ERR_STATE, "bitstrings differ from the registered set");
+  }
+  const int t = mp->t;
+  const int n = mp->circ.n;
+  const uint64_t full = n == 64 ? ~0ULL : ((1ULL << n) - 1);
+  for (size_t i = 0; i < m; ++i)
+    if (bits[i] & ~full) return fail(QS_ERR_ARG, "bitstring has bits set beyond the qubit count");
+  std::vector<std::vector<int>> idx(t, std::vector<int>(m));
+  mp->nvals.assign(t, 0);
+  double grid = 1, tmax = 0;
+  for (int p = 0; p < t; ++p) {
+    const Side& s = mp->parts[p]->side[0];
+    std::vector<uint32_t> hv(m);
+    for (size_t i = 0; i < m; ++i) {
+      uint32_t v = 0;
+      for (int q = 0; q < s.n; ++q) v |= (uint32_t)((bits[i] >> s.qubits[q]) & 1) << q;
+      hv[i] = v;
+    }
+    std::vector<uint32_t> u(hv);
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    for (size_t i = 0; i < m; ++i)
+      idx[p][i] = (int)(std::lower_bound(u.begin(), u.end(), hv[i]) - u.begin());
+    mp->nvals[p] = (int)u.size();
+    mp->parts[p]->vals[0] = std::move(u);
+    grid *= mp->nvals[p];
+    if (p + 1 < t) tmax = std::max(tmax, grid * std::ldexp(1.0, mp->link_c[p]));
+  }
+  // the products run over the whole grid of part values
+  if (std::max(grid, tmax) > (double)(1u << 28))
+    return fail(QS_ERR_UNSUPPORTED, "the part values span a grid above 2^28 amplitudes");
+  std::vector<int> iu(m), il(m);
+  for (size_t i = 0; i < m; ++i) {
+    size_t r = 0;
+    for (int p = 0; p + 1 < t; ++p) r = r * mp->nvals[p] + idx[p][i];
+    iu[i] = (int)r;
+    il[i] = idx[t - 1][i];
+  }
+  (void)hipDeviceSynchronize();
+  mp->pool.settle();
+  int* a = (int*)mp->pool.get(m * sizeof(int), nullptr);
+  int* b = (int*)mp->pool.get(m * sizeof(int), nullptr);
+  if (!a || !b) return fail(QS_ERR_OOM, "value tables");
+  HIPCHECK(hipMemcpy(a, iu.data(), m * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(b, il.data(), m * sizeof(int), hipMemcpyHostToDevice));
+  mp->d_iu = a;
+  mp->d_il = b;
+  mp->bits.assign(bits, bits + m);
+  mp->registered = true;
+  return QS_OK;
+}
+
+qs_status qs_chain_amplitudes_device(qs_mplan* mp, float* d_out_c64, double* d_out_sums,
+                                     void* hip_stream) {
+  if (!mp || !d_out_c64) return fail(QS_ERR_ARG, "null pointer");
+  if (!mp->registered) return fail(QS_ERR_STATE, "no bitstrings registered");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int t = mp->t;
+  std::vector<float2*> Y(t, nullptr);
+  double phr = 1, phi = 0;
+  for (int p = 0; p < t; ++p) {
+    qs_plan* pp = mp->parts[p].get();
+    const int cp = (int)pp->cuts.size();
+    const size_t K = (size_t)1 << cp;
+    const int S = mp->nvals[p];
+    Prepared* pr = nullptr;
+    qs_status s = prepare_side(pp, 0, Block{}, &pr);
+    if (s != QS_OK) return s;
+    const double a = pp->phi[0][0], b = pp->phi[0][1];
+    const double r0 = phr * a - phi * b, i0 = phr * b + phi * a;
+    phr = r0;
+    phi = i0;
+    float2* X = (float2*)pp->pool.get((size_t)S * K * sizeof(float2), st);
+    float2* O = (float2*)mp->pool.get((size_t)S * K * sizeof(float2), st);
+    if (!X || !O) return fail(QS_ERR_OOM, "part amplitudes");
+    s = run_side(pp, 0, *pr, X, st);
+    if (s != QS_OK) return s;
+    if (!mp->d_perm[p]) {
+      // ordered column (k of the later link major, the earlier link minor) of
+      // every natural column nu
+      const std::vector<int>& lk = mp->link_of[p];
+      std::vector<uint32_t> perm(K);
+      for (size_t nu = 0; nu < K; ++nu) {
+        const uint32_t k = pr->nu_to_k[nu];
+        uint32_t hi = 0, lo = 0;
+        for (int j = 0; j < cp; ++j) {
+          const uint32_t bit = (k >> (cp - 1 - j)) & 1;
+          if (lk[j] == p) hi = (hi << 1) | bit;
+          else lo = (lo << 1) | bit;
+        }
+        const int nlo = p > 0 ? mp->link_c[p - 1] : 0;
+        perm[((size_t)hi << nlo) | lo] = (uint32_t)nu;
+      }
+      uint32_t* d = nullptr;
+      HIPCHECK(hipMalloc(&d, K * sizeof(uint32_t)));
+      HIPCHECK(hipMemcpy(d, perm.data(), K * sizeof(uint32_t), hipMemcpyHostToDevice));
+      mp->d_perm[p] = d;
+    }
+    HIPCHECK(launch_permute_cols(X, O, mp->d_perm[p], S, (int)K, st));
+    pp->pool.put(X, st);
+    Y[p] = O;
+  }
+  // the chain of products
+  float2* T = Y[0];
+  size_t R = (size_t)mp->nvals[0];
+  bool own_t = false;
+  for (int p = 1; p < t; ++p) {
+    const int Kc = 1 << mp->link_c[p - 1];
+    const bool last = p == t - 1;
+    const size_t N = last ? (size_t)mp->nvals[p] : (size_t)mp->nvals[p] << mp->link_c[p];
+    float2* C = (float2*)mp->pool.get(R * N * sizeof(float2), st);
+    void* work = mp->pool.get(std::max<size_t>(256, zgemm_workspace_bytes(0, (int)R, (int)N, Kc)), st);
+    if (!C || !work) return fail(QS_ERR_OOM, "chain products");
+    HIPCHECK(launch_zgemm_tn(0, (int)R, (int)N, Kc, T, Kc, Y[p], Kc, C, (int)N, 0, work, st));
+    mp->pool.put(work, st);
+    if (own_t || p == 1) mp->pool.put(T, st);
+    mp->pool.put(Y[p], st);
+    T = C;
+    own_t = true;
+    if (!last) R *= (size_t)mp->nvals[p];
+  }
+  const size_t m = mp->bits.size();
+  const int nl = mp->nvals[t - 1];
+  HIPCHECK(launch_gather_amps(T, nl, mp->d_iu, mp->d_il, m, (float2*)d_out_c64,
+                              make_float2((float)phr, (float)phi), st));
+  const int nb = prob_partial_blocks(m);
+  double* part = (double*)mp->pool.get((2 * (size_t)nb + 2) * sizeof(double), st);
+  if (!part) return fail(QS_ERR_OOM, "probability sums");
+  HIPCHECK(launch_prob_sums((const float2*)d_out_c64, m, part, d_out_sums ? d_out_sums : part + 2 * nb, st));
+  mp->pool.put(part, st);
+  mp->pool.put(T, st);
+  return QS_OK;
+}
+
+qs_status qs_chain_amplitudes(qs_mplan* mp, const uint64_t* bits, size_t m, float* out_c64,
+                              double* out_stats, void* hip_stream) {
+  if (!mp || !bits || !out_c64) return fail(QS_ERR_ARG, "null pointer");
+  qs_status s = qs_chain_register(mp, bits, m);
+  if (s != QS_OK) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  float2* amps = (float2*)mp->pool.get(m * sizeof(float2), st);
+  double* sums = (double*)mp->pool.get(2 * sizeof(double), st);
+  if (!amps || !sums) return fail(QS_ERR_OOM, "output buffers");
+  s = qs_chain_amplitudes_device(mp, (float*)amps, sums, hip_stream);
+  if (s != QS_OK) return s;
+  HIPCHECK(hipMemcpyAsync(out_c64, amps, m * sizeof(float2), hipMemcpyDeviceToHost, st));
+  double h[2];
+  HIPCHECK(hipMemcpyAsync(h, sums, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  if (out_stats) {
+    const int n = mp->circ.n;
+    out_stats[0] = h[0];
+    out_stats[1] = std::ldexp(h[0] / (double)m, n);
+    out_stats[2] = std::ldexp(h[1] / (double)m, 2 * n);
+  }
+  mp->pool.put(amps, st);
+  mp->pool.put(sums, st);
   return QS_OK;
 }
 

@@ -54,11 +54,17 @@ bool build_partition(const Circuit& c, uint64_t upper_mask, std::vector<Cut>& cu
     cut_of[{k.cycle, k.upper}] = k.index;
     cut_of[{k.cycle, k.lower}] = k.index;
   }
-  for (int sidx = 0; sidx < 2; ++sidx) {
-    Side& s = sidx == 0 ? up : lo;
-    uint64_t mask = sidx == 0 ? upper_mask : lower_mask;
+  build_side(c, upper_mask, true, cut_of, up);
+  build_side(c, lower_mask, false, cut_of, lo);
+  return true;
+}
+
+void build_side(const Circuit& c, uint64_t mask, bool upper,
+                const std::map<std::pair<int, int>, int>& cut_of, Side& s) {
+  const int n = c.n;
+  {
     s = Side();
-    s.upper = sidx == 0;
+    s.upper = upper;
     std::vector<int> loc(n, -1);
     for (int q = 0; q < n; ++q)
       if ((mask >> q) & 1) {
@@ -73,7 +79,7 @@ bool build_partition(const Circuit& c, uint64_t upper_mask, std::vector<Cut>& cu
         if (a >= 0 && b >= 0) ops.push_back(HOp{OP_CZ, a, b, -1, 0, g.cycle});
         else if (a >= 0 || b >= 0) {
           int q = a >= 0 ? g.q0 : g.q1;
-          ops.push_back(HOp{OP_CUT, loc[q], -1, cut_of[{g.cycle, q}], 0, g.cycle});
+          ops.push_back(HOp{OP_CUT, loc[q], -1, cut_of.at({g.cycle, q}), 0, g.cycle});
         }
       } else {
         int a = loc[g.q0];
@@ -95,7 +101,6 @@ bool build_partition(const Circuit& c, uint64_t upper_mask, std::vector<Cut>& cu
       if (!fold) s.ops.push_back(o);
     }
   }
-  return true;
 }
 
 Tree build_tree(const Side& s, int c, const Block& blk) {

@@ -5,6 +5,7 @@
 #pragma once
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,14 @@ namespace qs {
 // Cuts of E_int in cut order and the two half programs.
 bool build_partition(const Circuit& c, uint64_t upper_mask, std::vector<Cut>& cuts, Side& up,
                      Side& lo, std::string& err);
+
+// The program of the qubits in `mask` (ascending ids are the local qubits):
+// gates inside the set as ops, gates with one endpoint inside as OP_CUT ops
+// whose cut index is cut_of[(cycle, endpoint)]; `upper` gives the cut
+// factors' kind (P_b when true, Z^b when false).  Leading H gates fold into
+// the initial product state.
+void build_side(const Circuit& c, uint64_t mask, bool upper,
+                const std::map<std::pair<int, int>, int>& cut_of, Side& s);
 
 // A block of copies: cut j < p is fixed to bit (k0 >> (c-1-j)) & 1, the rest are free.
 struct Block {

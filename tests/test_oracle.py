@@ -328,3 +328,42 @@ def test_controlled_prefix_recursion_equals_plain_copies():
         for k in range(1 << ncut):
             plain = P.half_state_plain(c, mask, upper, k)
             assert np.allclose(tree[:, k], plain, atol=1e-13)
+
+
+# ---------------------------------------------------------------- partitions into t parts (Sec. 3, Fig. 3)
+
+def _bands(rows, cols, bands):
+    return [W.grid_rows_mask(rows, cols, b) for b in bands]
+
+
+@pytest.mark.parametrize("rows,cols,depth,bands,two_qubit", [
+    (6, 3, 10, [[0, 1], [2, 3], [4, 5]], "cz"),
+    (8, 2, 12, [[0, 1], [2, 3], [4, 5], [6, 7]], "cz"),
+    (6, 3, 10, [[0], [1, 2, 3], [4, 5]], "mixed"),
+])
+def test_multipart_equals_full_state(rows, cols, depth, bands, two_qubit):
+    from oracle import multipart as MP
+    c = OC.parse(W.random_grid_circuit(rows, cols, depth, 1, two_qubit))
+    masks = _bands(rows, cols, bands)
+    cuts = MP.chain_cuts(c, masks)
+    assert {k.lo_part for k in cuts} == set(range(len(bands) - 1))  # every link is cut
+    x = np.random.default_rng(3).integers(0, 1 << (rows * cols), size=2000)
+    assert np.allclose(MP.amplitudes(c, masks, x), SV.simulate(c)[x], atol=1e-12)
+
+
+def test_multipart_two_parts_is_the_two_part_scheme():
+    """t = 2: part 0 carries P_b, part 1 Z^b, copy for copy as in Sec. 2.1."""
+    from oracle import multipart as MP
+    c = circ(4, 4, 12, 2)
+    m = W.grid_rows_mask(4, 4, [0, 1])
+    for p, upper in ((0, True), (1, False)):
+        assert np.array_equal(MP.part_states(c, [m, 0xFFFF & ~m], p), P.half_states(c, m, upper))
+
+
+def test_multipart_rejects_non_chains():
+    from oracle import multipart as MP
+    c = circ(6, 3, 10, 1)
+    with pytest.raises(ValueError, match="chain"):
+        MP.chain_cuts(c, _bands(6, 3, [[0, 1], [4, 5], [2, 3]]))
+    with pytest.raises(ValueError):
+        MP.chain_cuts(c, _bands(6, 3, [[0, 1], [2, 3]]))  # qubits left out

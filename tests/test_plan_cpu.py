@@ -238,3 +238,19 @@ def test_binding_maps_one_hip_runtime():
                          timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.split() == ["1", "1"]
+
+
+def test_failed_partition_frees_the_circuit_once():
+    """A plan whose partition is rejected releases its circuit exactly once
+    (a second release would corrupt the heap of this process)."""
+    import gc
+    text = W.random_grid_circuit(6, 4, 12, 1)
+    for _ in range(3):
+        with pytest.raises(Q.QSError):
+            Q.Plan(text, 0)
+        with pytest.raises(Q.QSError):
+            Q.ChainPlan(text, [W.grid_rows_mask(6, 4, b) for b in ([0, 1], [4, 5], [2, 3])])
+        gc.collect()
+    p = Q.Plan(text, W.grid_rows_mask(6, 4, [0, 1, 2]))
+    assert p.n_cuts > 0
+    p.close()

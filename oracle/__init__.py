@@ -20,6 +20,12 @@ Contents (each function cites the passage it follows):
                      over copies of upper times lower amplitudes.
 * ``counting``    -- cut counts, equivalent qubits (Table 2) and the time
                      estimate of Eq. (2) (Table 1).
+* ``multipart``   -- partitions into t parts in a chain (Sec. 3, Fig. 3): the
+                     sum over all copies of the product of t part amplitudes.
+
+Controlled-U gates (Supp. Eq. 1, U = X or Y) are applied directly in
+``statevector`` and ``dense`` and, when cut, split as P_b on the control and
+U^b on the target in ``partition`` and ``multipart``.
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test
 against a value or property the paper or the mathematics fixes (see the

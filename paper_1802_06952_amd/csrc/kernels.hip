@@ -776,6 +776,8 @@ k_tail_mm(const TailDesc* __restrict__ tdp, const float2* __restrict__ W,
 // light cone must be on state bits 0..q-1 (x(s, y) = base + y).
 
 constexpr int kFusedRows = 32;  // 16 or 32
+constexpr int kFusedWaves = 4;  // waves per workgroup (4 or 8)
+constexpr int kFusedThreads = 64 * kFusedWaves;
 constexpr int kFusedDepth = 8;
 constexpr int kFusedPadQ = 2;    // complex padding after each quarter of a row
 constexpr int kFusedPadRow = 28; // more padding per row (row stride = 4 mod 32 complex)
@@ -855,8 +857,8 @@ __device__ __forceinline__ void fused_unit(const TailDesc& T, const float2* __re
 #pragma unroll
   for (int bb = 0; bb < NBT; ++bb) {
     // LDS row col = w RW + ci kSt + st (RW = rows per wave, kSt = steps of a
-    // chain per chunk) holds path w J4 + ci J4/2 + ch kSt + st
-    constexpr int RW = kFusedRows / 4, kSt = RW / 2;
+    // chain per chunk) holds path w J4 + ci J4/2 + ch kSt + st (J4: paths per wave)
+    constexpr int RW = kFusedRows / kFusedWaves, kSt = RW / 2;
     const int col = (b0 + bb) * 16 + li;
     const uint32_t j = (uint32_t)(col / RW) * J4 + (uint32_t)((col % RW) / kSt) * (J4 / 2) +
                        (uint32_t)(ch * kSt + col % kSt);
@@ -896,7 +898,7 @@ bool tail_fused_ok(const TailDesc& h) {
 }
 
 template <int R>
-__global__ void __launch_bounds__(kTailThreads)
+__global__ void __launch_bounds__(kFusedThreads)
 k_tail_fused(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
              const float2* __restrict__ states, const uint32_t* __restrict__ svals, int s0,
              float2* __restrict__ X) {
@@ -926,16 +928,16 @@ k_tail_fused(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
 #pragma unroll
   for (int r = 0; r < RC; ++r) c.xs[r] = base | (uint32_t)(lane + 64 * (r % R));
   const int nlev = T.nlev, M = T.M;
-  const uint32_t J4 = 1u << (M - 2);  // paths per wave
-  const uint32_t JC = J4 / C;         // paths per chain
+  const uint32_t J4 = (1u << M) / kFusedWaves;  // paths per wave
+  const uint32_t JC = J4 / C;                    // paths per chain
   const uint32_t jw = (uint32_t)wave * J4;
-  constexpr int kSteps = kFusedRows / 4 / C;  // steps of a chain per chunk
+  constexpr int kSteps = kFusedRows / kFusedWaves / C;  // steps of a chain per chunk
   const int nchunks = (int)(JC / kSteps);
   const int nat = (T.n_nodes + 15) >> 4;
   float2 u[kFusedDepth][RC];
   uint32_t jprev = 0;
   for (int ch = 0; ch < nchunks; ++ch) {
-    // ---- rows of this chunk: wave w, chain ci, step st -> LDS row w * kFusedRows / 4 + ci * kSteps + st
+    // ---- rows of this chunk: wave w, chain ci, step st -> LDS row w * rows per wave + ci * kSteps + st
     for (int st = 0; st < kSteps; ++st) {
       const uint32_t jl = (uint32_t)(ch * kSteps + st);  // path index inside a chain
       int d0 = -1;  // u[0..d0] still hold
@@ -987,7 +989,7 @@ k_tail_fused(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
               const int b = (int)((j >> L.pos) & ((1u << L.m) - 1u));
               uint32_t cmask, cval, zmask;
               cut_factors(L.bq, L.m, b, T.upper, cmask, cval, zmask);
-              float2* row = wl + (wave * (kFusedRows / 4) + ci * kSteps + st) * RS;
+              float2* row = wl + (wave * (kFusedRows / kFusedWaves) + ci * kSteps + st) * RS;
 #pragma unroll
               for (int r = 0; r < R; ++r) {
                 float2 a = u[D][ci * R + r];
@@ -1006,13 +1008,13 @@ k_tail_fused(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
     // is one 16-node tile with both 16-column tiles (or one, when there are
     // fewer than four node tiles)
     if constexpr (kFusedRows == 16) {
-      for (int un = wave; un < nat; un += 4)
+      for (int un = wave; un < nat; un += kFusedWaves)
         fused_unit<R, 1>(T, states, base, wl, un, 0, ch, J4, si, s, X);
-    } else if (nat >= 4) {
-      for (int un = wave; un < nat; un += 4)
+    } else if (nat >= kFusedWaves) {
+      for (int un = wave; un < nat; un += kFusedWaves)
         fused_unit<R, 2>(T, states, base, wl, un, 0, ch, J4, si, s, X);
     } else {
-      for (int un = wave; un < 2 * nat; un += 4)
+      for (int un = wave; un < 2 * nat; un += kFusedWaves)
         fused_unit<R, 1>(T, states, base, wl, un >> 1, un & 1, ch, J4, si, s, X);
     }
     __syncthreads();
@@ -1030,7 +1032,7 @@ hipError_t launch_tail(const TailDesc& h, const TailDesc* d_desc, const DevOp* d
   if (h.fused) {
     const int R = 1 << (h.q - 6);
     if (!tail_fused_ok(h)) return hipErrorInvalidValue;
-    dim3 g((unsigned)ns), b(kTailThreads);
+    dim3 g((unsigned)ns), b(kFusedThreads);
     switch (R) {
       case 1:
         hipLaunchKernelGGL(k_tail_fused<1>, g, b, 0, st, d_desc, d_ops, states, svals, s0, X);

@@ -239,7 +239,8 @@ qs_status qs_set_timing(qs_plan* plan, int enable);
  * buffers; it is not thread-safe.  Errors: QS_ERR_ARG (null pointers, t
  * outside 2..8, masks that overlap, leave a qubit out, are empty or exceed 32
  * qubits), QS_ERR_UNSUPPORTED (a cut gate joins parts that are not
- * neighbours, more than 40 cuts touch one part). */
+ * neighbours, more than 30 cuts touch one part: a part's 2^c_p copies run as
+ * one block). */
 typedef struct qs_mplan qs_mplan;
 qs_status qs_partition_chain(const qs_circuit* circ, const uint64_t* part_masks, int t,
                              const qs_options* opts, qs_mplan** out);

@@ -1335,12 +1335,16 @@ qs_status qs_set_timing(qs_plan* plan, int enable) {
 // CZ puts P_b on its endpoint in the even-numbered part and Z^b on the one in
 // the odd-numbered part, so every part carries one kind of cut factor and
 // runs as side 0 of a one-sided plan over its own cuts (numbered in cut
-// order).  Part p's output X_p[v][k] (value v, local copy k) is permuted to
-// the column order (k_p major, k_{p-1} minor), k_i the bits of link i's
-// cuts; the sum over copies is then a chain of t - 1 products:
-//   T_0 = X_0,  T_p[(v_0..v_p)][k_p] = sum_{k_{p-1}} T_{p-1}[(v_0..v_{p-1})][k_{p-1}]
-//                                        X_p[v_p][k_p][k_{p-1}],
-//   amp[(v_0..v_{t-2})][v_{t-1}] = sum_k T_{t-2}[..][k] X_{t-1}[v_{t-1}][k].
+// order).  With k_i the bits of link i's cuts, the sum over copies is a
+// chain of t - 1 products contracted from both ends towards a split part s
+// (chosen at registration for the fewest flops):
+//   left,  p < s:  T_p[(v_0..v_p)][k_p] = sum_{k_{p-1}} T_{p-1}[(v_0..v_{p-1})][k_{p-1}]
+//                                            X_p[v_p][k_p][k_{p-1}]      (T_0 = X_0)
+//   right, p >= s: R_p[(v_{t-1}..v_p)][k_{p-1}] = sum_{k_p} R_{p+1}[(v_{t-1}..v_{p+1})][k_p]
+//                                            X_p[v_p][k_{p-1}][k_p]      (R_{t-1} = X_{t-1})
+//   amp[(v_0..v_{s-1})][(v_{t-1}..v_s)] = sum_k T_{s-1}[..][k] R_s[..][k].
+// Part p's output X_p[v][k] (value v, local copy k) is first permuted to the
+// column order its side of the chain needs.
 
 struct qs_mplan {
   Circuit circ;
@@ -1356,11 +1360,14 @@ struct qs_mplan {
   int* d_iu = nullptr;   // grid row of each bitstring (values of parts 0..t-2)
   int* d_il = nullptr;   // value index in the last part
   std::vector<uint32_t*> d_perm;  // per part: natural column of each ordered column
+  int split = 1;  // parts [0, split) contract from the left end, [split, t) from the right
+  hipEvent_t ev_fork = nullptr;   // the parts run on their plans' streams (qs_plan::aux)
   ~qs_mplan() {
     (void)hipDeviceSynchronize();
     for (uint32_t* q : d_perm)
       if (q) (void)hipFree(q);
     pool.release_all();
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
   }
 };
 
@@ -1426,7 +1433,8 @@ qs_status qs_partition_chain(const qs_circuit* circ, const uint64_t* part_masks,
       cut_of[{std::get<0>(r), q}] = j;
       mp->link_of[p].push_back(link);
     }
-    if (pp->cuts.size() > 40) return fail(QS_ERR_UNSUPPORTED, "more than 40 cut gates on one part");
+    // all of a part's copies run as one block: X_p holds values x 2^c_p amplitudes
+    if (pp->cuts.size() > 30) return fail(QS_ERR_UNSUPPORTED, "more than 30 cut gates touch one part");
     build_side(c, part_masks[p], p % 2 == 0, cut_of, pp->side[0]);
     pp->side[1] = Side();
     pp->side[1].upper = false;
@@ -1480,15 +1488,46 @@ qs_status qs_chain_register(qs_mplan* mp, const uint64_t* bits, size_t m) {
     grid *= mp->nvals[p];
     if (p + 1 < t) tmax = std::max(tmax, grid * std::ldexp(1.0, mp->link_c[p]));
   }
+  (void)tmax;
   // the products run over the whole grid of part values
-  if (std::max(grid, tmax) > (double)(1u << 28))
+  if (grid > (double)(1u << 28))
     return fail(QS_ERR_UNSUPPORTED, "the part values span a grid above 2^28 amplitudes");
+  // split part: the fewest flops over both partial chains and the last product
+  {
+    const std::vector<int>& nv = mp->nvals;
+    const std::vector<int>& lc = mp->link_c;
+    double best = -1;
+    for (int sp = 1; sp < t; ++sp) {
+      double f = 0, big = 0, rows = nv[0];
+      for (int p = 1; p < sp; ++p) {  // left products
+        const double out = rows * nv[p] * std::ldexp(1.0, lc[p]);
+        f += out * std::ldexp(1.0, lc[p - 1]);
+        big = std::max(big, out);
+        rows *= nv[p];
+      }
+      double rr = nv[t - 1];
+      for (int p = t - 2; p >= sp; --p) {  // right products
+        const double out = rr * nv[p] * std::ldexp(1.0, lc[p - 1]);
+        f += out * std::ldexp(1.0, lc[p]);
+        big = std::max(big, out);
+        rr *= nv[p];
+      }
+      f += rows * rr * std::ldexp(1.0, lc[sp - 1]);
+      if (big > (double)(1u << 28)) continue;
+      if (best < 0 || f < best) {
+        best = f;
+        mp->split = sp;
+      }
+    }
+    if (best < 0) return fail(QS_ERR_UNSUPPORTED, "a partial product would exceed 2^28 amplitudes");
+  }
   std::vector<int> iu(m), il(m);
   for (size_t i = 0; i < m; ++i) {
-    size_t r = 0;
-    for (int p = 0; p + 1 < t; ++p) r = r * mp->nvals[p] + idx[p][i];
+    size_t r = 0, c = 0;
+    for (int p = 0; p < mp->split; ++p) r = r * mp->nvals[p] + idx[p][i];
+    for (int p = t - 1; p >= mp->split; --p) c = c * mp->nvals[p] + idx[p][i];
     iu[i] = (int)r;
-    il[i] = idx[t - 1][i];
+    il[i] = (int)c;
   }
   (void)hipDeviceSynchronize();
   mp->pool.settle();
@@ -1512,8 +1551,24 @@ qs_status qs_chain_amplitudes_device(qs_mplan* mp, float* d_out_c64, double* d_o
   const int t = mp->t;
   std::vector<float2*> Y(t, nullptr);
   double phr = 1, phi = 0;
+  // the parts are independent until the products: each runs on a stream of
+  // its own (default priority), forked from the caller's stream after the
+  // work already queued there and joined back before the products.  Their
+  // buffers return to the part streams, whose later work always starts after
+  // such a fork, so after the products that read them.
+  if (!mp->ev_fork) HIPCHECK(hipEventCreateWithFlags(&mp->ev_fork, hipEventDisableTiming));
+  HIPCHECK(hipEventRecord(mp->ev_fork, st));
   for (int p = 0; p < t; ++p) {
     qs_plan* pp = mp->parts[p].get();
+    if (!pp->aux) {
+      HIPCHECK(hipStreamCreateWithFlags(&pp->aux, hipStreamNonBlocking));
+      HIPCHECK(hipEventCreateWithFlags(&pp->ev_join, hipEventDisableTiming));
+    }
+    HIPCHECK(hipStreamWaitEvent(pp->aux, mp->ev_fork, 0));
+  }
+  for (int p = 0; p < t; ++p) {
+    qs_plan* pp = mp->parts[p].get();
+    hipStream_t ps = pp->aux;
     const int cp = (int)pp->cuts.size();
     const size_t K = (size_t)1 << cp;
     const int S = mp->nvals[p];
@@ -1524,65 +1579,99 @@ qs_status qs_chain_amplitudes_device(qs_mplan* mp, float* d_out_c64, double* d_o
     const double r0 = phr * a - phi * b, i0 = phr * b + phi * a;
     phr = r0;
     phi = i0;
-    float2* X = (float2*)pp->pool.get((size_t)S * K * sizeof(float2), st);
-    float2* O = (float2*)mp->pool.get((size_t)S * K * sizeof(float2), st);
+    float2* X = (float2*)pp->pool.get((size_t)S * K * sizeof(float2), ps);
+    float2* O = (float2*)mp->pool.get((size_t)S * K * sizeof(float2), ps);
     if (!X || !O) return fail(QS_ERR_OOM, "part amplitudes");
-    s = run_side(pp, 0, *pr, X, st);
+    s = run_side(pp, 0, *pr, X, ps);
     if (s != QS_OK) return s;
     if (!mp->d_perm[p]) {
-      // ordered column (k of the later link major, the earlier link minor) of
-      // every natural column nu
+      // ordered column of every natural column nu: left of the split the
+      // later link's bits are major, from the split on the earlier link's
       const std::vector<int>& lk = mp->link_of[p];
+      const bool left = p < mp->split;
       std::vector<uint32_t> perm(K);
       for (size_t nu = 0; nu < K; ++nu) {
         const uint32_t k = pr->nu_to_k[nu];
-        uint32_t hi = 0, lo = 0;
+        uint32_t later = 0, earlier = 0;
         for (int j = 0; j < cp; ++j) {
           const uint32_t bit = (k >> (cp - 1 - j)) & 1;
-          if (lk[j] == p) hi = (hi << 1) | bit;
-          else lo = (lo << 1) | bit;
+          if (lk[j] == p) later = (later << 1) | bit;
+          else earlier = (earlier << 1) | bit;
         }
-        const int nlo = p > 0 ? mp->link_c[p - 1] : 0;
-        perm[((size_t)hi << nlo) | lo] = (uint32_t)nu;
+        const int ne_ = p > 0 ? mp->link_c[p - 1] : 0;
+        const int nl_ = p + 1 < t ? mp->link_c[p] : 0;
+        const size_t col = left ? ((size_t)later << ne_) | earlier : ((size_t)earlier << nl_) | later;
+        perm[col] = (uint32_t)nu;
       }
       uint32_t* d = nullptr;
       HIPCHECK(hipMalloc(&d, K * sizeof(uint32_t)));
       HIPCHECK(hipMemcpy(d, perm.data(), K * sizeof(uint32_t), hipMemcpyHostToDevice));
       mp->d_perm[p] = d;
     }
-    HIPCHECK(launch_permute_cols(X, O, mp->d_perm[p], S, (int)K, st));
-    pp->pool.put(X, st);
+    HIPCHECK(launch_permute_cols(X, O, mp->d_perm[p], S, (int)K, ps));
+    pp->pool.put(X, ps);
     Y[p] = O;
+    HIPCHECK(hipEventRecord(pp->ev_join, ps));
+    HIPCHECK(hipStreamWaitEvent(st, pp->ev_join, 0));
   }
-  // the chain of products
-  float2* T = Y[0];
-  size_t R = (size_t)mp->nvals[0];
-  bool own_t = false;
-  for (int p = 1; p < t; ++p) {
-    const int Kc = 1 << mp->link_c[p - 1];
-    const bool last = p == t - 1;
-    const size_t N = last ? (size_t)mp->nvals[p] : (size_t)mp->nvals[p] << mp->link_c[p];
-    float2* C = (float2*)mp->pool.get(R * N * sizeof(float2), st);
-    void* work = mp->pool.get(std::max<size_t>(256, zgemm_workspace_bytes(0, (int)R, (int)N, Kc)), st);
-    if (!C || !work) return fail(QS_ERR_OOM, "chain products");
-    HIPCHECK(launch_zgemm_tn(0, (int)R, (int)N, Kc, T, Kc, Y[p], Kc, C, (int)N, 0, work, st));
+  // the two partial chains, then their product; a part's buffer returns to
+  // its stream, a product's to the caller's
+  auto product = [&](const float2* A, const float2* B, size_t M, size_t N, int kbits,
+                     float2** C) -> qs_status {
+    const int Kc = 1 << kbits;
+    *C = (float2*)mp->pool.get(M * N * sizeof(float2), st);
+    void* work = mp->pool.get(std::max<size_t>(256, zgemm_workspace_bytes(0, (int)M, (int)N, Kc)), st);
+    if (!*C || !work) return fail(QS_ERR_OOM, "chain products");
+    HIPCHECK(launch_zgemm_tn(0, (int)M, (int)N, Kc, A, Kc, B, Kc, *C, (int)N, 0, work, st));
     mp->pool.put(work, st);
-    if (own_t || p == 1) mp->pool.put(T, st);
-    mp->pool.put(Y[p], st);
+    return QS_OK;
+  };
+  auto release = [&](float2* buf, int part) {  // part < 0: a product
+    mp->pool.put(buf, part < 0 ? st : mp->parts[part]->aux);
+  };
+  const int sp = mp->split;
+  float2* T = Y[0];
+  int t_part = 0;
+  size_t R = (size_t)mp->nvals[0];
+  for (int p = 1; p < sp; ++p) {
+    float2* C = nullptr;
+    qs_status s = product(T, Y[p], R, (size_t)mp->nvals[p] << mp->link_c[p], mp->link_c[p - 1], &C);
+    if (s != QS_OK) return s;
+    release(T, t_part);
+    release(Y[p], p);
     T = C;
-    own_t = true;
-    if (!last) R *= (size_t)mp->nvals[p];
+    t_part = -1;
+    R *= (size_t)mp->nvals[p];
+  }
+  float2* U = Y[t - 1];
+  int u_part = t - 1;
+  size_t Rr = (size_t)mp->nvals[t - 1];
+  for (int p = t - 2; p >= sp; --p) {
+    float2* C = nullptr;
+    qs_status s = product(U, Y[p], Rr, (size_t)mp->nvals[p] << mp->link_c[p - 1], mp->link_c[p], &C);
+    if (s != QS_OK) return s;
+    release(U, u_part);
+    release(Y[p], p);
+    U = C;
+    u_part = -1;
+    Rr *= (size_t)mp->nvals[p];
+  }
+  float2* G = nullptr;
+  {
+    qs_status s = product(T, U, R, Rr, mp->link_c[sp - 1], &G);
+    if (s != QS_OK) return s;
+    release(T, t_part);
+    release(U, u_part);
   }
   const size_t m = mp->bits.size();
-  const int nl = mp->nvals[t - 1];
-  HIPCHECK(launch_gather_amps(T, nl, mp->d_iu, mp->d_il, m, (float2*)d_out_c64,
+  HIPCHECK(launch_gather_amps(G, (int)Rr, mp->d_iu, mp->d_il, m, (float2*)d_out_c64,
                               make_float2((float)phr, (float)phi), st));
   const int nb = prob_partial_blocks(m);
   double* part = (double*)mp->pool.get((2 * (size_t)nb + 2) * sizeof(double), st);
   if (!part) return fail(QS_ERR_OOM, "probability sums");
   HIPCHECK(launch_prob_sums((const float2*)d_out_c64, m, part, d_out_sums ? d_out_sums : part + 2 * nb, st));
   mp->pool.put(part, st);
-  mp->pool.put(T, st);
+  mp->pool.put(G, st);
   return QS_OK;
 }
 

@@ -135,3 +135,25 @@ def test_chain_errors():
     with pytest.raises(Q.QSError) as e:
         Q.ChainPlan(text, band_masks(6, 3, [[0, 1], [2, 3]]))
     assert e.value.status == -1  # a qubit left out
+
+
+@pytest.mark.parametrize("depth,masks_fn", [
+    # the link between rows 1 and 2 has no cut gate at depth 6
+    (6, lambda: band_masks(4, 3, [[0], [1], [2, 3]])),
+    # a one-qubit part (qubit 0, whose neighbours are all in part 1)
+    (8, lambda: [0b1, W.grid_rows_mask(4, 3, [0, 1]) & ~0b1, W.grid_rows_mask(4, 3, [2, 3])]),
+])
+def test_chain_degenerate_parts(depth, masks_fn):
+    Q = _lib()
+    text = W.random_grid_circuit(4, 3, depth, 0)
+    masks = masks_fn()
+    bits = np.arange(1 << 12, dtype=np.uint64)
+    say(f"case chain degenerate depth {depth}")
+    cp = Q.ChainPlan(text, masks)
+    try:
+        amp, _ = cp.amplitudes(bits)
+        info = (cp.part_qubits, cp.link_cuts)
+    finally:
+        cp.close()
+    assert 0 in info[1] or 1 in info[0]
+    assert relerr(amp, SV.simulate(OC.parse(text))) < 1e-5

@@ -1469,7 +1469,7 @@ qs_status qs_chain_register(qs_mplan* mp, const uint64_t* bits, size_t m) {
     if (bits[i] & ~full) return fail(QS_ERR_ARG, "bitstring has bits set beyond the qubit count");
   std::vector<std::vector<int>> idx(t, std::vector<int>(m));
   mp->nvals.assign(t, 0);
-  double grid = 1, tmax = 0;
+  double grid = 1;
   for (int p = 0; p < t; ++p) {
     const Side& s = mp->parts[p]->side[0];
     std::vector<uint32_t> hv(m);
@@ -1486,9 +1486,7 @@ qs_status qs_chain_register(qs_mplan* mp, const uint64_t* bits, size_t m) {
     mp->nvals[p] = (int)u.size();
     mp->parts[p]->vals[0] = std::move(u);
     grid *= mp->nvals[p];
-    if (p + 1 < t) tmax = std::max(tmax, grid * std::ldexp(1.0, mp->link_c[p]));
   }
-  (void)tmax;
   // the products run over the whole grid of part values
   if (grid > (double)(1u << 28))
     return fail(QS_ERR_UNSUPPORTED, "the part values span a grid above 2^28 amplitudes");
@@ -1550,7 +1548,7 @@ qs_status qs_chain_amplitudes_device(qs_mplan* mp, float* d_out_c64, double* d_o
   hipStream_t st = (hipStream_t)hip_stream;
   const int t = mp->t;
   std::vector<float2*> Y(t, nullptr);
-  double phr = 1, phi = 0;
+  double ph_re = 1, ph_im = 0;  // product of the parts' constants (Prepared::phi)
   // the parts are independent until the products: each runs on a stream of
   // its own (default priority), forked from the caller's stream after the
   // work already queued there and joined back before the products.  Their
@@ -1576,9 +1574,9 @@ qs_status qs_chain_amplitudes_device(qs_mplan* mp, float* d_out_c64, double* d_o
     qs_status s = prepare_side(pp, 0, Block{}, &pr);
     if (s != QS_OK) return s;
     const double a = pp->phi[0][0], b = pp->phi[0][1];
-    const double r0 = phr * a - phi * b, i0 = phr * b + phi * a;
-    phr = r0;
-    phi = i0;
+    const double r0 = ph_re * a - ph_im * b, i0 = ph_re * b + ph_im * a;
+    ph_re = r0;
+    ph_im = i0;
     float2* X = (float2*)pp->pool.get((size_t)S * K * sizeof(float2), ps);
     float2* O = (float2*)mp->pool.get((size_t)S * K * sizeof(float2), ps);
     if (!X || !O) return fail(QS_ERR_OOM, "part amplitudes");
@@ -1665,7 +1663,7 @@ qs_status qs_chain_amplitudes_device(qs_mplan* mp, float* d_out_c64, double* d_o
   }
   const size_t m = mp->bits.size();
   HIPCHECK(launch_gather_amps(G, (int)Rr, mp->d_iu, mp->d_il, m, (float2*)d_out_c64,
-                              make_float2((float)phr, (float)phi), st));
+                              make_float2((float)ph_re, (float)ph_im), st));
   const int nb = prob_partial_blocks(m);
   double* part = (double*)mp->pool.get((2 * (size_t)nb + 2) * sizeof(double), st);
   if (!part) return fail(QS_ERR_OOM, "probability sums");

@@ -115,6 +115,31 @@ def controlled_variant(Q, w, bits, prec, k0, k1, a, stream, d_out, d_sums) -> di
         cp.close()
 
 
+def executed_updates(dump: dict, n_values) -> dict:
+    """Gate-amplitude updates the schedule executes per step (metric (ii)'s
+    executed count, next to the flat one): every gate of a full-state pass on
+    every amplitude of every state it runs on (the last pass counted in full,
+    although it computes only the tiles the leaf stage reads), plus the 2x2
+    and diagonal gates of the leaf levels on the light-cone rows (2^q
+    amplitudes per row, one row per leaf path prefix and requested value)."""
+    passes = leaf = 0.0
+    for s, S in zip(dump["sides"], n_values):
+        n, ops, levels = s["n"], s["ops"], s["levels"]
+        gate = lambda i: ops[i][0] != "cut"
+        for pp in s["passes"]:
+            li = pp["level_in"]
+            nin = sum(1 for i in pp["ops_in"] if gate(i))
+            nout = sum(1 for i in pp["ops_out"] if gate(i))
+            passes += 2.0 ** n * (levels[li]["nodes"] * nin + levels[min(li + 1, len(levels) - 1)]["nodes"]
+                                  * nout * (1 if pp["branch"] else 0))
+        q = len(s["Q"])
+        paths = 1.0
+        for lv in reversed(levels[s["lstar"] + 1:]):
+            leaf += S * paths * sum(1 for i in lv["ops"] if gate(i)) * 2.0 ** q
+            paths *= 2.0 ** len(lv["cuts"])
+    return {"passes": passes, "leaf_rows": leaf, "total": passes + leaf}
+
+
 def chain_variant(Q, a, stream) -> dict:
     """Amplitudes/s of a partition into four parts (Sec. 3, Fig. 3): the 8x8
     grid (64 qubits) at depth 10 cut into row bands of 16 qubits, 32 values
@@ -313,6 +338,7 @@ def main() -> int:
             g_side[s] += 1
     flat_updates = (k1 - k0) * (g_side[0] * 2.0 ** n_u + g_side[1] * 2.0 ** n_l)
     amp_updates_per_s = flat_updates / (ms_per_step / 1000.0)
+    ex = executed_updates(plan.dump(k0, k1), (len(np.unique(u_vals)), len(np.unique(l_vals))))
 
     out = {
         "metric": "output amplitudes/s and half-circuit amp-updates/s at 42q d20; HBM/MFMA %peak",
@@ -329,6 +355,9 @@ def main() -> int:
                    "qubits": w.n, "depth": w.depth, "cuts": c, "copies": k1 - k0, "bitstrings": m,
                    "assembly": "fp32 mfma" if prec == 0 else "split-bf16 (3 products) mfma"},
         "amp_updates_per_s_flat": amp_updates_per_s,
+        "amp_updates_per_s_executed": ex["total"] / (ms_per_step / 1000.0),
+        "amp_updates_executed_per_step": ex,
+        "passes_per_s": launches["pass"] / (ms_per_step / 1000.0),
         "device_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
         "launches_per_step": launches,
         "setup_s": round(setup_s, 3),

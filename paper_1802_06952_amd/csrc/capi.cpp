@@ -782,21 +782,19 @@ qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_s
           tm.launches += 2;
           if (plan->timing) plan->gemm_flops += 8.0 * M * N * (double)K0;
         } else if (b.ne > 0) {
-          // split-BF16: one product per end-cut pattern
-          const int K0 = K >> b.ne;
-          const size_t wb = zgemm_workspace_bytes((int)prec, M, N, K0);
+          // split-BF16: the same grouped product, operands split once for all
+          // end-cut patterns
+          const int K0 = K >> b.ne, ng = 1 << b.ne;
+          int maxn = 1;
+          for (int g = 0; g < ng; ++g) maxn = std::max(maxn, b.goff[g + 1] - b.goff[g]);
+          const size_t wb = zgemm_grouped_bf16_workspace_bytes(M, N, maxn, K0, ng);
           void* work = plan->pool.get(wb, st);
           if (!work) return fail(QS_ERR_OOM, "assembly workspace");
-          for (int g = 0; g < (1 << b.ne); ++g) {
-            const int ng = b.goff[g + 1] - b.goff[g];
-            if (ng == 0) continue;
-            HIPCHECK(launch_zgemm_tn((int)prec, M, ng, K0, b.Ut + (size_t)g * M * K0, K0,
-                                     b.X[1] + (size_t)b.goff[g] * K0, K0, C, N, first ? 0 : 1,
-                                     work, st, b.d_rows + b.goff[g]));
-            tm.launches += prec == QS_PREC_FP32 ? 2 : 4;
-            if (plan->timing) plan->gemm_flops += 8.0 * M * ng * (double)K0;
-          }
+          HIPCHECK(launch_zgemm_grouped_bf16(M, N, maxn, K0, ng, (const int*)(b.d_rows + N), b.Ut,
+                                             b.X[1], C, N, first ? 0 : 1, work, st, b.d_rows));
           plan->pool.put(work, st);
+          tm.launches += 4;
+          if (plan->timing) plan->gemm_flops += 8.0 * M * N * (double)K0;
         } else {
           const size_t wb = zgemm_workspace_bytes((int)prec, M, N, K);
           void* work = plan->pool.get(wb, st);

@@ -53,6 +53,15 @@ hipError_t launch_zgemm_grouped(int M, int Ntot, int maxn, int K, int ngroups, c
                                 int ldc, int accumulate, void* work, hipStream_t st,
                                 const uint32_t* cmap);
 
+// The same grouped product in split-BF16 (three bf16 products per real
+// product, FP32 accumulation): A holds ngroups * M rows of K (group g's M rows
+// at row g * M), B Ntot rows of K; both are split once for all groups.
+size_t zgemm_grouped_bf16_workspace_bytes(int M, int Ntot, int maxn, int K, int ngroups);
+hipError_t launch_zgemm_grouped_bf16(int M, int Ntot, int maxn, int K, int ngroups,
+                                     const int* d_goff, const float2* A, const float2* B,
+                                     float2* C, int ldc, int accumulate, void* work,
+                                     hipStream_t st, const uint32_t* cmap);
+
 // out[r][j] = in[rowsel[r]][colsel[j]].
 hipError_t launch_gather_rows_cols(const float2* in, float2* out, const uint32_t* rowsel,
                                    const uint32_t* colsel, int rows, int Kin, int Kout,

@@ -1286,19 +1286,33 @@ __device__ __forceinline__ bf16x8 bf_neg(bf16x8 v) {
   return __builtin_bit_cast(bf16x8, u);
 }
 
+// Grouped form (goff != nullptr): blockIdx.z = group * nsplit + split; group g
+// takes the columns goff[g] .. goff[g+1]-1 (B rows, and the columns of the
+// partial product) and A rows g * a_grows .. (its M rows); blockIdx.x counts
+// the group's column tiles.  Plain form: blockIdx.z is the split.
 __global__ void __launch_bounds__(kGemmThreads)
 k_zgemm_tn_bf16x3(int M, int N, int Kp, int kper, const __hip_bfloat16* __restrict__ Ap,
                   int Mp, const __hip_bfloat16* __restrict__ Bp, int Np, float2* __restrict__ out,
-                  int ldo, size_t split_stride) {
+                  int ldo, size_t split_stride, const int* __restrict__ goff, int nsplit,
+                  int a_grows) {
   // LDS: [plane][row][k] with rows of kBK bf16 (64 bytes) plus 16 bytes of padding
   constexpr int RS = kBK + 8;
   __shared__ __attribute__((aligned(16))) __hip_bfloat16 As[4][kGBM][RS];
   __shared__ __attribute__((aligned(16))) __hip_bfloat16 Bs[4][kGBN][RS];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int i_blk = blockIdx.y * kGBM, j_blk = blockIdx.x * kGBN;
+  int split = blockIdx.z, j_blk = blockIdx.x * kGBN, jend = N, a_row0 = 0;
+  if (goff) {
+    const int g = blockIdx.z / nsplit;
+    split = blockIdx.z - g * nsplit;
+    j_blk = goff[g] + blockIdx.x * kGBN;
+    jend = goff[g + 1];
+    if (j_blk >= jend) return;  // the whole tile lies past the group (uniform per block)
+    a_row0 = g * a_grows;
+  }
+  const int i_blk = blockIdx.y * kGBM;
   const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
-  const int kb = blockIdx.z * kper;
+  const int kb = split * kper;
   const int ke = min(Kp, kb + kper);
   const size_t pa = (size_t)Mp * Kp, pb = (size_t)Np * Kp;
   floatx4 ar[4][4], ai[4][4];
@@ -1316,7 +1330,7 @@ k_zgemm_tn_bf16x3(int M, int N, int Kp, int kper, const __hip_bfloat16* __restri
     for (int x = 0; x < 8; ++x) {
       const int c = tid + x * kGemmThreads;  // 0..2047
       const int p = c >> 9, row = (c >> 2) & 127, q = c & 3;
-      const u32x4 va = *(const u32x4*)(Ap + p * pa + (size_t)(i_blk + row) * Kp + k0 + q * 8);
+      const u32x4 va = *(const u32x4*)(Ap + p * pa + (size_t)(a_row0 + i_blk + row) * Kp + k0 + q * 8);
       const u32x4 vb = *(const u32x4*)(Bp + p * pb + (size_t)(j_blk + row) * Kp + k0 + q * 8);
       *(u32x4*)(&As[p][row][q * 8]) = va;
       *(u32x4*)(&Bs[p][row][q * 8]) = vb;
@@ -1356,7 +1370,7 @@ k_zgemm_tn_bf16x3(int M, int N, int Kp, int kper, const __hip_bfloat16* __restri
     }
     __syncthreads();
   }
-  float2* o = out + (size_t)blockIdx.z * split_stride;
+  float2* o = out + (size_t)split * split_stride;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -1365,7 +1379,7 @@ k_zgemm_tn_bf16x3(int M, int N, int Kp, int kper, const __hip_bfloat16* __restri
       for (int e = 0; e < 4; ++e) {
         const int i = i_blk + wi + a * 16 + 4 * (lane >> 4) + e;
         const int j = j_blk + wj + b * 16 + (lane & 15);
-        if (i < M && j < N) o[(size_t)i * ldo + j] = make_float2(ar[a][b][e], ai[a][b][e]);
+        if (i < M && j < jend) o[(size_t)i * ldo + j] = make_float2(ar[a][b][e], ai[a][b][e]);
       }
 }
 
@@ -1427,7 +1441,7 @@ hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int l
     hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, st, B, ldb,
                        K, N, Kp, Np, Bp);
     hipLaunchKernelGGL(k_zgemm_tn_bf16x3, grid, dim3(kGemmThreads), 0, st, M, N, Kp, g.kper, Ap,
-                       Mp, Bp, Np, P, N, ss);
+                       Mp, Bp, Np, P, N, ss, (const int*)nullptr, g.splits, 0);
   }
   const size_t tot = ss;
   hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, N,
@@ -1475,6 +1489,62 @@ hipError_t launch_zgemm_grouped(int M, int Ntot, int maxn, int K, int ngroups, c
   if (grid.z > 65535) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_zgemm_nt_f32<4, kGroupTN>), grid, dim3(kGemmThreads), 0, st, M, Ntot, K,
                      g.kper, A, K, B, K, P, Ntot, ss, d_goff, g.splits, a_gstride);
+  hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((ss + 255) / 256)), dim3(256), 0, st, M, Ntot,
+                     g.splits, P, ss, C, ldc, accumulate, cmap);
+  return hipGetLastError();
+}
+
+// Grouped split-BF16 product: as launch_zgemm_grouped, with both operands split
+// once for all groups (A as ngroups * M rows) and one launch of
+// k_zgemm_tn_bf16x3 over every group's column tiles.
+struct GroupedBf16Shape {
+  int Kp, tpg, mt, splits, kper;
+  size_t rows_a, rows_b;  // split-plane rows, with the padding the tiles read
+};
+
+GroupedBf16Shape grouped_bf16_shape(int M, int Ntot, int maxn, int K, int ngroups) {
+  GroupedBf16Shape g;
+  g.Kp = round_up(K, kBK);
+  g.tpg = (maxn + kGBN - 1) / kGBN;
+  g.mt = (M + kGBM - 1) / kGBM;
+  const int tiles = std::max(1, g.tpg * g.mt * ngroups);
+  const int want = std::max(1, 1024 / tiles);
+  const int maxsplit = std::max(1, g.Kp / (4 * kBK));
+  g.splits = std::max(1, std::min({want, maxsplit, 64}));
+  g.kper = round_up((g.Kp + g.splits - 1) / g.splits, kBK);
+  g.splits = (g.Kp + g.kper - 1) / g.kper;
+  g.rows_a = (size_t)ngroups * M + kGBM;
+  g.rows_b = (size_t)round_up(Ntot, kGBN) + (size_t)g.tpg * kGBN;
+  return g;
+}
+
+size_t zgemm_grouped_bf16_workspace_bytes(int M, int Ntot, int maxn, int K, int ngroups) {
+  const GroupedBf16Shape g = grouped_bf16_shape(M, Ntot, maxn, K, ngroups);
+  return (size_t)g.splits * M * Ntot * sizeof(float2) +
+         4 * (size_t)g.Kp * (g.rows_a + g.rows_b) * sizeof(__hip_bfloat16) + 256;
+}
+
+hipError_t launch_zgemm_grouped_bf16(int M, int Ntot, int maxn, int K, int ngroups,
+                                     const int* d_goff, const float2* A, const float2* B,
+                                     float2* C, int ldc, int accumulate, void* work,
+                                     hipStream_t st, const uint32_t* cmap) {
+  if (M <= 0 || Ntot <= 0 || K <= 0 || ngroups <= 0 || maxn <= 0) return hipErrorInvalidValue;
+  const GroupedBf16Shape g = grouped_bf16_shape(M, Ntot, maxn, K, ngroups);
+  if ((size_t)ngroups * g.splits > 65535) return hipErrorInvalidValue;
+  const size_t ss = (size_t)M * Ntot;
+  float2* P = (float2*)work;
+  char* base = (char*)work + (size_t)g.splits * ss * sizeof(float2);
+  base = (char*)(((uintptr_t)base + 255) & ~(uintptr_t)255);
+  __hip_bfloat16* Ap = (__hip_bfloat16*)base;
+  __hip_bfloat16* Bp = Ap + 4 * g.rows_a * g.Kp;
+  const size_t ta = g.rows_a * g.Kp, tb = g.rows_b * g.Kp;
+  hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((ta + 255) / 256)), dim3(256), 0, st, A, K, K,
+                     ngroups * M, g.Kp, (int)g.rows_a, Ap);
+  hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, st, B, K, K,
+                     Ntot, g.Kp, (int)g.rows_b, Bp);
+  dim3 grid(g.tpg, g.mt, ngroups * g.splits);
+  hipLaunchKernelGGL(k_zgemm_tn_bf16x3, grid, dim3(kGemmThreads), 0, st, M, Ntot, g.Kp, g.kper,
+                     Ap, (int)g.rows_a, Bp, (int)g.rows_b, P, Ntot, ss, d_goff, g.splits, M);
   hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((ss + 255) / 256)), dim3(256), 0, st, M, Ntot,
                      g.splits, P, ss, C, ldc, accumulate, cmap);
   return hipGetLastError();

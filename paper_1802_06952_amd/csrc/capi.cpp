@@ -194,6 +194,11 @@ struct qs_plan {
   int* d_idx[2] = {nullptr, nullptr};
   bool list_mode = false;  // bitstrings far from a product set: per-bitstring sums
   bool part_mode = false;  // one part of a chain partition (qs_mplan): side 0 only
+  // buffers released by qs_plan_reset wait for the next run to be ordered
+  // after their last users (Pool::put_unordered); last_st is the stream of the
+  // latest run or assembly
+  bool unordered = false;
+  hipStream_t last_st = nullptr;
   double phi[2][2] = {{1, 0}, {1, 0}};  // per half: the constant of its unit-entry gates (Prepared)
   std::vector<BlockRes> blocks;
   std::vector<std::pair<uint64_t, uint64_t>> ranges;
@@ -739,6 +744,7 @@ float2 phi_of(const qs_plan* plan) {
 }
 
 qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_sums, hipStream_t st) {
+  plan->last_st = st;
   const int M = (int)plan->vals[0].size(), N = (int)plan->vals[1].size();
   const size_t m = plan->bits.size();
   const int nb = prob_partial_blocks(m);
@@ -1024,6 +1030,7 @@ qs_status qs_plan_reset(qs_plan* plan, int keep_bitstrings) {
   }
   plan->blocks.clear();
   plan->ranges.clear();
+  plan->unordered = true;
   if (!keep_bitstrings) {
     for (int k = 0; k < 2; ++k) {
       if (plan->d_vals[k]) plan->pool.put_unordered(plan->d_vals[k]);
@@ -1051,6 +1058,16 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
   qs_status s = register_bits(plan, bitstrings, m);
   if (s != QS_OK) return s;
   hipStream_t st = (hipStream_t)hip_stream;
+  if (plan->unordered) {
+    // the blocks below settle the pool after their fork, which orders reuse on
+    // both streams after the released buffers' last users when those ran on
+    // this stream (and on aux, joined into it); after a change of stream, wait
+    // for them first
+    if (st != plan->last_st) HIPCHECK(hipDeviceSynchronize());
+    plan->pool.settle();
+    plan->unordered = false;
+  }
+  plan->last_st = st;
   uint64_t k = copy_begin;
   while (k < copy_end) {
     int sz = std::min(ctz64(k), c);

@@ -1508,7 +1508,7 @@ GroupedBf16Shape grouped_bf16_shape(int M, int Ntot, int maxn, int K, int ngroup
   g.tpg = (maxn + kGBN - 1) / kGBN;
   g.mt = (M + kGBM - 1) / kGBM;
   const int tiles = std::max(1, g.tpg * g.mt * ngroups);
-  const int want = std::max(1, 1024 / tiles);
+  const int want = std::max(1, 256 / tiles);  // longer k loops, fewer partials
   const int maxsplit = std::max(1, g.Kp / (4 * kBK));
   g.splits = std::max(1, std::min({want, maxsplit, 64}));
   g.kper = round_up((g.Kp + g.splits - 1) / g.splits, kBK);

@@ -205,8 +205,8 @@ def main() -> int:
     a = ap.parse_args()
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (copies of a half circuit are independent; "
-              "the multi-GPU split is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py: runs on one GPU only (the copies of a half circuit are independent, but "
+              "splitting them over several GPUs is not implemented); use --gpus 1", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -254,3 +254,41 @@ def test_failed_partition_frees_the_circuit_once():
     p = Q.Plan(text, W.grid_rows_mask(6, 4, [0, 1, 2]))
     assert p.n_cuts > 0
     p.close()
+
+
+@pytest.mark.parametrize("rows,cols,depth,bands", [
+    (6, 4, 12, [[0, 1], [2, 3], [4, 5]]),
+    (8, 8, 10, [[0, 1], [2, 3], [4, 5], [6, 7]]),
+    (5, 4, 12, [[0], [1, 2], [3, 4]]),
+])
+def test_chain_partition_against_oracle(rows, cols, depth, bands):
+    """Part sizes and cuts per link of qs_partition_chain equal the oracle's
+    chain partition (Sec. 3, Fig. 3)."""
+    from oracle import multipart as MP
+    text = W.random_grid_circuit(rows, cols, depth, 0)
+    masks = [W.grid_rows_mask(rows, cols, b) for b in bands]
+    cuts = MP.chain_cuts(OC.parse(text), masks)
+    cp = Q.ChainPlan(text, masks)
+    try:
+        assert cp.t == len(bands)
+        assert cp.part_qubits == [len(b) * cols for b in bands]
+        assert cp.link_cuts == [sum(1 for k in cuts if k.lo_part == i) for i in range(len(bands) - 1)]
+    finally:
+        cp.close()
+
+
+def test_chain_partition_errors():
+    text = W.random_grid_circuit(4, 3, 8, 0)
+    rows = [W.grid_rows_mask(4, 3, [r]) for r in range(4)]
+    c = Q.qs_load_circuit(text)
+    try:
+        for masks, status in (([rows[0] | rows[1], rows[1] | rows[2], rows[3]], -1),  # overlap
+                              ([rows[0], rows[1], rows[2]], -1),                      # a row left out
+                              ([rows[0], 0, rows[1] | rows[2] | rows[3]], -1),        # empty part
+                              ([rows[0]], -1),                                        # t = 1
+                              ([rows[0], rows[2], rows[1], rows[3]], -3)):            # not a chain
+            with pytest.raises(Q.QSError) as e:
+                Q.qs_partition_chain(c, masks)
+            assert e.value.status == status, masks
+    finally:
+        Q.qs_circuit_free(c)

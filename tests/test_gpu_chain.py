@@ -157,3 +157,26 @@ def test_chain_degenerate_parts(depth, masks_fn):
         cp.close()
     assert 0 in info[1] or 1 in info[0]
     assert relerr(amp, SV.simulate(OC.parse(text))) < 1e-5
+
+
+@pytest.mark.parametrize("rows,cols,depth,bands,per_band", [
+    (8, 4, 10, [[0, 1], [2, 3], [4, 5], [6, 7]], 8),   # 32 qubits, 4 cuts per link
+    (6, 6, 8, [[0, 1], [2, 3], [4, 5]], 16),            # 36 qubits, 6 cuts per link
+])
+def test_chain_against_multipart_oracle(rows, cols, depth, bands, per_band):
+    """Beyond the state vector: the FP64 t-part oracle (sum over all copies of
+    the product of the part amplitudes) on 4096 band-product bitstrings."""
+    from oracle import multipart as MP
+    Q = _lib()
+    text = W.random_grid_circuit(rows, cols, depth, 0)
+    masks = band_masks(rows, cols, bands)
+    bits = band_product_bits(rows, cols, bands, per_band, 50 + rows)
+    say(f"case chain {rows}x{cols} d{depth} against the t-part oracle: {bits.size} bitstrings")
+    cp = Q.ChainPlan(text, masks)
+    try:
+        amp, _ = cp.amplitudes(bits)
+    finally:
+        cp.close()
+    say("case chain: oracle")
+    ref = MP.amplitudes(OC.parse(text), masks, bits)
+    assert relerr(amp, ref) < 1e-5

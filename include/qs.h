@@ -13,7 +13,8 @@
  * Conventions shared by every call:
  *   - A circuit is a sequence of layers ("cycles"); each layer holds gates on
  *     disjoint qubits (Supp. A, the layer graphs G_t = (V_t, E_t)).  Gates:
- *     h, t, sx (square root of X), sy (square root of Y), cz.
+ *     h, t, sx (square root of X), sy (square root of Y), cz, and the
+ *     controlled gates cx and cy (control first; Supp. Eq. 1).
  *   - Bit q of a bitstring (uint64) is the outcome of qubit q.  Bits >= n must
  *     be zero.
  *   - Cut j is the j-th crossing CZ ordered by (layer, upper endpoint id); copy
@@ -29,7 +30,7 @@
  * Ownership: handles are created by qs_* calls and released by the matching
  * qs_*_free; every input array belongs to the caller and is copied before the
  * call returns; output arrays belong to the caller.  Device memory belongs to
- * the plan and is released by qs_plan_free.
+ * the plan, comes from qs_options.alloc, and is released by qs_plan_free.
  * Threads: a plan is not thread-safe; different plans may be used from
  * different threads and streams at the same time.
  */
@@ -62,6 +63,20 @@ typedef enum {
 typedef struct qs_circuit qs_circuit; /* opaque, host memory */
 typedef struct qs_plan qs_plan;       /* opaque, owns device buffers */
 
+/* Device memory for a plan's buffers.  alloc returns `bytes` of device memory
+ * on the current device, aligned to 256 bytes, or NULL on failure (the call
+ * that needed it then fails with QS_ERR_OOM); free releases a pointer that
+ * alloc returned.  ctx is passed back unchanged.  The library calls them only
+ * from inside qs_* calls, on the calling thread, and frees a buffer only when
+ * no queued kernel uses it any more (after a device synchronisation).  Both
+ * NULL: hipMalloc and hipFree.  The Python binding passes PyTorch's caching
+ * allocator here. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} qs_allocator;
+
 /* Tuning knobs; a zero field means "choose automatically". */
 typedef struct {
   int tile_bits;          /* qubits held per workgroup tile in a full-state pass (6..13) */
@@ -71,20 +86,34 @@ typedef struct {
   int plain;              /* 1 = the paper's flat per-copy form, for comparison: every copy
                              simulated from |0> on its own (no shared prefix), one gate per
                              full-state pass, full leaf states then a gather */
-  size_t mem_budget;      /* bytes of device memory the plan may hold for states */
+  size_t mem_budget;      /* bytes of device memory the plan may hold for states; 0 = 80 % of
+                             the device's memory.  Fixed once per plan (the first run), and
+                             shared by whatever runs at the same time (the two halves on two
+                             streams, the t parts of a chain), so the same inputs always give
+                             the same schedule */
   int one_stream;         /* 1 = run the two halves one after the other on hip_stream; 0 = the
                              lower half on a stream of the plan (default priority), ordered
                              after the work queued on hip_stream by an event and joined back
                              into hip_stream by another before the assembly */
+  uint64_t copies_per_launch; /* most copies one block of qs_run_halves holds (a power of two,
+                             0 = as many as the range allows): each block's passes and leaf
+                             evaluation run over all of its copies in one launch each, and
+                             blocks run one after another */
+  qs_allocator alloc;     /* every device buffer of the plan (states, gathered half amplitudes,
+                             descriptors, copy tables, assembly workspace) comes from here */
 } qs_options;
 
 /* Message describing the last failed call on this thread ("" if none). */
 const char* qs_last_error(void);
 
 /* Parse circuit text (format: "qubits <n>" then one gate per line,
- * "<layer> <gate> <q> [<q2>]", '#' comments).  Layers must not decrease and a
- * qubit may appear once per layer.  n <= 64.  On success *out owns a new
- * circuit.  Errors: QS_ERR_ARG (null pointers), QS_ERR_PARSE. */
+ * "<layer> <gate> <q> [<q2>]", '#' comments).  The text is the layered circuit
+ * of Supp. A: layer t holds the gates of G_t = (V_t, E_t), each CZ an edge of
+ * E_t, no qubit in two gates of one layer; the one-qubit gates are those of
+ * the random circuits of Sec. 2.2 (H, square roots of X and Y, T).  Layers
+ * must not decrease.  n <= 64.  On success *out owns a new circuit (host
+ * memory).  Errors: QS_ERR_ARG (null pointers), QS_ERR_PARSE (unknown gate,
+ * qubit out of range, a qubit twice in a layer, decreasing layers). */
 qs_status qs_load_circuit(const char* text, size_t len, qs_circuit** out);
 
 /* Number of qubits and gates of a parsed circuit (either pointer may be NULL). */
@@ -172,12 +201,15 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
                         const uint64_t* bitstrings, size_t m, void* hip_stream);
 
 /* Amplitudes of the m bitstrings summed over every copy run so far (the whole
- * circuit when all 2^c copies were run, a partial sum for a slice).  If no
+ * circuit when all 2^c copies were run, a partial sum for a slice): the sum
+ * over copies k of U_k[u(x)] L_k[l(x)] of Supp. A, Eq. (8), i.e. the tensor
+ * products of the sampled half amplitudes added up as in Sec. 2.3.1.  If no
  * copy has been run yet, runs all copies first with these bitstrings.  The
  * bitstrings must be the registered set.  out_c64 receives 2*m floats (re, im)
  * in host memory.  out_stats (nullable, host) receives three doubles computed
  * in FP64 on the GPU: sum |a|^2, 2^n * mean |a|^2, 2^(2n) * mean |a|^4.
- * Synchronises hip_stream.  Errors: QS_ERR_ARG, QS_ERR_STATE, QS_ERR_HIP. */
+ * Synchronises hip_stream.  out_c64 and out_stats are written only when the
+ * call succeeds.  Errors: QS_ERR_ARG, QS_ERR_STATE, QS_ERR_OOM, QS_ERR_HIP. */
 qs_status qs_amplitudes(qs_plan* plan, const uint64_t* bitstrings, size_t m, qs_precision prec,
                         float* out_c64, double* out_stats, void* hip_stream);
 

@@ -50,10 +50,60 @@ class qs_cut_score(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class qs_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
 class qs_options(C.Structure):
     _fields_ = [("tile_bits", C.c_int), ("coalesce_bits", C.c_int), ("tail_max_qubits", C.c_int),
                 ("materialize_level", C.c_int), ("plain", C.c_int), ("mem_budget", C.c_size_t),
-                ("one_stream", C.c_int)]
+                ("one_stream", C.c_int), ("copies_per_launch", C.c_uint64),
+                ("alloc", qs_allocator)]
+
+
+class TorchAllocator:
+    """qs_allocator backed by PyTorch's caching allocator (device memory of
+    the current device).  Keeps the ctypes callbacks alive while a plan uses
+    them; counts the calls (``n_alloc``, ``n_free``)."""
+
+    def __init__(self):
+        import torch
+        self._torch = torch
+        self.n_alloc = 0
+        self.n_free = 0
+        self.live = 0
+
+        def _alloc(nbytes, _ctx):
+            try:
+                ptr = self._torch.cuda.caching_allocator_alloc(int(nbytes))
+            except Exception:  # out of memory: the library reports QS_ERR_OOM
+                return None
+            self.n_alloc += 1
+            self.live += 1
+            return ptr
+
+        def _free(ptr, _ctx):
+            if ptr:
+                self._torch.cuda.caching_allocator_delete(ptr)
+                self.n_free += 1
+                self.live -= 1
+
+        self._alloc_cb = ALLOC_FN(_alloc)
+        self._free_cb = FREE_FN(_free)
+        self.struct = qs_allocator(self._alloc_cb, self._free_cb, None)
+
+
+def _allocator(alloc):
+    """None -> hipMalloc / hipFree inside the library; "torch" -> a new TorchAllocator."""
+    if alloc is None:
+        return None
+    if alloc == "torch":
+        return TorchAllocator()
+    return alloc
 
 
 def _load() -> C.CDLL:
@@ -310,9 +360,12 @@ class ChainPlan:
     """Owns a circuit handle and a chain-partition plan (t parts)."""
 
     def __init__(self, circuit_text: str, part_masks, tile_bits: int = 0, tail_max_qubits: int = 0,
-                 materialize_level: int = -1, mem_budget: int = 0):
+                 materialize_level: int = -1, mem_budget: int = 0, alloc="torch"):
+        self.allocator = _allocator(alloc)
         self._circ = qs_load_circuit(circuit_text)
         opts = qs_options(tile_bits, 0, tail_max_qubits, materialize_level, 0, mem_budget, 1)
+        if self.allocator is not None:
+            opts.alloc = self.allocator.struct
         try:
             self._plan = qs_partition_chain(self._circ, part_masks, opts)
         except Exception:
@@ -345,14 +398,23 @@ class ChainPlan:
             pass
 
 class Plan:
-    """Owns a circuit handle and a plan handle."""
+    """Owns a circuit handle and a plan handle.
+
+    ``alloc``: "torch" (default) routes the plan's device memory through
+    PyTorch's caching allocator; None lets the library call hipMalloc; any
+    object with a ``struct`` attribute (a ``qs_allocator``) is passed as is.
+    """
 
     def __init__(self, circuit_text: str, upper_mask: int, tile_bits: int = 0,
                  coalesce_bits: int = 0, tail_max_qubits: int = 0, materialize_level: int = -1,
-                 plain: bool = False, mem_budget: int = 0, one_stream: bool = False):
+                 plain: bool = False, mem_budget: int = 0, one_stream: bool = False,
+                 copies_per_launch: int = 0, alloc="torch"):
+        self.allocator = _allocator(alloc)
         self._circ = qs_load_circuit(circuit_text)
         opts = qs_options(tile_bits, coalesce_bits, tail_max_qubits, materialize_level,
-                          1 if plain else 0, mem_budget, 1 if one_stream else 0)
+                          1 if plain else 0, mem_budget, 1 if one_stream else 0, copies_per_launch)
+        if self.allocator is not None:
+            opts.alloc = self.allocator.struct
         try:
             self._plan = qs_partition(self._circ, upper_mask, opts)
         except Exception:

@@ -28,7 +28,26 @@ qs_status fail(qs_status s, const std::string& m) {
   return s;
 }
 
-// Device buffers of a plan, recycled between calls of the same size.
+// Device memory of a plan: the caller's allocator (qs_options.alloc) or
+// hipMalloc / hipFree.
+struct DevAlloc {
+  qs_allocator a{};
+  void* get(size_t bytes) {
+    if (a.alloc) return a.alloc(bytes, a.ctx);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
+  }
+  void put(void* p) {
+    if (!p) return;
+    if (a.free) a.free(p, a.ctx);
+    else (void)hipFree(p);
+  }
+};
+
 // Device buffers of a plan, reused across calls.  The two halves of a copy
 // block run on two streams; a released buffer is reused only by the stream
 // that released it until settle(), called where the streams are ordered by
@@ -43,6 +62,7 @@ struct Pool {
   };
   std::vector<Ent> ents;
   size_t held = 0;
+  DevAlloc* da = nullptr;
   void* get(size_t bytes, void* stream) {
     if (bytes == 0) bytes = 256;
     Ent* best = nullptr;
@@ -54,15 +74,12 @@ struct Pool {
       best->used = true;
       return best->p;
     }
-    void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-      (void)hipGetLastError();
+    void* p = da->get(bytes);
+    if (!p) {
       // release idle buffers and retry once
       trim();
-      if (hipMalloc(&p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-      }
+      p = da->get(bytes);
+      if (!p) return nullptr;
     }
     ents.push_back(Ent{p, bytes, true, false, stream});
     held += bytes;
@@ -96,14 +113,14 @@ struct Pool {
     for (Ent& e : ents) {
       if (e.used) keep.push_back(e);
       else {
-        (void)hipFree(e.p);
+        da->put(e.p);
         held -= e.bytes;
       }
     }
     ents.swap(keep);
   }
   void release_all() {
-    for (Ent& e : ents) (void)hipFree(e.p);
+    for (Ent& e : ents) da->put(e.p);
     ents.clear();
     held = 0;
   }
@@ -137,6 +154,7 @@ struct qs_circuit {
 
 // A planned block of one half: schedule, descriptors (host and device).
 struct Prepared {
+  DevAlloc* da = nullptr;  // owner of dev
   SidePlan sp;
   std::vector<PassDesc> pds;
   TailDesc td{};
@@ -158,7 +176,7 @@ struct Prepared {
   double phi_re = 1, phi_im = 0;
   double tail_flops = 0;  // 2x2-gate flops of the leaf evaluation
   ~Prepared() {
-    if (dev) (void)hipFree(dev);
+    if (dev) da->put(dev);
   }
 };
 
@@ -185,8 +203,17 @@ struct qs_plan {
   std::vector<Cut> cuts;
   Side side[2];
   qs_options opts{};
+  DevAlloc dalloc;
   Pool pool;
+  // memory budget of one half's schedule: fixed at the first run, the plan's
+  // budget divided by the sides that run at the same time (concurrency)
+  size_t side_budget = 0;
+  bool budget_set = false;
+  int concurrency = 1;
   bool registered = false;
+  // qs_plan_reset without keep_bitstrings leaves the registered set here
+  // (stale): registering the same set again reuses its tables and block plans
+  bool stale = false;
   std::vector<uint64_t> bits;
   std::vector<uint32_t> vals[2];
   std::vector<int> idx[2];
@@ -213,17 +240,23 @@ struct qs_plan {
   double tms[4] = {0, 0, 0, 0};
   double counts[4] = {0, 0, 0, 0};
   double pass_bytes = 0, gemm_flops = 0, tail_flops = 0;
+  qs_plan() { pool.da = &dalloc; }
+  // cached block plans and their copy tables; the caller synchronises first
+  void drop_block_plans() {
+    cache.clear();
+    for (auto& kv : perms) {
+      dalloc.put(kv.second.d_perm);
+      dalloc.put(kv.second.d_colsel);
+    }
+    perms.clear();
+  }
   ~qs_plan() {
     (void)hipDeviceSynchronize();
     for (EvRec& e : events) {
       (void)hipEventDestroy(e.a);
       (void)hipEventDestroy(e.b);
     }
-    cache.clear();
-    for (auto& kv : perms) {
-      (void)hipFree(kv.second.d_perm);
-      if (kv.second.d_colsel) (void)hipFree(kv.second.d_colsel);
-    }
+    drop_block_plans();
     pool.release_all();
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
@@ -241,17 +274,28 @@ namespace {
 
 int ctz64(uint64_t x) { return x ? __builtin_ctzll(x) : 64; }
 
-PlanKnobs knobs_of(const qs_plan* p, int S) {
+// Cached block plans (one per half and copy block) kept at most; the flat
+// form plans every copy as a block of its own.
+constexpr size_t kMaxCachedSides = 4096;
+
+PlanKnobs knobs_of(qs_plan* p, int S) {
   PlanKnobs k;
   if (p->opts.tile_bits > 0) k.tile_bits = std::min(p->opts.tile_bits, 13);
   if (p->opts.coalesce_bits > 0) k.coalesce_bits = p->opts.coalesce_bits;
   if (p->opts.tail_max_qubits > 0) k.tail_max_qubits = std::min(p->opts.tail_max_qubits, 10);
   k.force_lstar = p->opts.materialize_level;
-  k.mem_budget = p->opts.mem_budget;
-  if (k.mem_budget == 0) {
-    size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) == hipSuccess) k.mem_budget = (size_t)(0.85 * (double)fr);
+  if (!p->budget_set) {
+    // once per plan, so that the same inputs always give the same schedule
+    size_t total = p->opts.mem_budget;
+    if (total == 0) {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess) total = (size_t)(0.8 * (double)tot);
+      else (void)hipGetLastError();
+    }
+    p->side_budget = total / (size_t)std::max(1, p->concurrency);
+    p->budget_set = true;
   }
+  k.mem_budget = p->side_budget;
   k.S = S;
   k.one_op_per_pass = p->opts.plain != 0;
   return k;
@@ -291,13 +335,10 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
     P->phi[sidx][1] = (*out)->phi_im;
     return QS_OK;
   }
-  if (P->cache.size() > 4096) {
-    (void)hipDeviceSynchronize();
-    P->cache.clear();
-  }
   const int c = (int)P->cuts.size();
   const int S = (int)P->vals[sidx].size();
   std::unique_ptr<Prepared> pr(new Prepared());
+  pr->da = &P->dalloc;
   SidePlan& sp = pr->sp;
   std::string err;
   if (!plan_side(P->side[sidx], c, blk, knobs_of(P, S), sp, err)) return fail(QS_ERR_UNSUPPORTED, err);
@@ -601,11 +642,8 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   std::memcpy(host.data() + pr->o_sv, sv.data(), b_sv);
   if (b_tl) std::memcpy(host.data() + pr->o_tl, tl.data(), b_tl);
   if (b_rows) std::memcpy(host.data() + pr->o_rows, rows_v.data(), b_rows);
-  if (hipMalloc(&pr->dev, total) != hipSuccess) {
-    (void)hipGetLastError();
-    pr->dev = nullptr;
-    return fail(QS_ERR_OOM, "descriptor buffer");
-  }
+  pr->dev = (char*)P->dalloc.get(total);
+  if (!pr->dev) return fail(QS_ERR_OOM, "descriptor buffer");
   HIPCHECK(hipMemcpy(pr->dev, host.data(), total, hipMemcpyHostToDevice));
   *out = pr.get();
   P->cache[key] = std::move(pr);
@@ -684,6 +722,22 @@ qs_status register_bits(qs_plan* P, const uint64_t* bits, size_t m) {
     return QS_OK;
   }
   if (!bits || m == 0) return fail(QS_ERR_ARG, "no bitstrings registered yet");
+  if (P->stale) {
+    if (m == P->bits.size() && std::memcmp(bits, P->bits.data(), m * 8) == 0) {
+      // the set registered before the last reset: its value tables and
+      // cached block plans still hold
+      P->stale = false;
+      P->registered = true;
+      return QS_OK;
+    }
+    for (int k = 0; k < 2; ++k) {
+      if (P->d_vals[k]) P->pool.put_unordered(P->d_vals[k]);
+      if (P->d_idx[k]) P->pool.put_unordered(P->d_idx[k]);
+      P->d_vals[k] = nullptr;
+      P->d_idx[k] = nullptr;
+    }
+    P->stale = false;
+  }
   for (size_t t = 0; t < m; ++t)
     if (bits[t] & ~full) return fail(QS_ERR_ARG, "bitstring has bits set beyond the qubit count");
   std::vector<uint32_t> vals[2];
@@ -725,12 +779,7 @@ qs_status register_bits(qs_plan* P, const uint64_t* bits, size_t m) {
   // a new value set changes the leaf evaluation (and, through the cost model,
   // possibly the trees): drop cached block plans and copy tables
   (void)hipDeviceSynchronize();
-  P->cache.clear();
-  for (auto& kv : P->perms) {
-    (void)hipFree(kv.second.d_perm);
-    if (kv.second.d_colsel) (void)hipFree(kv.second.d_colsel);
-  }
-  P->perms.clear();
+  P->drop_block_plans();
   P->registered = true;
   return QS_OK;
 }
@@ -886,6 +935,12 @@ qs_status qs_partition(const qs_circuit* circ, uint64_t upper_mask, const qs_opt
   }
   if (p->opts.tile_bits < 0 || p->opts.coalesce_bits < 0 || p->opts.tail_max_qubits < 0)
     return fail(QS_ERR_ARG, "negative option");
+  if ((p->opts.alloc.alloc == nullptr) != (p->opts.alloc.free == nullptr))
+    return fail(QS_ERR_ARG, "allocator needs both alloc and free");
+  if (p->opts.copies_per_launch & (p->opts.copies_per_launch - 1))
+    return fail(QS_ERR_ARG, "copies_per_launch must be a power of two");
+  p->dalloc.a = p->opts.alloc;
+  p->concurrency = (p->opts.one_stream || p->opts.plain) ? 1 : 2;
   std::string err;
   if (!build_partition(p->circ, upper_mask, p->cuts, p->side[0], p->side[1], err))
     return fail(QS_ERR_ARG, err);
@@ -995,7 +1050,9 @@ qs_status qs_plan_dump(const qs_plan* plan, uint64_t copy_begin, uint64_t copy_e
   if (copy_begin >= copy_end || copy_end > (1ULL << c)) return fail(QS_ERR_ARG, "copy range outside [0, 2^c)");
   // the first block of the range, as qs_run_halves would split it
   int sz = std::min(ctz64(copy_begin), c);
-  while (sz > 0 && copy_begin + (1ULL << sz) > copy_end) --sz;
+  while (sz > 0 && (copy_begin + (1ULL << sz) > copy_end ||
+                    (plan->opts.copies_per_launch && (1ULL << sz) > plan->opts.copies_per_launch)))
+    --sz;
   if (plan->opts.plain) sz = 0;
   Block blk;
   blk.k0 = copy_begin;
@@ -1031,17 +1088,10 @@ qs_status qs_plan_reset(qs_plan* plan, int keep_bitstrings) {
   plan->blocks.clear();
   plan->ranges.clear();
   plan->unordered = true;
-  if (!keep_bitstrings) {
-    for (int k = 0; k < 2; ++k) {
-      if (plan->d_vals[k]) plan->pool.put_unordered(plan->d_vals[k]);
-      if (plan->d_idx[k]) plan->pool.put_unordered(plan->d_idx[k]);
-      plan->d_vals[k] = nullptr;
-      plan->d_idx[k] = nullptr;
-      plan->vals[k].clear();
-      plan->idx[k].clear();
-    }
-    plan->bits.clear();
+  if (!keep_bitstrings && plan->registered) {
+    // the tables stay (stale) until a different set is registered
     plan->registered = false;
+    plan->stale = true;
   }
   return QS_OK;
 }
@@ -1071,7 +1121,9 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
   uint64_t k = copy_begin;
   while (k < copy_end) {
     int sz = std::min(ctz64(k), c);
-    while (sz > 0 && k + (1ULL << sz) > copy_end) --sz;
+    while (sz > 0 && (k + (1ULL << sz) > copy_end ||
+                      (plan->opts.copies_per_launch && (1ULL << sz) > plan->opts.copies_per_launch)))
+      --sz;
     if (plan->opts.plain) sz = 0;  // the flat form runs every copy on its own
     Block blk;
     blk.k0 = k;
@@ -1080,6 +1132,15 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
     br.k0 = k;
     br.k1 = k + (1ULL << sz);
     const uint64_t Kb = 1ULL << sz;
+    if (plan->cache.size() + 2 > kMaxCachedSides &&
+        plan->cache.find(std::make_tuple(0, blk.k0, blk.p)) == plan->cache.end()) {
+      // bound the host and device memory of cached block plans (the flat
+      // form plans every copy as a block of its own): drop them all, with
+      // their copy tables, before this block plans either side, once no
+      // queued kernel reads their descriptors
+      HIPCHECK(hipDeviceSynchronize());
+      plan->drop_block_plans();
+    }
     Prepared* prs[2] = {nullptr, nullptr};
     for (int sidx = 0; sidx < 2; ++sidx) {
       s = prepare_side(plan, sidx, blk, &prs[sidx]);
@@ -1095,10 +1156,20 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
       for (uint64_t nu = 0; nu < Kb; ++nu) inv[kl[nu]] = (uint32_t)nu;
       for (uint64_t nu = 0; nu < Kb; ++nu) perm[nu] = inv[ku[nu]];
       BlockMaps bm;
-      if (hipMalloc(&bm.d_perm, Kb * sizeof(uint32_t)) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(QS_ERR_OOM, "copy permutation");
-      }
+      // the tables go to the cache at the end; a failure on the way frees them
+      struct Guard {
+        DevAlloc* da;
+        BlockMaps* bm;
+        bool keep = false;
+        ~Guard() {
+          if (!keep) {
+            da->put(bm->d_perm);
+            da->put(bm->d_colsel);
+          }
+        }
+      } guard{&plan->dalloc, &bm};
+      bm.d_perm = (uint32_t*)plan->dalloc.get(Kb * sizeof(uint32_t));
+      if (!bm.d_perm) return fail(QS_ERR_OOM, "copy permutation");
       HIPCHECK(hipMemcpy(bm.d_perm, perm.data(), Kb * sizeof(uint32_t), hipMemcpyHostToDevice));
       bm.nu_to_k = std::make_shared<std::vector<uint32_t>>(ku);
       const TailDesc& tl = prs[1]->td;
@@ -1123,13 +1194,12 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
           if (nl & ((1u << bm.ne) - 1)) return fail(QS_ERR_UNSUPPORTED, "internal: end bits do not match");
           colsel[v] = nl >> bm.ne;
         }
-        if (hipMalloc(&bm.d_colsel, K0 * sizeof(uint32_t)) != hipSuccess) {
-          (void)hipGetLastError();
-          return fail(QS_ERR_OOM, "copy permutation");
-        }
+        bm.d_colsel = (uint32_t*)plan->dalloc.get(K0 * sizeof(uint32_t));
+        if (!bm.d_colsel) return fail(QS_ERR_OOM, "copy permutation");
         HIPCHECK(hipMemcpy(bm.d_colsel, colsel.data(), K0 * sizeof(uint32_t), hipMemcpyHostToDevice));
       }
       pit = plan->perms.emplace(pkey, bm).first;
+      guard.keep = true;
     }
     br.nu_to_k = pit->second.nu_to_k;
     const BlockMaps& bmap = pit->second;
@@ -1226,18 +1296,21 @@ qs_status qs_amplitudes(qs_plan* plan, const uint64_t* bitstrings, size_t m, qs_
   if (!amps || !sums) return fail(QS_ERR_OOM, "output buffers");
   qs_status s = assemble(plan, prec, amps, sums, st);
   if (s != QS_OK) return s;
-  HIPCHECK(hipMemcpyAsync(out_c64, amps, m * sizeof(float2), hipMemcpyDeviceToHost, st));
+  // staged on the host: the caller's arrays are written only on success
+  std::vector<float2> ha(m);
   double h[2];
+  HIPCHECK(hipMemcpyAsync(ha.data(), amps, m * sizeof(float2), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipMemcpyAsync(h, sums, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
+  plan->pool.put(amps, st);
+  plan->pool.put(sums, st);
+  std::memcpy(out_c64, ha.data(), m * sizeof(float2));
   if (out_stats) {
     const double n = plan->circ.n;
     out_stats[0] = h[0];
     out_stats[1] = std::ldexp(h[0] / (double)m, (int)n);
     out_stats[2] = std::ldexp(h[1] / (double)m, (int)(2 * n));
   }
-  plan->pool.put(amps, st);
-  plan->pool.put(sums, st);
   return QS_OK;
 }
 
@@ -1368,6 +1441,7 @@ struct qs_mplan {
   std::vector<int> link_c;                       // cuts of link i (parts i, i+1)
   std::vector<std::unique_ptr<qs_plan>> parts;   // one-sided plans
   std::vector<std::vector<int>> link_of;         // per part, per local cut: its link
+  DevAlloc dalloc;
   Pool pool;
   bool registered = false;
   std::vector<uint64_t> bits;
@@ -1377,10 +1451,10 @@ struct qs_mplan {
   std::vector<uint32_t*> d_perm;  // per part: natural column of each ordered column
   int split = 1;  // parts [0, split) contract from the left end, [split, t) from the right
   hipEvent_t ev_fork = nullptr;   // the parts run on their plans' streams (qs_plan::aux)
+  qs_mplan() { pool.da = &dalloc; }
   ~qs_mplan() {
     (void)hipDeviceSynchronize();
-    for (uint32_t* q : d_perm)
-      if (q) (void)hipFree(q);
+    for (uint32_t* q : d_perm) dalloc.put(q);
     pool.release_all();
     if (ev_fork) (void)hipEventDestroy(ev_fork);
   }
@@ -1417,8 +1491,11 @@ qs_status qs_partition_chain(const qs_circuit* circ, const uint64_t* part_masks,
     raw.emplace_back(g.cycle, a, b, owner[a]);
   }
   std::sort(raw.begin(), raw.end());
+  if (opts && (opts->alloc.alloc == nullptr) != (opts->alloc.free == nullptr))
+    return fail(QS_ERR_ARG, "allocator needs both alloc and free");
   std::unique_ptr<qs_mplan> mp(new (std::nothrow) qs_mplan());
   if (!mp) return fail(QS_ERR_OOM, "host allocation");
+  if (opts) mp->dalloc.a = opts->alloc;
   mp->circ = c;
   mp->t = t;
   mp->masks.assign(part_masks, part_masks + t);
@@ -1438,6 +1515,8 @@ qs_status qs_partition_chain(const qs_circuit* circ, const uint64_t* part_masks,
       pp->opts.materialize_level = -1;
     }
     pp->opts.one_stream = 1;
+    pp->dalloc.a = pp->opts.alloc;
+    pp->concurrency = t;  // the parts run at the same time
     std::map<std::pair<int, int>, int> cut_of;
     for (auto& r : raw) {
       const int link = std::get<3>(r);
@@ -1616,10 +1695,10 @@ qs_status qs_chain_amplitudes_device(qs_mplan* mp, float* d_out_c64, double* d_o
         const size_t col = left ? ((size_t)later << ne_) | earlier : ((size_t)earlier << nl_) | later;
         perm[col] = (uint32_t)nu;
       }
-      uint32_t* d = nullptr;
-      HIPCHECK(hipMalloc(&d, K * sizeof(uint32_t)));
-      HIPCHECK(hipMemcpy(d, perm.data(), K * sizeof(uint32_t), hipMemcpyHostToDevice));
+      uint32_t* d = (uint32_t*)mp->dalloc.get(K * sizeof(uint32_t));
+      if (!d) return fail(QS_ERR_OOM, "part column order");
       mp->d_perm[p] = d;
+      HIPCHECK(hipMemcpy(d, perm.data(), K * sizeof(uint32_t), hipMemcpyHostToDevice));
     }
     HIPCHECK(launch_permute_cols(X, O, mp->d_perm[p], S, (int)K, ps));
     pp->pool.put(X, ps);
@@ -1699,18 +1778,21 @@ qs_status qs_chain_amplitudes(qs_mplan* mp, const uint64_t* bits, size_t m, floa
   if (!amps || !sums) return fail(QS_ERR_OOM, "output buffers");
   s = qs_chain_amplitudes_device(mp, (float*)amps, sums, hip_stream);
   if (s != QS_OK) return s;
-  HIPCHECK(hipMemcpyAsync(out_c64, amps, m * sizeof(float2), hipMemcpyDeviceToHost, st));
+  // staged on the host: the caller's arrays are written only on success
+  std::vector<float2> ha(m);
   double h[2];
+  HIPCHECK(hipMemcpyAsync(ha.data(), amps, m * sizeof(float2), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipMemcpyAsync(h, sums, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
+  mp->pool.put(amps, st);
+  mp->pool.put(sums, st);
+  std::memcpy(out_c64, ha.data(), m * sizeof(float2));
   if (out_stats) {
     const int n = mp->circ.n;
     out_stats[0] = h[0];
     out_stats[1] = std::ldexp(h[0] / (double)m, n);
     out_stats[2] = std::ldexp(h[1] / (double)m, 2 * n);
   }
-  mp->pool.put(amps, st);
-  mp->pool.put(sums, st);
   return QS_OK;
 }
 

@@ -3,14 +3,16 @@
 Small circuits (18-20 qubits) against the oracle's full state vector, every
 amplitude; at 48 qubits, beyond the state vector, the four-part chain against
 the two-part path (itself checked against the oracle at 36-48 qubits) on the
-same bitstrings.  Error measure as in test_gpu_parity: norm-wise relative
-error, 1e-5 for the FP32 path.
+same bitstrings.  Bounds as in test_gpu_parity (checks.assert_close):
+norm-wise and element-wise, tolerance 1e-5 for the FP32 path.
 """
 
 import sys
 
 import numpy as np
 import pytest
+
+from checks import assert_close, errors
 
 from oracle import circuit as OC, statevector as SV
 from workloads import circuits as W
@@ -30,9 +32,6 @@ def say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
 
-
-def relerr(a, ref):
-    return float(np.linalg.norm(a.astype(np.complex128) - ref) / np.linalg.norm(ref))
 
 
 def band_masks(rows, cols, bands):
@@ -68,7 +67,7 @@ def test_chain_all_amplitudes(rows, cols, depth, bands, two_qubit):
     finally:
         cp.close()
     ref = SV.simulate(OC.parse(text))
-    assert relerr(amp, ref) < 1e-5
+    assert_close(amp, ref, 1e-5)
     assert abs(stats[0] - 1.0) < 1e-5  # all amplitudes: the norm
 
 
@@ -91,7 +90,7 @@ def test_chain_48q_against_two_part_path():
         amp2, _ = p.amplitudes(bits)
     finally:
         p.close()
-    assert relerr(amp4, amp2.astype(np.complex128)) < 1e-5
+    assert_close(amp4, amp2.astype(np.complex128), 1e-5)
 
 
 def test_chain_repeated_and_schedule_knobs():
@@ -114,7 +113,7 @@ def test_chain_repeated_and_schedule_knobs():
             continue
         finally:
             cp.close()
-        assert relerr(amp, ref) < 1e-5
+        assert_close(amp, ref, 1e-5)
         assert np.array_equal(amp[300:307], amp[:7])
 
 
@@ -156,7 +155,7 @@ def test_chain_degenerate_parts(depth, masks_fn):
     finally:
         cp.close()
     assert 0 in info[1] or 1 in info[0]
-    assert relerr(amp, SV.simulate(OC.parse(text))) < 1e-5
+    assert_close(amp, SV.simulate(OC.parse(text)), 1e-5)
 
 
 @pytest.mark.parametrize("rows,cols,depth,bands,per_band", [
@@ -179,4 +178,4 @@ def test_chain_against_multipart_oracle(rows, cols, depth, bands, per_band):
         cp.close()
     say("case chain: oracle")
     ref = MP.amplitudes(OC.parse(text), masks, bits)
-    assert relerr(amp, ref) < 1e-5
+    assert_close(amp, ref, 1e-5)

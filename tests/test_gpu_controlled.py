@@ -4,9 +4,9 @@ The oracle splits a cut controlled-U literally: P_b on the control and U^b on
 the target, in whichever half each lies.  The library stores CNOT and CY as a
 CZ between basis changes on the target, so its copies equal the oracle's
 when every cut gate's control is in the upper half and are the mirrored split
-otherwise; the amplitudes (sums over all copies) agree in every case.  Error
-measure and bounds as in test_gpu_parity: norm-wise relative error, 1e-5 for
-FP32 and 1e-4 for the split-BF16 assembly.
+otherwise; the amplitudes (sums over all copies) agree in every case.  Bounds
+as in test_gpu_parity (checks.assert_close): norm-wise and element-wise,
+tolerance 1e-5 for FP32 and 1e-4 for the split-BF16 assembly.
 """
 
 import os
@@ -14,6 +14,8 @@ import sys
 
 import numpy as np
 import pytest
+
+from checks import assert_close, errors
 
 from oracle import circuit as OC, partition as P, statevector as SV
 from workloads import circuits as W, product_bitstrings, workload
@@ -37,9 +39,6 @@ def say(msg):
     sys.stdout.flush()
 
 
-def relerr(a, ref):
-    return float(np.linalg.norm(a.astype(np.complex128) - ref) / np.linalg.norm(ref))
-
 
 @pytest.mark.parametrize("two_qubit,orient,seed,prec", [
     ("cx", "random", 6, 0),
@@ -61,7 +60,7 @@ def test_controlled_all_amplitudes(two_qubit, orient, seed, prec):
         amp, _ = p.amplitudes(bits, prec)
     finally:
         p.close()
-    assert relerr(amp, SV.simulate(oc)) < TOL[prec]
+    assert_close(amp, SV.simulate(oc), TOL[prec])
 
 
 def test_controlled_per_copy_half_amplitudes():
@@ -82,7 +81,7 @@ def test_controlled_per_copy_half_amplitudes():
         p.close()
     A, B = P.gathered_halves(oc, mask, np.sort(uu.astype(np.int64)), np.sort(ll.astype(np.int64)))
     for g, ref in zip(got, (A, B)):
-        assert relerr(g.T, ref) < 1e-5
+        assert_close(g.T, ref, 1e-5)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -102,4 +101,4 @@ def test_grid6x6_d16_mixed_golden(prec):
         amp, _ = p.amplitudes(bits, prec)
     finally:
         p.close()
-    assert relerr(amp, g["amp"]) < TOL[prec]
+    assert_close(amp, g["amp"], TOL[prec])

@@ -3,14 +3,17 @@
 Degenerate partitions (no cut, a one-qubit half, a circuit of depth 0), the
 smallest and ragged bitstring sets (one bitstring, repeated bitstrings, value
 grids that fill no kernel tile), the all-zero and all-one bitstrings, and both
-assembly precisions.  Error measure as in test_gpu_parity: norm-wise relative
-error, 1e-5 for FP32 and 1e-4 for split-BF16.
+assembly precisions.  Bounds as in test_gpu_parity (checks.assert_close):
+norm-wise relative error and the largest single error against rms(a_ref),
+tolerance 1e-5 for FP32 and 1e-4 for split-BF16.
 """
 
 import sys
 
 import numpy as np
 import pytest
+
+from checks import assert_close, errors
 
 from oracle import circuit as OC, statevector as SV
 from workloads import circuits as W, product_bitstrings
@@ -32,9 +35,6 @@ def say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
 
-
-def relerr(a, ref):
-    return float(np.linalg.norm(a.astype(np.complex128) - ref) / np.linalg.norm(ref))
 
 
 def amps(Q, text, mask, bits, prec=0, **kw):
@@ -62,7 +62,7 @@ def test_no_cut(prec):
     assert p.n_cuts == 0
     p.close()
     a, _ = amps(Q, text, 0b0011, bits, prec)
-    assert relerr(a, reference(text, bits)) < TOL[prec]
+    assert_close(a, reference(text, bits), TOL[prec])
 
 
 def test_depth_zero():
@@ -83,7 +83,7 @@ def test_one_qubit_half():
     bits = np.arange(512, dtype=np.uint64)
     say("case one-qubit half")
     a, _ = amps(Q, text, 0b1, bits)
-    assert relerr(a, reference(text, bits)) < 1e-5
+    assert_close(a, reference(text, bits), 1e-5)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -113,7 +113,7 @@ def test_repeated_and_extreme_bitstrings():
     say("case repeated and extreme bitstrings")
     a, _ = amps(Q, text, mask, bits)
     ref = reference(text, bits)
-    assert relerr(a, ref) < 1e-5
+    assert_close(a, ref, 1e-5)
     assert a[0] == a[3] and a[1] == a[5] and a[2] == a[6]
 
 
@@ -126,7 +126,7 @@ def test_ragged_value_grid(prec):
     bits, _, _ = product_bitstrings(20, mask, 37, 101, 21, 22)
     say(f"case ragged 37 x 101 prec={prec}")
     a, _ = amps(Q, text, mask, bits, prec)
-    assert relerr(a, reference(text, bits)) < TOL[prec]
+    assert_close(a, reference(text, bits), TOL[prec])
 
 
 @pytest.mark.parametrize("depth,kw", [
@@ -152,4 +152,4 @@ def test_light_cone_sizes(depth, kw):
         # a limit the planner cannot meet is reported, not approximated
         assert e.status == -3, e
         pytest.skip(f"no schedule for {kw}")
-    assert relerr(a, reference(text, bits)) < 1e-5
+    assert_close(a, reference(text, bits), 1e-5)

@@ -31,6 +31,53 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(Q.EXPORTED)
 
 
+def test_binding_struct_layouts_match_the_header(tmp_path):
+    """The ctypes structures of the binding against the C header, compiled by
+    gcc: size and field offsets of qs_options, qs_allocator and qs_cut_score."""
+    import ctypes
+    import subprocess
+    src = tmp_path / "layout.c"
+    fields = {"qs_options": [f for f, _ in Q.qs_options._fields_],
+              "qs_allocator": [f for f, _ in Q.qs_allocator._fields_],
+              "qs_cut_score": [f for f, _ in Q.qs_cut_score._fields_]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for st, fs in fields.items():
+        lines.append(f'  printf("{st} size %zu\\n", sizeof({st}));')
+        for fld in fs:
+            lines.append(f'  printf("{st} {fld} %zu\\n", offsetof({st}, {fld}));')
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for ln in out.splitlines():
+        st, key, val = ln.split()
+        got[(st, key)] = int(val)
+    for st, fs in fields.items():
+        cls = getattr(Q, st)
+        assert got[(st, "size")] == ctypes.sizeof(cls), st
+        for fld in fs:
+            assert got[(st, fld)] == getattr(cls, fld).offset, (st, fld)
+
+
+def test_copies_per_launch_blocks():
+    """copies_per_launch caps the block the dump (and qs_run_halves) takes;
+    it must be a power of two."""
+    text = W.random_grid_circuit(4, 4, 16, 1)
+    mask = W.grid_rows_mask(4, 4, [0, 1])
+    p = Q.Plan(text, mask, alloc=None)
+    c = p.n_cuts
+    assert p.dump()["block"] == {"k0": 0, "p": 0}
+    p.close()
+    p = Q.Plan(text, mask, copies_per_launch=4, alloc=None)
+    assert p.dump()["block"] == {"k0": 0, "p": c - 2}
+    p.close()
+    with pytest.raises(Q.QSError) as e:
+        Q.Plan(text, mask, copies_per_launch=6, alloc=None)
+    assert e.value.status == -1
+
+
 def test_parse_errors():
     for bad in ["", "qubits 0\n", "qubits 65\n", "qubits 2\n0 cz 0 0\n", "qubits 2\n0 h 2\n",
                 "qubits 2\n1 h 0\n0 h 1\n", "qubits 2\n0 h 0\n0 t 0\n", "qubits 2\n0 foo 1\n",

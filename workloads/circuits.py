@@ -37,14 +37,15 @@ def _hp(rows: int) -> int:
     return (rows // 2 - 1) % 2
 
 
-def cz_pattern(rows: int, cols: int, position: int) -> list[tuple[int, int]]:
-    """CZ pairs (q0 < q1) of pattern position 1..8 on a rows x cols grid."""
+def cz_pattern(rows: int, cols: int, position: int, drop_rows=()) -> list[tuple[int, int]]:
+    """CZ pairs (q0 < q1) of pattern position 1..8 on a rows x cols grid.
+    ``drop_rows``: rows r whose vertical bonds to row r + 1 never fire."""
     hp = _hp(rows)
     pairs: list[tuple[int, int]] = []
 
     def vert(row_parity_eq_hp: bool, col_parity: int) -> None:
         for r in range(rows - 1):
-            if ((r % 2) == hp) != row_parity_eq_hp:
+            if ((r % 2) == hp) != row_parity_eq_hp or r in drop_rows:
                 continue
             for c in range(cols):
                 if c % 2 == col_parity:
@@ -80,8 +81,13 @@ def cz_pattern(rows: int, cols: int, position: int) -> list[tuple[int, int]]:
 
 
 def random_grid_circuit_gates(rows: int, cols: int, depth: int, seed: int,
-                              two_qubit: str = "cz", orient: str = "random"):
-    """Return the gate list [(cycle, name, qubits...)] of the seeded circuit."""
+                              two_qubit: str = "cz", orient: str = "random", drop_rows=()):
+    """Return the gate list [(cycle, name, qubits...)] of the seeded circuit.
+
+    ``drop_rows``: rows r whose vertical bonds to row r + 1 are left out, which
+    splits the grid into bands of rows with no gate between them (the bands
+    are then independent circuits; the one-qubit gates follow the same rule
+    on the remaining CZ gates)."""
     if rows < 2 or cols < 1:
         raise ValueError("grid needs at least 2 rows and 1 column")
     if two_qubit not in ("cz", "cx", "cy", "mixed") or orient not in ("random", "low"):
@@ -93,7 +99,7 @@ def random_grid_circuit_gates(rows: int, cols: int, depth: int, seed: int,
     prev_busy: set[int] = set()
     last_1q: dict[int, str] = {}
     for t in range(1, depth + 1):
-        pairs = cz_pattern(rows, cols, ((t - 1) % 8) + 1)
+        pairs = cz_pattern(rows, cols, ((t - 1) % 8) + 1, tuple(drop_rows))
         busy = {q for p in pairs for q in p}
         if t >= 2:
             for q in range(n):
@@ -130,10 +136,12 @@ def gates_to_text(n: int, gates, rows: int | None = None, cols: int | None = Non
 
 
 def random_grid_circuit(rows: int, cols: int, depth: int, seed: int = 0,
-                        two_qubit: str = "cz", orient: str = "random") -> str:
+                        two_qubit: str = "cz", orient: str = "random", drop_rows=()) -> str:
     """Circuit text of the seeded universal random circuit on a rows x cols grid."""
-    gates = random_grid_circuit_gates(rows, cols, depth, seed, two_qubit, orient)
+    gates = random_grid_circuit_gates(rows, cols, depth, seed, two_qubit, orient, drop_rows)
     extra = "" if two_qubit == "cz" else f" {two_qubit} {orient}"
+    if drop_rows:
+        extra += " without the vertical bonds below rows " + ",".join(str(r) for r in sorted(drop_rows))
     return gates_to_text(rows * cols, gates, rows, cols,
                          comment=f"random grid circuit {rows}x{cols} depth {depth} seed {seed}{extra}")
 

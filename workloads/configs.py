@@ -30,6 +30,7 @@ class Workload:
     note: str = ""
     two_qubit: str = "cz"    # cz, or the controlled gates cx / cy / mixed
     orient: str = "random"   # which endpoint of a controlled gate is the control
+    drop_rows: tuple = ()    # rows whose vertical bonds to the next row are left out
 
     @property
     def n(self) -> int:
@@ -37,7 +38,7 @@ class Workload:
 
     def circuit_text(self) -> str:
         return random_grid_circuit(self.rows, self.cols, self.depth, self.seed,
-                                   self.two_qubit, self.orient)
+                                   self.two_qubit, self.orient, self.drop_rows)
 
 
 def _all_upper_lower(rows, cols, upper_rows):
@@ -74,6 +75,12 @@ _add(Workload("grid8x8_d22_slice64", 8, 8, 22, 0, grid_rows_mask(8, 8, [0, 1, 2,
               note="64 qubits, 32+32 halves, copies [0, 64) of 65536: partial amplitudes"))
 
 
+_add(Workload("grid8x8_d22_bands", 8, 8, 22, 0, grid_rows_mask(8, 8, [0, 1, 2, 3]), 1024, 1024,
+              1008, 2008, copy_begin=0, copy_end=64, drop_rows=(1, 5),
+              note="64 qubits, 32+32 halves, copies [0, 64) of 65536, with the vertical bonds "
+                   "between rows 1-2 and 5-6 left out: each half is an independent 16-qubit band "
+                   "(rows 0-1, rows 6-7) times the 16 qubits next to the cut, so the FP64 oracle "
+                   "pins the partial amplitudes of the 32-qubit halves from 16-qubit states"))
 _add(Workload("grid6x6_d16_mixed", 6, 6, 16, 0, grid_rows_mask(6, 6, [0, 1, 2]), 256, 256,
               1007, 2007, two_qubit="mixed", orient="random",
               note="36 qubits, 18+18 halves, each two-qubit gate drawn from CZ, CNOT and CY with "

@@ -235,6 +235,23 @@ qs_status qs_half_amplitudes(qs_plan* plan, int side, uint64_t copy_begin, uint6
 qs_status qs_amplitudes_device(qs_plan* plan, qs_precision prec, float* d_out_c64,
                                double* d_out_sums, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * as qs_amplitudes_device, with every temporary buffer of the assembly (the
+ * value grid, split-K partial products, split-BF16 operand planes, FP64
+ * partial sums) taken from a static region of 256 MiB per device that the
+ * library holds until the process ends, instead of from the plan's
+ * allocator.  The call allocates nothing and creates no event (timing, if
+ * enabled, skips it); it still needs the plan's run copies and its
+ * registered bitstrings, as qs_amplitudes_device does.  Every call on one
+ * device shares that device's region: calls that overlap on one device (on
+ * different streams, or from different threads) race and must not be made.
+ * Errors: QS_ERR_ARG, QS_ERR_STATE (no copies run), QS_ERR_UNSUPPORTED (the
+ * assembly needs more than 256 MiB of scratch; about 56 MiB in FP32 and
+ * 190 MiB in split-BF16 for 1024 x 1024 values over 2^14 copies), QS_ERR_HIP. */
+qs_status qs_amplitudes_device_static(qs_plan* plan, qs_precision prec, float* d_out_c64,
+                                      double* d_out_sums, void* hip_stream);
+
 /* Forget every run copy of the plan.  keep_bitstrings = 1 keeps the
  * registered bitstrings (a new round of qs_run_halves may pass NULL);
  * 0 forgets them too.  Device buffers and cached block plans are kept. */

@@ -29,7 +29,8 @@ _STATUS = {0: "QS_OK", -1: "QS_ERR_ARG", -2: "QS_ERR_PARSE", -3: "QS_ERR_UNSUPPO
 
 EXPORTED = ("qs_last_error", "qs_load_circuit", "qs_circuit_info", "qs_circuit_free",
             "qs_partition", "qs_plan_info", "qs_plan_dump", "qs_plan_free", "qs_run_halves",
-            "qs_amplitudes", "qs_amplitudes_device", "qs_half_amplitudes", "qs_plan_reset",
+            "qs_amplitudes", "qs_amplitudes_device", "qs_amplitudes_device_static",
+            "qs_half_amplitudes", "qs_plan_reset",
             "qs_get_timing", "qs_set_timing", "qs_score_cut", "qs_choose_cut",
             "qs_partition_chain", "qs_chain_info", "qs_chain_register", "qs_chain_amplitudes_device",
             "qs_chain_amplitudes", "qs_chain_free")
@@ -137,6 +138,7 @@ def _load() -> C.CDLL:
     lib.qs_amplitudes.argtypes = [vp, u64p, C.c_size_t, C.c_int, C.POINTER(C.c_float),
                                   C.POINTER(C.c_double), vp]
     lib.qs_amplitudes_device.argtypes = [vp, C.c_int, vp, vp, vp]
+    lib.qs_amplitudes_device_static.argtypes = [vp, C.c_int, vp, vp, vp]
     lib.qs_half_amplitudes.argtypes = [vp, C.c_int, C.c_uint64, C.c_uint64, C.POINTER(C.c_float),
                                        C.c_size_t, C.POINTER(C.c_size_t), vp]
     lib.qs_plan_reset.argtypes = [vp, C.c_int]
@@ -281,6 +283,15 @@ def qs_amplitudes_device(plan, prec: int, d_out_ptr: int, d_sums_ptr: int | None
     _check(_lib.qs_amplitudes_device(plan, prec, C.c_void_p(d_out_ptr),
                                      C.c_void_p(d_sums_ptr) if d_sums_ptr else None,
                                      _stream_handle(stream)))
+
+
+def qs_amplitudes_device_static(plan, prec: int, d_out_ptr: int, d_sums_ptr: int | None = None,
+                                stream=None) -> None:
+    """As qs_amplitudes_device, with the assembly's scratch in the library's
+    static region (no allocation)."""
+    _check(_lib.qs_amplitudes_device_static(plan, prec, C.c_void_p(d_out_ptr),
+                                            C.c_void_p(d_sums_ptr) if d_sums_ptr else None,
+                                            _stream_handle(stream)))
 
 
 def qs_half_amplitudes(plan, side: int, copy_begin: int, copy_end: int, n_values: int,
@@ -439,6 +450,10 @@ class Plan:
     def amplitudes_device(self, prec: int, d_out_ptr: int, d_sums_ptr: int | None = None,
                           stream=None) -> None:
         qs_amplitudes_device(self._plan, prec, d_out_ptr, d_sums_ptr, stream)
+
+    def amplitudes_device_static(self, prec: int, d_out_ptr: int, d_sums_ptr: int | None = None,
+                                 stream=None) -> None:
+        qs_amplitudes_device_static(self._plan, prec, d_out_ptr, d_sums_ptr, stream)
 
     def half_amplitudes(self, side: int, copy_begin: int, copy_end: int, n_values: int,
                         stream=None) -> np.ndarray:

@@ -792,88 +792,123 @@ float2 phi_of(const qs_plan* plan) {
   return make_float2((float)(a * c - b * d), (float)(a * d + b * c));
 }
 
-qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_sums, hipStream_t st) {
-  plan->last_st = st;
+// Temporary device buffers of one assembly: from the plan's pool, or (static
+// form) carved in call order from a caller-given region.  Every request is
+// 256-byte aligned; release() returns the region to a mark (the stream orders
+// the next user after the previous one).
+struct Scratch {
+  qs_plan* P;
+  hipStream_t st;
+  char* base = nullptr;  // static region (nullptr: the pool)
+  size_t cap = 0, used = 0;
+  bool measure = false;  // only add up the bytes the requests need
+  void* get(size_t bytes) {
+    if (!base && !measure) return P->pool.get(bytes, st);
+    const size_t off = (used + 255) & ~(size_t)255;
+    if (!measure && off + bytes > cap) return nullptr;
+    used = off + bytes;
+    return measure ? (void*)(uintptr_t)256 : (void*)(base + off);  // measure: never dereferenced
+  }
+  void put(void* p) {
+    if (!base && !measure) P->pool.put(p, st);
+  }
+  size_t mark() const { return used; }
+  void release(size_t m) {
+    if (base || measure) used = m;
+  }
+};
+
+// Assembly of every run block into C, then the amplitudes of the registered
+// bitstrings into d_amps and their FP64 sums into d_sums.  Asynchronous.
+// sc.measure: no launch, only the scratch bytes (sc.used afterwards).
+qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_sums, Scratch& sc) {
+  hipStream_t st = sc.st;
+  const bool run = !sc.measure;
+  if (run) plan->last_st = st;
   const int M = (int)plan->vals[0].size(), N = (int)plan->vals[1].size();
   const size_t m = plan->bits.size();
   const int nb = prob_partial_blocks(m);
-  double* d_part = (double*)plan->pool.get((2 * (size_t)nb + 2) * sizeof(double), st);
+  double* d_part = (double*)sc.get((2 * (size_t)nb + 2) * sizeof(double));
   if (!d_part) return fail(QS_ERR_OOM, "assembly buffers");
   if (plan->list_mode) {
     // the bitstrings are far from a product set: one sum over the copies per
     // bitstring (FP32 accumulation for either precision)
-    Timer tm(plan, st, 2);
-    bool first = true;
-    for (BlockRes& b : plan->blocks) {
-      const int K = (int)(b.k1 - b.k0);
-      HIPCHECK(launch_gathered_dot(K, b.X[0], K, b.X[1], K, plan->d_idx[0], plan->d_idx[1], m,
-                                   d_amps, first ? 0 : 1, phi_of(plan), st));
-      ++tm.launches;
-      if (plan->timing) plan->gemm_flops += 8.0 * (double)m * (double)K;
-      first = false;
-    }
-  } else {
-    float2* C = (float2*)plan->pool.get((size_t)M * N * sizeof(float2), st);
-    if (!C) return fail(QS_ERR_OOM, "assembly buffers");
-    {
+    if (run) {
       Timer tm(plan, st, 2);
       bool first = true;
       for (BlockRes& b : plan->blocks) {
         const int K = (int)(b.k1 - b.k0);
-        if (b.ne > 0 && prec == QS_PREC_FP32) {
-          // one product per end-cut pattern sig over K >> ne copies (the
-          // transformed upper operand for sig against the lower values with
-          // that pattern, scattered to their columns of C), all in one launch
-          const int K0 = K >> b.ne, ng = 1 << b.ne;
-          int maxn = 1;
-          for (int g = 0; g < ng; ++g) maxn = std::max(maxn, b.goff[g + 1] - b.goff[g]);
-          const size_t wb = zgemm_grouped_workspace_bytes(M, N, maxn, K0, ng);
-          void* work = plan->pool.get(wb, st);
-          if (!work) return fail(QS_ERR_OOM, "assembly workspace");
-          HIPCHECK(launch_zgemm_grouped(M, N, maxn, K0, ng, (const int*)(b.d_rows + N), b.Ut,
-                                        (size_t)M * K0, b.X[1], C, N, first ? 0 : 1, work, st,
-                                        b.d_rows));
-          plan->pool.put(work, st);
-          tm.launches += 2;
-          if (plan->timing) plan->gemm_flops += 8.0 * M * N * (double)K0;
-        } else if (b.ne > 0) {
-          // split-BF16: the same grouped product, operands split once for all
-          // end-cut patterns
-          const int K0 = K >> b.ne, ng = 1 << b.ne;
-          int maxn = 1;
-          for (int g = 0; g < ng; ++g) maxn = std::max(maxn, b.goff[g + 1] - b.goff[g]);
-          const size_t wb = zgemm_grouped_bf16_workspace_bytes(M, N, maxn, K0, ng);
-          void* work = plan->pool.get(wb, st);
-          if (!work) return fail(QS_ERR_OOM, "assembly workspace");
-          HIPCHECK(launch_zgemm_grouped_bf16(M, N, maxn, K0, ng, (const int*)(b.d_rows + N), b.Ut,
-                                             b.X[1], C, N, first ? 0 : 1, work, st, b.d_rows));
-          plan->pool.put(work, st);
-          tm.launches += 4;
-          if (plan->timing) plan->gemm_flops += 8.0 * M * N * (double)K0;
-        } else {
-          const size_t wb = zgemm_workspace_bytes((int)prec, M, N, K);
-          void* work = plan->pool.get(wb, st);
-          if (!work) return fail(QS_ERR_OOM, "assembly workspace");
-          HIPCHECK(launch_zgemm_tn((int)prec, M, N, K, b.X[0], K, b.X[1], K, C, N, first ? 0 : 1,
-                                   work, st));
-          plan->pool.put(work, st);
-          tm.launches += prec == QS_PREC_FP32 ? 2 : 4;
-          if (plan->timing) plan->gemm_flops += 8.0 * M * N * (double)K;
-        }
+        HIPCHECK(launch_gathered_dot(K, b.X[0], K, b.X[1], K, plan->d_idx[0], plan->d_idx[1], m,
+                                     d_amps, first ? 0 : 1, phi_of(plan), st));
+        ++tm.launches;
+        if (plan->timing) plan->gemm_flops += 8.0 * (double)m * (double)K;
         first = false;
       }
     }
-    Timer tm(plan, st, 3);
-    HIPCHECK(launch_gather_amps(C, N, plan->d_idx[0], plan->d_idx[1], m, d_amps, phi_of(plan), st));
-    tm.launches += 1;
-    plan->pool.put(C, st);
+  } else {
+    float2* C = (float2*)sc.get((size_t)M * N * sizeof(float2));
+    if (!C) return fail(QS_ERR_OOM, "assembly buffers");
+    {
+      std::unique_ptr<Timer> tm(run ? new Timer(plan, st, 2) : nullptr);
+      bool first = true;
+      for (BlockRes& b : plan->blocks) {
+        const int K = (int)(b.k1 - b.k0);
+        const size_t mk = sc.mark();
+        if (b.ne > 0) {
+          // one product per end-cut pattern sig over K >> ne copies (the
+          // transformed upper operand for sig against the lower values with
+          // that pattern, scattered to their columns of C), all in one
+          // launch; split-BF16 splits both operands once for all patterns
+          const int K0 = K >> b.ne, ng = 1 << b.ne;
+          int maxn = 1;
+          for (int g = 0; g < ng; ++g) maxn = std::max(maxn, b.goff[g + 1] - b.goff[g]);
+          const bool f32 = prec == QS_PREC_FP32;
+          const size_t wb = f32 ? zgemm_grouped_workspace_bytes(M, N, maxn, K0, ng)
+                                : zgemm_grouped_bf16_workspace_bytes(M, N, maxn, K0, ng);
+          void* work = sc.get(wb);
+          if (!work) return fail(QS_ERR_OOM, "assembly workspace");
+          if (run) {
+            if (f32)
+              HIPCHECK(launch_zgemm_grouped(M, N, maxn, K0, ng, (const int*)(b.d_rows + N), b.Ut,
+                                            (size_t)M * K0, b.X[1], C, N, first ? 0 : 1, work, st,
+                                            b.d_rows));
+            else
+              HIPCHECK(launch_zgemm_grouped_bf16(M, N, maxn, K0, ng, (const int*)(b.d_rows + N),
+                                                 b.Ut, b.X[1], C, N, first ? 0 : 1, work, st,
+                                                 b.d_rows));
+            tm->launches += f32 ? 2 : 4;
+            if (plan->timing) plan->gemm_flops += 8.0 * M * N * (double)K0;
+          }
+          sc.put(work);
+        } else {
+          const size_t wb = zgemm_workspace_bytes((int)prec, M, N, K);
+          void* work = sc.get(wb);
+          if (!work) return fail(QS_ERR_OOM, "assembly workspace");
+          if (run) {
+            HIPCHECK(launch_zgemm_tn((int)prec, M, N, K, b.X[0], K, b.X[1], K, C, N,
+                                     first ? 0 : 1, work, st));
+            tm->launches += prec == QS_PREC_FP32 ? 2 : 4;
+            if (plan->timing) plan->gemm_flops += 8.0 * M * N * (double)K;
+          }
+          sc.put(work);
+        }
+        sc.release(mk);  // the next block's workspace reuses this one's
+        first = false;
+      }
+    }
+    if (run) {
+      Timer tm(plan, st, 3);
+      HIPCHECK(launch_gather_amps(C, N, plan->d_idx[0], plan->d_idx[1], m, d_amps, phi_of(plan), st));
+      tm.launches += 1;
+    }
+    sc.put(C);
   }
-  {
+  if (run) {
     Timer tm(plan, st, 3);
     HIPCHECK(launch_prob_sums(d_amps, m, d_part, d_sums ? d_sums : d_part + 2 * nb, st));
     tm.launches += 2;
   }
-  plan->pool.put(d_part, st);
+  sc.put(d_part);
   return QS_OK;
 }
 
@@ -1294,7 +1329,8 @@ qs_status qs_amplitudes(qs_plan* plan, const uint64_t* bitstrings, size_t m, qs_
   float2* amps = (float2*)plan->pool.get(m * sizeof(float2), st);
   double* sums = (double*)plan->pool.get(2 * sizeof(double), st);
   if (!amps || !sums) return fail(QS_ERR_OOM, "output buffers");
-  qs_status s = assemble(plan, prec, amps, sums, st);
+  Scratch sc{plan, st};
+  qs_status s = assemble(plan, prec, amps, sums, sc);
   if (s != QS_OK) return s;
   // staged on the host: the caller's arrays are written only on success
   std::vector<float2> ha(m);
@@ -1319,7 +1355,35 @@ qs_status qs_amplitudes_device(qs_plan* plan, qs_precision prec, float* d_out_c6
   if (!plan || !d_out_c64) return fail(QS_ERR_ARG, "null pointer");
   if (prec != QS_PREC_FP32 && prec != QS_PREC_SPLIT_BF16) return fail(QS_ERR_ARG, "unknown precision");
   if (!plan->registered || plan->blocks.empty()) return fail(QS_ERR_STATE, "no copies run");
-  return assemble(plan, prec, (float2*)d_out_c64, d_out_sums, (hipStream_t)hip_stream);
+  Scratch sc{plan, (hipStream_t)hip_stream};
+  return assemble(plan, prec, (float2*)d_out_c64, d_out_sums, sc);
+}
+
+qs_status qs_amplitudes_device_static(qs_plan* plan, qs_precision prec, float* d_out_c64,
+                                      double* d_out_sums, void* hip_stream) {
+  if (!plan || !d_out_c64) return fail(QS_ERR_ARG, "null pointer");
+  if (prec != QS_PREC_FP32 && prec != QS_PREC_SPLIT_BF16) return fail(QS_ERR_ARG, "unknown precision");
+  if (!plan->registered || plan->blocks.empty()) return fail(QS_ERR_STATE, "no copies run");
+  // the scratch bytes this assembly needs, before anything is launched
+  Scratch need{plan, (hipStream_t)hip_stream};
+  need.measure = true;
+  qs_status s = assemble(plan, prec, nullptr, nullptr, need);
+  if (s != QS_OK) return s;
+  if (need.used > static_scratch_capacity())
+    return fail(QS_ERR_UNSUPPORTED, "the assembly needs " + std::to_string(need.used) +
+                                        " bytes of scratch, more than the static region's " +
+                                        std::to_string(static_scratch_capacity()));
+  void* base = nullptr;
+  HIPCHECK(static_scratch(&base));
+  Scratch sc{plan, (hipStream_t)hip_stream};
+  sc.base = (char*)base;
+  sc.cap = static_scratch_capacity();
+  // no timing events either (creating one is an allocation of the runtime)
+  const bool timing = plan->timing;
+  plan->timing = false;
+  s = assemble(plan, prec, (float2*)d_out_c64, d_out_sums, sc);
+  plan->timing = timing;
+  return s;
 }
 
 qs_status qs_half_amplitudes(qs_plan* plan, int side, uint64_t copy_begin, uint64_t copy_end,

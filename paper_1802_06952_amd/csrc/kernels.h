@@ -89,4 +89,9 @@ hipError_t launch_prob_sums(const float2* amps, size_t m, double* partial, doubl
 
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 
+// The static scratch region of the allocation-free assembly: its size, and
+// its device address on the current device (looked up once per device).
+size_t static_scratch_capacity();
+hipError_t static_scratch(void** base);
+
 }  // namespace qs

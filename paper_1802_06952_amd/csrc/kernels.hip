@@ -10,6 +10,8 @@
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -1794,6 +1796,38 @@ hipError_t launch_prob_sums(const float2* amps, size_t m, double* partial, doubl
   hipLaunchKernelGGL(k_prob_partial, dim3(nb), dim3(kProbThreads), 0, st, amps, m, partial);
   hipLaunchKernelGGL(k_prob_final, dim3(1), dim3(kProbThreads), 0, st, partial, nb, out);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ static scratch
+//
+// Scratch of the allocation-free assembly (qs_amplitudes_device_static): the
+// value grid C, the split-K partial products, the split-BF16 operand planes
+// and the FP64 partial sums, carved from one region per device that lives as
+// long as the process.  In host code the array's name is not a device
+// address: the address comes from hipGetSymbolAddress, once per device.
+
+constexpr size_t kStaticScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) char assembly_scratch[kStaticScratchBytes];
+
+size_t static_scratch_capacity() { return kStaticScratchBytes; }
+
+hipError_t static_scratch(void** base) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  static std::mutex mu;
+  static std::map<int, void*> addr;  // device -> address of its copy of assembly_scratch
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(assembly_scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    it = addr.emplace(dev, p).first;
+  }
+  *base = it->second;
+  return hipSuccess;
 }
 
 __global__ void k_fill_zero(uint32_t* __restrict__ p, size_t words) {

@@ -52,32 +52,102 @@ def _traffic_from_profile(kernel_family: str, workload: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, n_copies: int, n_values: int):
-    """The FP64 oracle on the host on a bounded sample of the same workload."""
-    import numpy as np
+def _oracle_subtree(args):
+    """One worker of the oracle baseline: the FP64 partition oracle on copies
+    [k0, k1) (a subtree of the copy tree: its shared prefix is recomputed),
+    its partial amplitudes on the gathered values."""
+    text, mask, u, l, k0, k1 = args
     import torch
+    torch.set_num_threads(1)
+    from oracle import circuit as OC, partition as P
+    A, B = P.gathered_halves(OC.parse(text), mask, u, l, k0, k1)
+    return A @ B.T
+
+
+def _worker_init():
+    import torch
+    torch.set_num_threads(1)
+    import oracle.partition  # noqa: F401  (imports before the timed region)
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, n_copies: int, n_values: int, workers: int):
+    """The FP64 oracle on the host on a bounded sample of the same workload:
+    copies [0, n_copies) split into aligned subtrees, one worker process per
+    subtree (each recomputes the prefix it shares with the others, as a GPU
+    of a multi-GPU run would), partial amplitudes summed at the end."""
+    import multiprocessing as mp
+    import numpy as np
     from oracle import circuit as OC, partition as P
     from workloads import product_bitstrings
 
-    oc = OC.parse(w.circuit_text())
-    c = len(P.find_cuts(oc, w.upper_mask))
+    text = w.circuit_text()
+    c = len(P.find_cuts(OC.parse(text), w.upper_mask))
     total = 1 << c
     k1 = min(total, n_copies)
+    workers = max(1, min(workers, k1))
+    while k1 % workers:
+        workers -= 1
     _, u, l = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
-    t0 = time.perf_counter()
-    A, B = P.gathered_halves(oc, w.upper_mask, u[:n_values].astype(np.int64),
-                             l[:n_values].astype(np.int64), 0, k1)
-    (A @ B.T)
-    dt = time.perf_counter() - t0
+    u = u[:n_values].astype(np.int64)
+    l = l[:n_values].astype(np.int64)
+    per = k1 // workers
+    jobs = [(text, w.upper_mask, u, l, i * per, (i + 1) * per) for i in range(workers)]
+    ctx = mp.get_context("spawn")   # the parent holds a GPU context: never fork it
+    with ctx.Pool(workers, initializer=_worker_init) as pool:
+        pool.map(_worker_init_probe, range(workers))   # every worker started and imported
+        t0 = time.perf_counter()
+        parts = pool.map(_oracle_subtree, jobs)
+        dt = time.perf_counter() - t0
+    C = sum(parts)
+    assert C.shape == (len(u), len(l))
     # the gathered set size hardly matters (full half states are simulated);
     # the whole job runs every copy: scale the time by the copy count
     scaled = dt * total / k1
     m = w.n_u * w.n_l
-    return {"value": m / scaled, "unit": "amplitudes/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"FP64 oracle on copies [0, {k1}) of {total} (both halves, prefix reuse "
-                      f"over cut layers, {n_values} upper x {n_values} lower values gathered): "
-                      f"{dt:.2f} s, scaled by {total}/{k1} copies to the whole job of {m} amplitudes"}
+    return {"value": m / scaled, "unit": "amplitudes/s", "cores": workers, "kind": "oracle",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"FP64 oracle on copies [0, {k1}) of {total} in {workers} worker processes "
+                      f"(one thread each; aligned subtrees of {per} copies, both halves, prefix "
+                      f"reuse over cut layers inside a subtree, each worker recomputing the prefix "
+                      f"its subtree shares with the others; {len(u)} upper x {len(l)} lower values "
+                      f"gathered): {dt:.2f} s, extrapolated linearly by {total}/{k1} copies to the "
+                      f"whole job of {m} amplitudes"}
+
+
+def tuned_knobs(Q, names) -> dict:
+    """Knobs the autotuner stored for the named workloads
+    (paper_1802_06952_amd/tuned.json), for those whose stored key still
+    matches the circuit, cut, copy range and bitstrings; the others are left
+    to the cost model."""
+    from paper_1802_06952_amd.autotune import tuned_opts, workload_key
+    from workloads import product_bitstrings, workload
+    out = {}
+    for name in names:
+        w = workload(name)
+        text = w.circuit_text()
+        bits, _, _ = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
+        p = Q.Plan(text, w.upper_mask)
+        k1 = w.copy_end if w.copy_end is not None else (1 << p.n_cuts)
+        p.close()
+        o = tuned_opts(name, workload_key(text, w.upper_mask, bits, w.copy_begin, k1))
+        if o is not None:
+            out[name] = o
+    return out
+
+
+def _worker_init_probe(_):
+    return os.getpid()
 
 
 def controlled_variant(Q, w, bits, prec, k0, k1, a, stream, d_out, d_sums) -> dict:
@@ -128,16 +198,146 @@ def executed_updates(dump: dict, n_values) -> dict:
         gate = lambda i: ops[i][0] != "cut"
         for pp in s["passes"]:
             li = pp["level_in"]
-            nin = sum(1 for i in pp["ops_in"] if gate(i))
-            nout = sum(1 for i in pp["ops_out"] if gate(i))
-            passes += 2.0 ** n * (levels[li]["nodes"] * nin + levels[min(li + 1, len(levels) - 1)]["nodes"]
-                                  * nout * (1 if pp["branch"] else 0))
+            passes += 2.0 ** n * levels[li]["nodes"] * sum(1 for i in pp["ops_in"] if gate(i))
+            for st, so in enumerate(pp["stages"]):
+                passes += 2.0 ** n * levels[li + st + 1]["nodes"] * sum(1 for i in so if gate(i))
         q = len(s["Q"])
         paths = 1.0
         for lv in reversed(levels[s["lstar"] + 1:]):
             leaf += S * paths * sum(1 for i in lv["ops"] if gate(i)) * 2.0 ** q
             paths *= 2.0 ** len(lv["cuts"])
     return {"passes": passes, "leaf_rows": leaf, "total": passes + leaf}
+
+
+def error_stats(a, ref) -> dict:
+    """Errors of computed amplitudes a against the FP64 oracle's ref: the
+    norm-wise relative error, the largest absolute error, that over the rms
+    amplitude, and the median of the per-amplitude relative errors."""
+    import numpy as np
+    a = np.asarray(a, dtype=np.complex128).reshape(-1)
+    ref = np.asarray(ref, dtype=np.complex128).reshape(-1)
+    d = np.abs(a - ref)
+    rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
+    return {"norm_rel": float(np.linalg.norm(a - ref) / np.linalg.norm(ref)),
+            "max_abs": float(d.max()), "max_over_rms": float(d.max() / rms),
+            "median_rel": float(np.median(d / np.maximum(np.abs(ref), 1e-300))),
+            "n": int(a.size)}
+
+
+def time_workload(Q, w, prec, steps, warmup, stream, knobs=None, one_stream=False) -> dict:
+    """Amplitudes/s of one workload on its own: run_halves over its copy range
+    and the assembly per step, bitstrings registered and outputs in HBM."""
+    import numpy as np
+    import torch
+    from workloads import product_bitstrings
+    bits, _, _ = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
+    m = int(bits.size)
+    p = Q.Plan(w.circuit_text(), w.upper_mask, one_stream=one_stream, **(knobs or {}))
+    try:
+        k0 = w.copy_begin
+        k1 = w.copy_end if w.copy_end is not None else (1 << p.n_cuts)
+        d_out = torch.empty(2 * m, dtype=torch.float32, device="cuda")
+        d_sums = torch.zeros(2, dtype=torch.float64, device="cuda")
+        p.run_halves(k0, k1, bits, stream)
+        p.amplitudes_device(prec, d_out.data_ptr(), d_sums.data_ptr(), stream)
+
+        def step():
+            p.reset(keep_bitstrings=True)
+            p.run_halves(k0, k1, None, stream)
+            p.amplitudes_device(prec, d_out.data_ptr(), d_sums.data_ptr(), stream)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / steps
+        return {"value": round(m / (ms / 1000.0), 1), "unit": "amplitudes/s",
+                "ms_per_step": round(ms, 4), "bitstrings": m, "copies": k1 - k0,
+                "halves": [p.n_upper, p.n_lower], "cuts": p.n_cuts,
+                "amplitudes": d_out.cpu().numpy().view(np.complex64)}
+    finally:
+        p.close()
+
+
+def coscheduled_pair(Q, names, prec, steps, warmup, knobs) -> dict:
+    """Two circuits cut into uneven halves, each plan on a stream of its own
+    (and each plan's lower half on the plan's second stream), launched
+    together every step: four half sizes in flight at once."""
+    import numpy as np
+    import torch
+    from workloads import product_bitstrings, workload
+    ws = [workload(n) for n in names]
+    streams = [torch.cuda.Stream() for _ in ws]    # default priority
+    plans, outs, ranges, ms_alone = [], [], [], []
+    try:
+        for w in ws:
+            bits, _, _ = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
+            p = Q.Plan(w.circuit_text(), w.upper_mask, **knobs.get(w.name, {}))
+            plans.append(p)
+            k1 = w.copy_end if w.copy_end is not None else (1 << p.n_cuts)
+            ranges.append((w.copy_begin, k1, int(bits.size)))
+            outs.append((torch.empty(2 * bits.size, dtype=torch.float32, device="cuda"),
+                         torch.zeros(2, dtype=torch.float64, device="cuda")))
+            p.run_halves(w.copy_begin, k1, bits, streams[len(plans) - 1])
+        torch.cuda.synchronize()
+
+        def launch(i):
+            p, (k0, k1, _), (o, sm), st = plans[i], ranges[i], outs[i], streams[i]
+            p.reset(keep_bitstrings=True)
+            p.run_halves(k0, k1, None, st)
+            p.amplitudes_device(prec, o.data_ptr(), sm.data_ptr(), st)
+
+        for i in range(len(plans)):   # each alone, for reference
+            for _ in range(warmup):
+                launch(i)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                launch(i)
+            torch.cuda.synchronize()
+            ms_alone.append((time.perf_counter() - t0) * 1000.0 / steps)
+        for _ in range(warmup):
+            for i in range(len(plans)):
+                launch(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for i in range(len(plans)):
+                launch(i)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / steps
+        mtot = sum(r[2] for r in ranges)
+        return {"value": round(mtot / (ms / 1000.0), 1), "unit": "amplitudes/s", "ms_per_step": round(ms, 4),
+                "ms_alone_sum": round(sum(ms_alone), 4),
+                "circuits": [{"workload": w.name, "halves": [p.n_upper, p.n_lower], "cuts": p.n_cuts,
+                              "bitstrings": r[2], "ms_alone": round(t, 4),
+                              "amplitudes_per_s_coscheduled": round(r[2] / (ms / 1000.0), 1),
+                              "knobs": knobs.get(w.name, {}) or "cost model defaults"}
+                             for w, p, r, t in zip(ws, plans, ranges, ms_alone)],
+                "schedule": "each plan on its own stream, its lower half on the plan's second "
+                            "stream: four half sizes in flight"}
+    finally:
+        for p in plans:
+            p.close()
+
+
+def per_pass_table(recs) -> list:
+    """Every full-state pass of a step with its launch time averaged over the
+    timed steps: [half, pass, input level, stages, tiles, MB, us, GB/s]."""
+    acc = {}
+    for r in recs:
+        k = (r["side"], r["pass"])
+        e = acc.setdefault(k, [r["level_in"], r["stages"], r["tiles"], r["bytes"], 0.0, 0])
+        e[4] += r["ms"]
+        e[5] += 1
+    rows = []
+    for (side, pi), (li, st, tiles, b, ms, cnt) in sorted(acc.items()):
+        us = ms * 1000.0 / cnt
+        rows.append([side, pi, li, st, tiles, round(b / 1e6, 2), round(us, 2), round(b / (us * 1e3), 1)])
+    return rows
 
 
 def chain_variant(Q, a, stream) -> dict:
@@ -193,8 +393,13 @@ def main() -> int:
                     help="skip the controlled-U variant of the workload (CZ, CNOT and CY mixed)")
     ap.add_argument("--no-chain", action="store_true",
                     help="skip the four-part chain partition of the 64-qubit depth-10 circuit")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (36-qubit, the co-scheduled uneven pair, the "
+                         "64-qubit slice)")
     ap.add_argument("--plain-copies", type=int, default=16)
     ap.add_argument("--cpu-copies", type=int, default=256)
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="worker processes of the oracle baseline (at most the host's CPUs)")
     ap.add_argument("--autotune", action="store_true",
                     help="time a grid of schedule knobs first and run with the fastest")
     ap.add_argument("--one-stream", action="store_true",
@@ -226,12 +431,14 @@ def main() -> int:
     c = Q.Plan(text, w.upper_mask).n_cuts
     k0 = w.copy_begin
     k1 = w.copy_end if w.copy_end is not None else (1 << c)
-    knobs = {}
     tuned = None
     if a.autotune:
         from paper_1802_06952_amd.autotune import autotune
-        tuned = autotune(text, w.upper_mask, bits, k0, k1, budget_s=90.0, extra_levels=(4, 5, 6, 7))
+        tuned = autotune(text, w.upper_mask, bits, k0, k1, budget_s=90.0)
         knobs = tuned["opts"]
+    else:
+        # knobs the autotuner stored for this workload, if measured on the same inputs
+        knobs = tuned_knobs(Q, (w.name,)).get(w.name, {})
     plan = Q.Plan(text, w.upper_mask, one_stream=a.one_stream, **knobs)
     stream = torch.cuda.current_stream()
     d_out = torch.empty(2 * m, dtype=torch.float32, device="cuda")
@@ -275,13 +482,14 @@ def main() -> int:
     for _ in range(a.warmup):
         tstep(prec)
     torch.cuda.synchronize()
-    tplan.set_timing(True)
+    tplan.set_timing(2)
     ts0 = time.perf_counter()
     for _ in range(a.steps):
         tstep(prec)
     torch.cuda.synchronize()
     ms_one_stream = (time.perf_counter() - ts0) * 1000.0 / a.steps
     tm = tplan.timing()
+    pass_table = per_pass_table(tplan.pass_timing())
     tplan.set_timing(False)
     tplan.close()
     fam_ms = {"pass": tm["pass_ms"], "tail": tm["tail_ms"], "gemm": tm["gemm_ms"], "other": tm["other_ms"]}
@@ -355,6 +563,10 @@ def main() -> int:
                    "qubits": w.n, "depth": w.depth, "cuts": c, "copies": k1 - k0, "bitstrings": m,
                    "assembly": "fp32 mfma" if prec == 0 else "split-bf16 (3 products) mfma"},
         "amp_updates_per_s_flat": amp_updates_per_s,
+        "amp_updates_flat_note": "the paper's Table 3 accounting (2^c copies times each half's gate "
+                                 "count times 2^n_half), not work done: the copy tree, the light "
+                                 "cone and the folded end cuts execute "
+                                 "amp_updates_executed_per_step of them",
         "amp_updates_per_s_executed": ex["total"] / (ms_per_step / 1000.0),
         "amp_updates_executed_per_step": ex,
         "passes_per_s": launches["pass"] / (ms_per_step / 1000.0),
@@ -363,12 +575,17 @@ def main() -> int:
         "setup_s": round(setup_s, 3),
         "roofline": roof,
         "roofline_by_family": roofs,
+        "pass_launches": {"columns": ["half", "pass", "level_in", "stages", "tiles", "MB", "us", "GB/s"],
+                          "rows": pass_table},
         "schedule": "halves on one stream" if a.one_stream else "halves on two streams, concurrent",
         "ms_per_step_one_stream_timed": round(ms_one_stream, 4),
         "knobs": knobs or "cost model defaults",
     }
     if tuned:
-        out["autotune"] = {"best_ms": round(tuned["ms"], 3), "candidates": len(tuned["tried"])}
+        out["autotune"] = {"best_ms": round(tuned["ms"], 3), "default_ms": round(tuned["default_ms"], 3),
+                           "candidates": len(tuned["tried"])}
+    elif knobs:
+        out["knobs_source"] = "paper_1802_06952_amd/tuned.json (autotuner, same inputs)"
 
     # split-BF16 assembly on the same simulated halves
     if prec == 0:
@@ -415,19 +632,49 @@ def main() -> int:
         step(prec)
         torch.cuda.synchronize()
 
+    if not a.no_configs and a.workload == "grid6x7_d20":
+        from workloads import workload as _wl
+        tk = tuned_knobs(Q, ("grid6x6_d16", "grid6x7_d20_cols", "grid6x6_d16_stair"))
+        # 36 qubits, 18+18 halves, all 4096 copies, 2^16 bitstrings: small enough that launch
+        # latency, not bandwidth, sets its time
+        r = time_workload(Q, _wl("grid6x6_d16"), 0, a.steps, a.warmup, stream, tk.get("grid6x6_d16"))
+        r["knobs"] = tk.get("grid6x6_d16") or "cost model defaults"
+        r.pop("amplitudes")
+        r["workload"] = "grid6x6_d16: 6x6 grid (36 qubits), depth 16, rows 0-2 | 3-5, FP32 assembly"
+        out["config2"] = r
+        # the uneven pair, co-scheduled
+        out["config4"] = coscheduled_pair(Q, ("grid6x7_d20_cols", "grid6x6_d16_stair"), 0, a.steps,
+                                          a.warmup, tk)
+        # one GPU's slice of the 64-qubit circuit (32+32 halves, copies [0, 64) of 65536)
+        c5 = {}
+        for p_, name in ((0, "fp32"), (1, "split_bf16")):
+            r = time_workload(Q, _wl("grid8x8_d22_slice64"), p_, max(2, a.steps // 5), 1, stream)
+            r.pop("amplitudes")
+            c5[name] = r
+        c5["workload"] = ("grid8x8_d22_slice64: 8x8 grid (64 qubits), depth 22, rows 0-3 | 4-7, "
+                          "copies [0, 64) of 65536, 1024 x 1024 bitstrings, partial amplitudes")
+        out["config5"] = c5
+        torch.cuda.empty_cache()
+        step(prec)
+        torch.cuda.synchronize()
+
     if not a.no_check:
         gpath = os.path.join(ROOT, "tests", "golden", f"{w.name}.npz")
-        if os.path.exists(gpath):
-            g = np.load(gpath)
-            amp = d_out.cpu().numpy().view(np.complex64).reshape(w.n_u, w.n_l)
-            nu, nl = len(g["u"]), len(g["l"])
-            sub = amp[:nu, :nl].reshape(-1).astype(np.complex128)
-            ref = g["amp"]
-            out["check"] = {"rel_err_vs_oracle_subset": float(np.linalg.norm(sub - ref) / np.linalg.norm(ref)),
-                            "subset": f"{nu} x {nl}"}
         sums = d_sums.cpu().numpy()
         out["stats"] = {"sum_p": float(sums[0]), "2^n mean p": float(np.ldexp(sums[0] / m, w.n)),
                         "2^2n mean p^2": float(np.ldexp(sums[1] / m, 2 * w.n))}
+        if os.path.exists(gpath):
+            g = np.load(gpath)
+            nu, nl = len(g["u"]), len(g["l"])
+            chk = {"subset": f"first {nu} upper x first {nl} lower values", "reference": "FP64 oracle"}
+            for p_, name in ((0, "fp32"), (1, "split_bf16")):
+                step(p_)
+                torch.cuda.synchronize()
+                amp = d_out.cpu().numpy().view(np.complex64).reshape(w.n_u, w.n_l)
+                chk[name] = error_stats(amp[:nu, :nl], g["amp"])
+            out["check"] = chk
+        step(prec)
+        torch.cuda.synchronize()
 
     if not a.no_plain:
         pc = min(a.plain_copies, k1 - k0)
@@ -458,7 +705,7 @@ def main() -> int:
         del x, y
 
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, a.cpu_copies, 64)
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_copies, 64, min(a.cpu_workers, os.cpu_count() or 1))
 
     plan.close()
     print(json.dumps(out), flush=True)

@@ -79,7 +79,8 @@ typedef struct {
 
 /* Tuning knobs; a zero field means "choose automatically". */
 typedef struct {
-  int tile_bits;          /* qubits held per workgroup tile in a full-state pass (6..13) */
+  int tile_bits;          /* largest tile of a full-state pass, in qubits (7..11 for halves of
+                             7+ qubits: 6 over the lanes of a wavefront, the rest in registers) */
   int coalesce_bits;      /* low qubits always inside a tile (contiguous runs of 2^b amplitudes) */
   int tail_max_qubits;    /* largest light cone the leaf evaluation accepts (0..10) */
   int materialize_level;  /* force the last materialised tree level (-1 = cost model) */
@@ -99,6 +100,12 @@ typedef struct {
                              0 = as many as the range allows): each block's passes and leaf
                              evaluation run over all of its copies in one launch each, and
                              blocks run one after another */
+  int max_stages;         /* tree levels one full-state pass may descend at once (1..2, 0 = 2):
+                             a pass reads a level, branches through the next levels' cut bits
+                             and gates in registers and writes only the deepest one; the
+                             planner picks where each pass lands */
+  int min_tile_bits;      /* smallest tile of a full-state pass (7..tile_bits, 0 = 8): a pass's
+                             tile holds its gates' qubits, padded up to this many */
   qs_allocator alloc;     /* every device buffer of the plan (states, gathered half amplitudes,
                              descriptors, copy tables, assembly workspace) comes from here */
 } qs_options;
@@ -267,7 +274,22 @@ qs_status qs_plan_reset(qs_plan* plan, int keep_bitstrings);
  * amplitude per gate on the light-cone subspaces).  Synchronises with the
  * recorded events.  out has 11 doubles. */
 qs_status qs_get_timing(qs_plan* plan, double* out11);
+/* enable: 0 off, 1 per kernel family (events around each family's launches),
+ * 2 also around every full-state pass launch (qs_get_pass_timing).  Clears the
+ * totals.  Timing adds events to the stream; leave it off when capturing a
+ * graph.  Errors: QS_ERR_ARG. */
 qs_status qs_set_timing(qs_plan* plan, int enable);
+
+/* Every full-state pass launch timed since qs_set_timing(plan, 2), in launch
+ * order, as 7 doubles: half (0 upper, 1 lower), pass index in that half's
+ * schedule, input tree level, branch stages (tree levels descended), wavefront
+ * tiles (or workgroups) launched, algorithmic bytes (8 B per amplitude of every
+ * state read and written; the last pass only its listed tiles), milliseconds
+ * (HIP events on the launch stream).  Writes min(n, cap_records) records to
+ * out (caller-owned, 7 * cap_records doubles) and the total count to
+ * *n_records.  Synchronises with the recorded events.  Errors: QS_ERR_ARG,
+ * QS_ERR_HIP. */
+qs_status qs_get_pass_timing(qs_plan* plan, double* out, size_t cap_records, size_t* n_records);
 
 /* ---------------------------------------------------------------- chain partitions
  *

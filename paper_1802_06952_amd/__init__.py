@@ -31,7 +31,7 @@ EXPORTED = ("qs_last_error", "qs_load_circuit", "qs_circuit_info", "qs_circuit_f
             "qs_partition", "qs_plan_info", "qs_plan_dump", "qs_plan_free", "qs_run_halves",
             "qs_amplitudes", "qs_amplitudes_device", "qs_amplitudes_device_static",
             "qs_half_amplitudes", "qs_plan_reset",
-            "qs_get_timing", "qs_set_timing", "qs_score_cut", "qs_choose_cut",
+            "qs_get_timing", "qs_set_timing", "qs_get_pass_timing", "qs_score_cut", "qs_choose_cut",
             "qs_partition_chain", "qs_chain_info", "qs_chain_register", "qs_chain_amplitudes_device",
             "qs_chain_amplitudes", "qs_chain_free")
 
@@ -63,7 +63,7 @@ class qs_options(C.Structure):
     _fields_ = [("tile_bits", C.c_int), ("coalesce_bits", C.c_int), ("tail_max_qubits", C.c_int),
                 ("materialize_level", C.c_int), ("plain", C.c_int), ("mem_budget", C.c_size_t),
                 ("one_stream", C.c_int), ("copies_per_launch", C.c_uint64),
-                ("alloc", qs_allocator)]
+                ("max_stages", C.c_int), ("min_tile_bits", C.c_int), ("alloc", qs_allocator)]
 
 
 class TorchAllocator:
@@ -144,6 +144,8 @@ def _load() -> C.CDLL:
     lib.qs_plan_reset.argtypes = [vp, C.c_int]
     lib.qs_get_timing.argtypes = [vp, C.POINTER(C.c_double)]
     lib.qs_set_timing.argtypes = [vp, C.c_int]
+    lib.qs_get_pass_timing.argtypes = [vp, C.POINTER(C.c_double), C.c_size_t,
+                                       C.POINTER(C.c_size_t)]
     lib.qs_partition_chain.argtypes = [vp, u64p, C.c_int, C.POINTER(qs_options), C.POINTER(vp)]
     lib.qs_chain_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
     lib.qs_chain_register.argtypes = [vp, u64p, C.c_size_t]
@@ -305,8 +307,27 @@ def qs_half_amplitudes(plan, side: int, copy_begin: int, copy_end: int, n_values
     return out.view(np.complex64).reshape(copy_end - copy_begin, nv.value)
 
 
-def qs_set_timing(plan, enable: bool) -> None:
-    _check(_lib.qs_set_timing(plan, 1 if enable else 0))
+def qs_set_timing(plan, enable) -> None:
+    """enable: False/0 off, True/1 per kernel family, 2 also per full-state pass."""
+    _check(_lib.qs_set_timing(plan, int(enable)))
+
+
+PASS_TIMING_FIELDS = ("side", "pass", "level_in", "stages", "tiles", "bytes", "ms")
+
+
+def qs_get_pass_timing(plan) -> list[dict]:
+    n = C.c_size_t(0)
+    _check(_lib.qs_get_pass_timing(plan, None, 0, C.byref(n)))
+    out = np.zeros(7 * max(1, n.value), dtype=np.float64)
+    _check(_lib.qs_get_pass_timing(plan, out.ctypes.data_as(C.POINTER(C.c_double)), n.value,
+                                   C.byref(n)))
+    recs = []
+    for r in out[: 7 * n.value].reshape(-1, 7):
+        d = dict(zip(PASS_TIMING_FIELDS, r.tolist()))
+        for k in ("side", "pass", "level_in", "stages", "tiles"):
+            d[k] = int(d[k])
+        recs.append(d)
+    return recs
 
 
 TIMING_FIELDS = ("pass_ms", "tail_ms", "gemm_ms", "other_ms", "pass_launches", "tail_launches",
@@ -419,11 +440,13 @@ class Plan:
     def __init__(self, circuit_text: str, upper_mask: int, tile_bits: int = 0,
                  coalesce_bits: int = 0, tail_max_qubits: int = 0, materialize_level: int = -1,
                  plain: bool = False, mem_budget: int = 0, one_stream: bool = False,
-                 copies_per_launch: int = 0, alloc="torch"):
+                 copies_per_launch: int = 0, max_stages: int = 0, min_tile_bits: int = 0,
+                 alloc="torch"):
         self.allocator = _allocator(alloc)
         self._circ = qs_load_circuit(circuit_text)
         opts = qs_options(tile_bits, coalesce_bits, tail_max_qubits, materialize_level,
-                          1 if plain else 0, mem_budget, 1 if one_stream else 0, copies_per_launch)
+                          1 if plain else 0, mem_budget, 1 if one_stream else 0, copies_per_launch,
+                          max_stages, min_tile_bits)
         if self.allocator is not None:
             opts.alloc = self.allocator.struct
         try:
@@ -462,11 +485,14 @@ class Plan:
     def reset(self, keep_bitstrings: bool = False) -> None:
         qs_plan_reset(self._plan, keep_bitstrings)
 
-    def set_timing(self, on: bool) -> None:
+    def set_timing(self, on) -> None:
         qs_set_timing(self._plan, on)
 
     def timing(self) -> dict:
         return qs_get_timing(self._plan)
+
+    def pass_timing(self) -> list[dict]:
+        return qs_get_pass_timing(self._plan)
 
     def close(self) -> None:
         if getattr(self, "_plan", None):

@@ -1,50 +1,51 @@
-"""Measured choice of the schedule knobs for one workload.
+"""Measured choice of the schedule knobs for a workload.
 
 The planner's cost model picks the materialised depth of each half's copy
-tree and packs gates into tiles of a fixed width.  This module times a small
-grid of candidates on the GPU (tile width, light-cone limit, a forced
-materialised depth around the model's choice) through the C ABI and keeps the
-fastest.  Results are cached in a JSON file keyed by the circuit text, the cut
-and the bitstring set.
+tree, packs gates into tiles of a fixed width, and lets a pass descend up to
+two tree levels.  This module times candidate knob sets on the GPU through the
+C ABI and keeps the fastest.  The knobs searched:
+
+* ``tile_bits``: the fusion width, the state bits one wavefront tile holds
+  (gates on them fuse into one pass over HBM): 9, 10 or 11;
+* ``max_stages``: the fusion depth, the tree levels one pass may descend: 1 or 2;
+* ``copies_per_launch``: the copy block one launch of the passes and the leaf
+  evaluation covers (all copies, or a quarter of them per block);
+* ``materialize_level``: the last materialised tree level (the cost model's
+  choice, or forced one level either side of it);
+* ``tail_max_qubits``: the largest light cone of the leaf evaluation: 8 or 10.
+
+The search is coordinate descent from the cost model's defaults: each knob in
+turn takes every value with the others fixed, and the best is kept.  A result
+is stored in a JSON file under the workload's name, with the SHA-256 of the
+circuit text, cut, copy range and bitstrings it was measured on; a reader
+uses the stored knobs only if that key still matches.
+
+    python -m paper_1802_06952_amd.autotune grid6x7_d20 grid6x6_d16 ... [--out FILE]
 """
 
 from __future__ import annotations
 
+import argparse
 import hashlib
 import json
 import os
+import sys
 import time
 
 import numpy as np
 
-from . import Plan
+from . import Plan, QSError
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_CACHE = os.path.join(HERE, "tuned.json")
 
 
-def _key(text: str, mask: int, bits: np.ndarray, k0: int, k1: int) -> str:
+def workload_key(text: str, mask: int, bits: np.ndarray, k0: int, k1: int) -> str:
     h = hashlib.sha256()
     h.update(text.encode())
     h.update(str((mask, k0, k1)).encode())
     h.update(np.ascontiguousarray(bits, dtype=np.uint64).tobytes())
     return h.hexdigest()[:24]
-
-
-def _time_opts(text, mask, bits, k0, k1, opts, reps, stream, sync) -> float:
-    p = Plan(text, mask, **opts)
-    try:
-        p.run_halves(k0, k1, bits, stream)
-        p.amplitudes_device(0, _scratch(bits.size), None, stream)
-        sync()
-        best = float("inf")
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            p.reset(keep_bitstrings=True)
-            p.run_halves(k0, k1, None, stream)
-            p.amplitudes_device(0, _scratch(bits.size), None, stream)
-            sync()
-            best = min(best, time.perf_counter() - t0)
-        return best
-    finally:
-        p.close()
 
 
 _SCRATCH = {}
@@ -59,46 +60,134 @@ def _scratch(m: int) -> int:
     return t.data_ptr()
 
 
-def candidates(base_levels=(-1,)):
-    out = []
-    for ml in base_levels:
-        for tb in (10, 11):
-            for tq in (8, 10):
-                out.append(dict(tile_bits=tb, tail_max_qubits=tq, materialize_level=ml))
-    return out
-
-
-def autotune(text: str, mask: int, bits, k0: int, k1: int, cache_path: str | None = None,
-             reps: int = 2, extra_levels=(), stream=None, budget_s: float = 60.0) -> dict:
-    """Fastest knob set for the workload: {'opts': {...}, 'ms': t, 'tried': [...]}"""
+def time_opts(text, mask, bits, k0, k1, opts, reps=3, stream=None) -> float:
+    """Best step time in seconds (run_halves over [k0, k1) plus the FP32
+    assembly) of a plan with the given knobs, after one untimed step."""
     import torch
+    p = Plan(text, mask, **opts)
+    try:
+        p.run_halves(k0, k1, bits, stream)
+        p.amplitudes_device(0, _scratch(bits.size), None, stream)
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            p.reset(keep_bitstrings=True)
+            p.run_halves(k0, k1, None, stream)
+            p.amplitudes_device(0, _scratch(bits.size), None, stream)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+    finally:
+        p.close()
+
+
+def knob_values(n_cuts: int, k0: int, k1: int, model_levels: list[int]) -> dict:
+    """The values tried per knob; the first of each list is the default."""
+    span = k1 - k0
+    cpl = [0]
+    if span >= 4 and (span & (span - 1)) == 0:
+        cpl.append(span // 4)
+    lv = [-1]
+    for base in sorted(set(model_levels)):
+        for d in (-1, 1):
+            if base + d >= 0 and base + d not in lv:
+                lv.append(base + d)
+    return {"tile_bits": [10, 9, 11], "max_stages": [2, 1], "copies_per_launch": cpl,
+            "materialize_level": lv, "tail_max_qubits": [10, 8]}
+
+
+def autotune(text: str, mask: int, bits, k0: int, k1: int, reps: int = 3, stream=None,
+             budget_s: float = 120.0, log=None) -> dict:
+    """Fastest knob set by coordinate descent: {'opts', 'ms', 'default_ms', 'tried'}."""
     bits = np.ascontiguousarray(bits, dtype=np.uint64)
-    key = _key(text, mask, bits, k0, k1)
-    cache = {}
-    if cache_path and os.path.exists(cache_path):
-        with open(cache_path) as f:
-            cache = json.load(f)
-        if key in cache:
-            return cache[key]
-    sync = torch.cuda.synchronize
-    tried = []
+    probe = Plan(text, mask)
+    try:
+        d = probe.dump(k0, k1)
+        n_cuts = probe.n_cuts
+    finally:
+        probe.close()
+    model_levels = [s.get("lstar", 0) for s in d["sides"]]
+    values = knob_values(n_cuts, k0, k1, model_levels)
+    cur = {k: v[0] for k, v in values.items()}
+    tried = {}
+
+    def measure(opts):
+        key = json.dumps(opts, sort_keys=True)
+        if key not in tried:
+            try:
+                tried[key] = time_opts(text, mask, bits, k0, k1, opts, reps, stream) * 1e3
+            except QSError as e:   # a knob set the planner rejects
+                tried[key] = float("inf")
+                if log:
+                    log(f"  {opts}: {e}")
+            if log and np.isfinite(tried[key]):
+                log(f"  {opts}: {tried[key]:.3f} ms")
+        return tried[key]
+
     t_start = time.perf_counter()
-    for opts in candidates((-1,) + tuple(extra_levels)):
-        if time.perf_counter() - t_start > budget_s:
-            break
-        try:
-            t = _time_opts(text, mask, bits, k0, k1, opts, reps, stream, sync)
-        except Exception as e:  # a knob set the planner rejects
-            tried.append({"opts": opts, "error": str(e)})
-            continue
-        tried.append({"opts": opts, "ms": t * 1e3})
-    ok = [x for x in tried if "ms" in x]
-    if not ok:
-        raise RuntimeError("no candidate ran")
-    best = min(ok, key=lambda x: x["ms"])
-    res = {"opts": best["opts"], "ms": best["ms"], "tried": tried}
-    if cache_path:
-        cache[key] = res
-        with open(cache_path, "w") as f:
-            json.dump(cache, f, indent=1)
-    return res
+    default_ms = best_ms = measure(cur)
+    for knob, vals in values.items():
+        for v in vals[1:]:
+            if time.perf_counter() - t_start > budget_s:
+                break
+            cand = dict(cur, **{knob: v})
+            ms = measure(cand)
+            if ms < best_ms:
+                best_ms, cur = ms, cand
+    if not np.isfinite(best_ms):
+        raise RuntimeError("no knob set ran")
+    return {"opts": cur, "ms": best_ms, "default_ms": default_ms,
+            "tried": [{"opts": json.loads(k), "ms": v if np.isfinite(v) else None}
+                      for k, v in tried.items()]}
+
+
+def load_tuned(path: str = DEFAULT_CACHE) -> dict:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f).get("workloads", {})
+
+
+def tuned_opts(name: str, key: str, path: str = DEFAULT_CACHE) -> dict | None:
+    """Stored knobs of a workload if they were measured on the same inputs."""
+    e = load_tuned(path).get(name)
+    if e and e.get("key") == key:
+        return e["opts"]
+    return None
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("workloads", nargs="+")
+    ap.add_argument("--out", default=DEFAULT_CACHE)
+    ap.add_argument("--budget-s", type=float, default=120.0)
+    a = ap.parse_args(argv)
+    sys.path.insert(0, os.path.dirname(HERE))
+    import torch
+    from workloads import product_bitstrings, workload
+    torch.cuda.set_device(0)
+    store = {"workloads": load_tuned(a.out)}
+    for name in a.workloads:
+        w = workload(name)
+        text = w.circuit_text()
+        bits, _, _ = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
+        p = Plan(text, w.upper_mask)
+        k1 = w.copy_end if w.copy_end is not None else (1 << p.n_cuts)
+        p.close()
+        print(f"autotune {name}: copies [{w.copy_begin}, {k1}), {bits.size} bitstrings", flush=True)
+        r = autotune(text, w.upper_mask, bits, w.copy_begin, k1, budget_s=a.budget_s,
+                     log=lambda s: print(s, flush=True))
+        r["key"] = workload_key(text, w.upper_mask, bits, w.copy_begin, k1)
+        r["device"] = torch.cuda.get_device_name(0)
+        store["workloads"][name] = r
+        print(f"  best {r['opts']}: {r['ms']:.3f} ms (cost-model defaults {r['default_ms']:.3f} ms)",
+              flush=True)
+        with open(a.out, "w") as f:
+            json.dump(store, f, indent=1)
+            f.write("\n")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

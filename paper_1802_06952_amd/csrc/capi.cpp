@@ -169,6 +169,7 @@ struct Prepared {
   std::vector<uint64_t> leaf_k;
   std::vector<uint32_t> nu_to_k;  // block-local copy index of each natural position nu
   double pass_bytes = 0;  // algorithmic bytes of the passes
+  std::vector<double> pass_bytes_each;  // the same per pass
   // The kernels apply the unit-entry part of every 2x2 gate, and each pass
   // (and the leaf evaluation) multiplies by an exact power of two: the true
   // amplitudes are the computed ones times phi = 2^(-carry/2) omega^A (A the
@@ -235,8 +236,16 @@ struct qs_plan {
   // the lower half runs on aux, forked from and joined into the caller's stream
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  bool timing = false;
+  int timing = 0;  // 1: per kernel family; 2: also every full-state pass on its own
   std::vector<EvRec> events;
+  struct PassRec {
+    int side, pass, level_in, stages;
+    uint64_t tiles;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  std::vector<PassRec> pass_events;
+  std::vector<double> pass_log;  // 7 doubles per timed pass launch (qs_get_pass_timing)
   double tms[4] = {0, 0, 0, 0};
   double counts[4] = {0, 0, 0, 0};
   double pass_bytes = 0, gemm_flops = 0, tail_flops = 0;
@@ -253,6 +262,10 @@ struct qs_plan {
   ~qs_plan() {
     (void)hipDeviceSynchronize();
     for (EvRec& e : events) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    for (PassRec& e : pass_events) {
       (void)hipEventDestroy(e.a);
       (void)hipEventDestroy(e.b);
     }
@@ -273,6 +286,10 @@ namespace {
   } while (0)
 
 int ctz64(uint64_t x) { return x ? __builtin_ctzll(x) : 64; }
+
+#ifndef QS_PASS_NT_DEFAULT
+#define QS_PASS_NT_DEFAULT 1
+#endif
 
 // Cached block plans (one per half and copy block) kept at most; the flat
 // form plans every copy as a block of its own.
@@ -298,6 +315,8 @@ PlanKnobs knobs_of(qs_plan* p, int S) {
   k.mem_budget = p->side_budget;
   k.S = S;
   k.one_op_per_pass = p->opts.plain != 0;
+  if (p->opts.max_stages > 0) k.max_stages = std::min(p->opts.max_stages, kMaxStages);
+  if (p->opts.min_tile_bits > 0) k.min_tile_bits = p->opts.min_tile_bits;
   return k;
 }
 
@@ -388,26 +407,32 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
     if (!encode_ops(s, pp.ops_in, tr.fixed, work_of, ops, err, false, rp))
       return fail(QS_ERR_UNSUPPORTED, err);
     d.n_in = (int)ops.size() - d.op_in;
-    d.op_out = (int)ops.size();
-    if (!encode_ops(s, pp.ops_out, tr.fixed, work_of, ops, err, false, rp))
-      return fail(QS_ERR_UNSUPPORTED, err);
-    d.n_out = (int)ops.size() - d.op_out;
-    d.m = 0;
-    const double nin = (double)sp.nodes[pp.level_in];
-    if (pp.branch) {
-      const Level& nx = tr.levels[pp.level_in + 1];
-      d.m = (int)nx.cuts.size();
-      for (int i = 0; i < d.m; ++i) d.bq[i] = cut_qubit(nx.cuts[i]);
-      last_bytes = (pp.init ? 0.0 : nin * SB) + (double)sp.nodes[pp.level_in + 1] * SB;
-    } else {
-      last_bytes = (pp.init ? 1.0 : 2.0) * nin * SB;
+    d.ns = (int)pp.stages.size();
+    if (d.ns > kMaxStages) return fail(QS_ERR_UNSUPPORTED, "internal: too many branch stages");
+    for (int st = 0; st < d.ns; ++st) {
+      const Level& nx = tr.levels[pp.level_in + 1 + st];
+      d.sm[st] = (int)nx.cuts.size();
+      for (int i = 0; i < d.sm[st]; ++i) d.sbq[st][i] = cut_qubit(nx.cuts[i]);
+      d.sop[st] = (int)ops.size() - d.op_in;
+      if (!encode_ops(s, pp.stages[st], tr.fixed, work_of, ops, err, false, rp))
+        return fail(QS_ERR_UNSUPPORTED, err);
+      d.snops[st] = (int)ops.size() - d.op_in - d.sop[st];
     }
+    d.n_all = (int)ops.size() - d.op_in;
+    if (d.n_all > kMaxPassOps) return fail(QS_ERR_UNSUPPORTED, "internal: too many ops in a pass");
+    const double nin = (double)sp.nodes[pp.level_in];
+    if (pp.branch())
+      last_bytes = (pp.init ? 0.0 : nin * SB) + (double)sp.nodes[pp.level_out()] * SB;
+    else
+      last_bytes = (pp.init ? 1.0 : 2.0) * nin * SB;
     pr->pass_bytes += last_bytes;
+    pr->pass_bytes_each.push_back(last_bytes);
     d.upper = s.upper ? 1 : 0;
+    d.nt = QS_PASS_NT_DEFAULT;
     {
       int k = 0;
       mat_counts(pp.ops_in, k, n_omega);
-      if (pp.branch) mat_counts(pp.ops_out, k, n_omega);
+      for (const std::vector<int>& so : pp.stages) mat_counts(so, k, n_omega);
       d.scale = std::ldexp(1.0f, -((k + carry) >> 1));
       carry = (k + carry) & 1;
     }
@@ -617,6 +642,7 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
         tl.clear();
       } else {
         pr->pass_bytes -= last_bytes * (1.0 - frac);
+        pr->pass_bytes_each.back() *= frac;
       }
     }
   }
@@ -672,8 +698,13 @@ qs_status run_side(qs_plan* P, int sidx, const Prepared& pr, float2* X, hipStrea
         cur = (float2*)P->pool.get(SB, st);
         if (!cur) return fail(QS_ERR_OOM, "root state");
       }
-      if (pp.branch) {
-        const uint64_t on = sp.nodes[pp.level_in + 1];
+      hipEvent_t ea = nullptr;
+      if (P->timing >= 2) {
+        HIPCHECK(hipEventCreate(&ea));
+        HIPCHECK(hipEventRecord(ea, st));
+      }
+      if (pp.branch()) {
+        const uint64_t on = sp.nodes[pp.level_out()];
         float2* nxt = (float2*)P->pool.get(SB * on, st);
         if (!nxt) return fail(QS_ERR_OOM, "tree level states");
         HIPCHECK(launch_pass(pr.pds[pi], dd, d_ops, cur, nxt, cur_nodes, tl, nl, st));
@@ -682,6 +713,16 @@ qs_status run_side(qs_plan* P, int sidx, const Prepared& pr, float2* X, hipStrea
         cur_nodes = on;
       } else {
         HIPCHECK(launch_pass(pr.pds[pi], dd, d_ops, cur, cur, cur_nodes, tl, nl, st));
+      }
+      if (P->timing >= 2) {
+        hipEvent_t eb = nullptr;
+        HIPCHECK(hipEventCreate(&eb));
+        HIPCHECK(hipEventRecord(eb, st));
+        const PassDesc& h = pr.pds[pi];
+        const uint64_t nin = pp.init ? 1 : sp.nodes[pp.level_in];
+        const uint64_t tiles = tl ? nin * nl : (nin << h.n_outer);
+        P->pass_events.push_back(qs_plan::PassRec{sidx, (int)pi, pp.level_in, (int)pp.stages.size(),
+                                                  tiles, pr.pass_bytes_each[pi], ea, eb});
       }
       ++tm.launches;
     }
@@ -921,6 +962,8 @@ PlanKnobs dump_knobs(const qs_plan* plan, int k) {
   kn.mem_budget = plan->opts.mem_budget;
   kn.S = plan->registered ? (int)plan->vals[k].size() : 1024;
   kn.one_op_per_pass = plan->opts.plain != 0;
+  if (plan->opts.max_stages > 0) kn.max_stages = std::min(plan->opts.max_stages, kMaxStages);
+  if (plan->opts.min_tile_bits > 0) kn.min_tile_bits = plan->opts.min_tile_bits;
   return kn;
 }
 
@@ -968,7 +1011,8 @@ qs_status qs_partition(const qs_circuit* circ, uint64_t upper_mask, const qs_opt
     p->opts = qs_options{};
     p->opts.materialize_level = -1;
   }
-  if (p->opts.tile_bits < 0 || p->opts.coalesce_bits < 0 || p->opts.tail_max_qubits < 0)
+  if (p->opts.tile_bits < 0 || p->opts.coalesce_bits < 0 || p->opts.tail_max_qubits < 0 ||
+      p->opts.max_stages < 0 || p->opts.min_tile_bits < 0)
     return fail(QS_ERR_ARG, "negative option");
   if ((p->opts.alloc.alloc == nullptr) != (p->opts.alloc.free == nullptr))
     return fail(QS_ERR_ARG, "allocator needs both alloc and free");
@@ -1459,6 +1503,17 @@ qs_status qs_get_timing(qs_plan* plan, double* out10) {
     (void)hipEventDestroy(e.b);
   }
   plan->events.clear();
+  for (qs_plan::PassRec& e : plan->pass_events) {
+    HIPCHECK(hipEventSynchronize(e.b));
+    float ms = 0;
+    HIPCHECK(hipEventElapsedTime(&ms, e.a, e.b));
+    const double rec[7] = {(double)e.side, (double)e.pass, (double)e.level_in, (double)e.stages,
+                           (double)e.tiles, e.bytes, (double)ms};
+    plan->pass_log.insert(plan->pass_log.end(), rec, rec + 7);
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  plan->pass_events.clear();
   for (int i = 0; i < 4; ++i) {
     out10[i] = plan->tms[i];
     out10[4 + i] = plan->counts[i];
@@ -1473,9 +1528,23 @@ qs_status qs_set_timing(qs_plan* plan, int enable) {
   if (!plan) return fail(QS_ERR_ARG, "null plan");
   double dummy[11];
   (void)qs_get_timing(plan, dummy);
-  plan->timing = enable != 0;
+  if (enable < 0 || enable > 2) return fail(QS_ERR_ARG, "timing mode must be 0, 1 or 2");
+  plan->timing = enable;
+  plan->pass_log.clear();
   for (int i = 0; i < 4; ++i) plan->tms[i] = plan->counts[i] = 0;
   plan->pass_bytes = plan->gemm_flops = plan->tail_flops = 0;
+  return QS_OK;
+}
+
+qs_status qs_get_pass_timing(qs_plan* plan, double* out, size_t cap_records, size_t* n_records) {
+  if (!plan || !n_records || (!out && cap_records)) return fail(QS_ERR_ARG, "null pointer");
+  double fam[11];
+  const qs_status st = qs_get_timing(plan, fam);
+  if (st != QS_OK) return st;
+  const size_t n = plan->pass_log.size() / 7;
+  const size_t k = std::min(n, cap_records);
+  if (k) std::memcpy(out, plan->pass_log.data(), k * 7 * sizeof(double));
+  *n_records = n;
   return QS_OK;
 }
 

@@ -146,10 +146,41 @@ __device__ void lds_apply_ops(float2* L, const DevOp* __restrict__ ops, int nops
   }
 }
 
+// Child tile of an LDS pass: dst = the cut factors of branch b (m cut bits on
+// state bits bq, MSB first) applied to src.
+__device__ void lds_child(float2* dst, const float2* src, const int* bq, int m, int b, int upper,
+                          int t, const int* tbit, uint32_t outer) {
+  const int size = 1 << t;
+  for (int i = threadIdx.x; i < size; i += kPassThreads) {
+    const uint32_t x = outer | deposit_tile(i, tbit, t);
+    float2 v = src[i];
+    for (int k = 0; k < m; ++k) {
+      const uint32_t want = (b >> (m - 1 - k)) & 1;
+      const uint32_t xb = (x >> bq[k]) & 1;
+      if (upper) {
+        if (xb != want) v = make_float2(0.f, 0.f);
+      } else if (want & xb) {
+        v = make_float2(-v.x, -v.y);
+      }
+    }
+    dst[i] = v;
+  }
+  __syncthreads();
+}
+
+__device__ void lds_store(float2* dst, const float2* L, float sc, int t, const int* tbit,
+                          uint32_t outer) {
+  for (int i = threadIdx.x; i < (1 << t); i += kPassThreads) {
+    const uint32_t x = outer | deposit_tile(i, tbit, t);
+    dst[x] = make_float2(L[i].x * sc, L[i].y * sc);
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(kPassThreads)
 k_pass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops,
        const float2* __restrict__ in, float2* __restrict__ out) {
-  extern __shared__ float2 smem[];
+  extern __shared__ float2 smem[];  // 1 + ns tiles
   __shared__ int tbit[kMaxTileBits];
   const PassDesc& P = *pdp;
   const int t = P.t;
@@ -174,40 +205,31 @@ k_pass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops,
     A[i] = v;
   }
   __syncthreads();
-  lds_apply_ops(A, ops + P.op_in, P.n_in, t, tbit, outer);
+  const DevOp* pops = ops + P.op_in;
+  lds_apply_ops(A, pops, P.n_in, t, tbit, outer);
   const float sc = P.scale;
-  if (P.m == 0) {
-    for (int i = threadIdx.x; i < size; i += kPassThreads) {
-      const uint32_t x = outer | deposit_tile(i, tbit, t);
-      out[node * N + x] = make_float2(A[i].x * sc, A[i].y * sc);
-    }
+  const int ns = P.ns;
+  if (ns == 0) {
+    lds_store(out + node * N, A, sc, t, tbit, outer);
     return;
   }
-  float2* Bb = smem + size;
-  const int m = P.m;
-  for (int b = 0; b < (1 << m); ++b) {
-    for (int i = threadIdx.x; i < size; i += kPassThreads) {
-      const uint32_t x = outer | deposit_tile(i, tbit, t);
-      float2 v = A[i];
-      for (int k = 0; k < m; ++k) {
-        const uint32_t want = (b >> (m - 1 - k)) & 1;
-        const uint32_t xb = (x >> P.bq[k]) & 1;
-        if (P.upper) {
-          if (xb != want) v = make_float2(0.f, 0.f);
-        } else if (want & xb) {
-          v = make_float2(-v.x, -v.y);
-        }
-      }
-      Bb[i] = v;
+  const int m1 = P.sm[0];
+  const int m2 = ns > 1 ? P.sm[1] : 0;
+  float2* B1 = smem + size;
+  float2* B2 = smem + 2 * size;
+  for (int b1 = 0; b1 < (1 << m1); ++b1) {
+    lds_child(B1, A, P.sbq[0], m1, b1, P.upper, t, tbit, outer);
+    lds_apply_ops(B1, pops + P.sop[0], P.snops[0], t, tbit, outer);
+    const uint64_t c1 = (node << m1) | (uint64_t)b1;
+    if (ns == 1) {
+      lds_store(out + c1 * N, B1, sc, t, tbit, outer);
+      continue;
     }
-    __syncthreads();
-    lds_apply_ops(Bb, ops + P.op_out, P.n_out, t, tbit, outer);
-    const uint64_t child = (node << m) | (uint64_t)b;
-    for (int i = threadIdx.x; i < size; i += kPassThreads) {
-      const uint32_t x = outer | deposit_tile(i, tbit, t);
-      out[child * N + x] = make_float2(Bb[i].x * sc, Bb[i].y * sc);
+    for (int b2 = 0; b2 < (1 << m2); ++b2) {
+      lds_child(B2, B1, P.sbq[1], m2, b2, P.upper, t, tbit, outer);
+      lds_apply_ops(B2, pops + P.sop[1], P.snops[1], t, tbit, outer);
+      lds_store(out + ((c1 << m2) | (uint64_t)b2) * N, B2, sc, t, tbit, outer);
     }
-    __syncthreads();
   }
 }
 
@@ -346,9 +368,13 @@ __device__ __forceinline__ void diag_regs(float2 (&v)[1 << NB], const DevOp& op,
                                           const uint32_t (&RB)[NB > 0 ? NB : 1],
                                           const float2* tab) {
   constexpr int E = 1 << NB;
-  int eF = __popc(F & (uint32_t)op.t0) + 2 * __popc(F & (uint32_t)op.t1) +
-           4 * __popc(F & (uint32_t)op.t2);
-  for (int i = 0; i < op.nd; ++i) eF += 4 * __popc(F & (F >> op.d[i]) & (uint32_t)op.M[i]);
+  // every field of the op is the same in all lanes: read into scalar registers
+  const auto su = [](uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane(x); };
+  int eF = __popc(F & su((uint32_t)op.t0)) + 2 * __popc(F & su((uint32_t)op.t1)) +
+           4 * __popc(F & su((uint32_t)op.t2));
+  const int nd = __builtin_amdgcn_readfirstlane(op.nd);
+  for (int i = 0; i < nd; ++i)
+    eF += 4 * __popc(F & (F >> su((uint32_t)op.d[i])) & su((uint32_t)op.M[i]));
   int ex[E];
   ex[0] = eF << 3;
   if constexpr (NB > 0) {
@@ -356,8 +382,8 @@ __device__ __forceinline__ void diag_regs(float2 (&v)[1 << NB], const DevOp& op,
     uint32_t rr[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-      wk[k] = (op.wl[k] + 4 * __popc(F & op.cross[k])) << 3;
-      rr[k] = op.rr[k];
+      wk[k] = ((int)su((uint32_t)op.wl[k]) + 4 * __popc(F & su(op.cross[k]))) << 3;
+      rr[k] = su(op.rr[k]);
     }
 #pragma unroll
     for (int r = 1; r < E; ++r) {
@@ -369,10 +395,10 @@ __device__ __forceinline__ void diag_regs(float2 (&v)[1 << NB], const DevOp& op,
   uint32_t off[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) off[r] = (uint32_t)ex[r] & 56u;
-  if (op.pmask) {
+  if (__builtin_amdgcn_readfirstlane((uint32_t)op.pmask) != 0) {
     // (x & pm) == pv splits into the lane's fixed bits and the register bits,
     // whose part is the same in every lane
-    const uint32_t pm = (uint32_t)op.pmask, pv = (uint32_t)op.pval;
+    const uint32_t pm = su((uint32_t)op.pmask), pv = su((uint32_t)op.pval);
     uint32_t rbm = 0;
 #pragma unroll
     for (int k = 0; k < NB; ++k) rbm |= RB[k];
@@ -398,8 +424,8 @@ __device__ __forceinline__ void wave_apply_ops(float2 (&v)[1 << R], const DevOp*
   constexpr int E = 1 << R;
   for (int o = 0; o < nops; ++o) {
     const DevOp& op = ops[o];
-    if (op.kind == 0) {
-      const int w = op.target;
+    if (__builtin_amdgcn_readfirstlane(op.kind) == 0) {
+      const int w = __builtin_amdgcn_readfirstlane(op.target);
       if (w < 6) {
         lane_mat<E>(v, op, w, (lane >> w) & 1);
       } else {
@@ -416,111 +442,201 @@ __device__ __forceinline__ void wave_apply_ops(float2 (&v)[1 << R], const DevOp*
   }
 }
 
+// Index bits of a wave tile: lane l holds the state bits F = xo | l (xo, the
+// tile's outer bits, is the same in every lane of the wave) and register r
+// adds the bits O_r = sum_k r_k RB[k].  Everything but the lane part is
+// wave-uniform, so the address of register r is a scalar base plus 8 l: the
+// loads and stores take the base in scalar registers and share one vector
+// offset, and conditions on an index split into a lane part and a uniform
+// register part.
+
+// Child of a wave tile: the cut factors of branch b (m cut bits on state bits
+// bq, MSB first) applied to v.
 template <int R>
+__device__ __forceinline__ void wave_child(float2 (&w)[1 << R], const float2 (&v)[1 << R],
+                                           const int* bq, int m, int b, int upper, uint32_t F,
+                                           const uint32_t (&RB)[R]) {
+  uint32_t cmask, cval, zmask;
+  cut_factors(bq, m, b, upper, cmask, cval, zmask);
+  uint32_t rbm = 0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) rbm |= RB[k];
+  // (x & cmask) == cval for x = F | O_r: the lane bits and the register bits separately
+  const bool lane_ok = (F & cmask) == (cval & ~rbm);
+  const bool lane_neg = __popc(F & zmask) & 1;
+#pragma unroll
+  for (int r = 0; r < (1 << R); ++r) {
+    const uint32_t o = reg_index<R>(r, RB);
+    const bool reg_ok = (o & cmask) == (cval & rbm);
+    const bool neg = lane_neg != (bool)(__popc(o & zmask) & 1);
+    float2 a = v[r];
+    if (!(lane_ok && reg_ok)) a = make_float2(0.f, 0.f);
+    if (neg) a = make_float2(-a.x, -a.y);
+    w[r] = a;
+  }
+}
+
+// Store of a wave tile, scaled by sc, at row + xo + O_r + lane; nt: streaming
+// stores that bypass the caches (the outputs are read again only by the next
+// pass or the leaf stage).
+template <int R>
+__device__ __forceinline__ void wave_store(float2* row, const float2 (&v)[1 << R], float sc,
+                                           uint32_t xo, uint32_t lane, const uint32_t (&RB)[R],
+                                           int nt) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  if (nt) {
+#pragma unroll
+    for (int r = 0; r < (1 << R); ++r) {
+      const f32x2 a = {v[r].x * sc, v[r].y * sc};
+      float2* base = row + (xo | reg_index<R>(r, RB));
+      __builtin_nontemporal_store(a, (f32x2*)(base + lane));
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < (1 << R); ++r) {
+      float2* base = row + (xo | reg_index<R>(r, RB));
+      base[lane] = make_float2(v[r].x * sc, v[r].y * sc);
+    }
+  }
+}
+
+// S = number of branch stages (P.ns).  The pass's ops (n_all of them from
+// op_in) are staged in LDS first, so that every wave reads its op stream from
+// LDS instead of waiting on a chain of scalar loads per op.
+template <int R, int S>
 __global__ void __launch_bounds__(kWaveThreads)
 k_wpass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops, const float2* in,
         float2* out, uint64_t total_tiles, const uint32_t* __restrict__ tlist, uint32_t n_list) {
   constexpr int E = 1 << R;
+  extern __shared__ uint2 wp_ops[];
   __shared__ float2 tab[kPhaseEntries];
-  init_phase_table(tab);
   const PassDesc& P = *pdp;
-  const int lane = threadIdx.x & 63;
-  const uint64_t wt = (uint64_t)blockIdx.x * (kWaveThreads / 64) + (threadIdx.x >> 6);
-  if (wt >= total_tiles) return;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t wt = (uint64_t)blockIdx.x * (kWaveThreads / 64) +
+                      (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool active = wt < total_tiles;
+  // the tile: its node, its outer bits (the same in every lane of the wave)
+  // and its register bits
   const int nouter = P.n_outer;
-  uint64_t node, tile;
-  if (tlist) {
-    // only the listed tiles of every node (the rest is never read)
-    node = wt / n_list;
-    tile = tlist[wt - node * n_list];
-  } else {
-    node = wt >> nouter;
-    tile = wt & ((1ull << nouter) - 1);
+  uint64_t node = 0, tile = 0;
+  if (active) {
+    if (tlist) {
+      // only the listed tiles of every node (the rest is never read)
+      node = wt / n_list;
+      tile = tlist[wt - node * n_list];
+    } else {
+      node = wt >> nouter;
+      tile = wt & ((1ull << nouter) - 1);
+    }
   }
   uint32_t xo = 0;
   for (int j = 0; j < nouter; ++j) xo |= (uint32_t)((tile >> j) & 1) << P.obit[j];
+  xo = __builtin_amdgcn_readfirstlane(xo);
+  node = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(node >> 32)) << 32) |
+         (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)node);
   uint32_t RB[R];
 #pragma unroll
   for (int k = 0; k < R; ++k) RB[k] = 1u << P.tbit[6 + k];
-  const uint32_t F = xo | (uint32_t)lane;
+  const uint32_t F = xo | lane;
   const uint64_t N = 1ull << P.n;
+  // the tile's loads go out first, so that their latency overlaps the
+  // staging of the ops below
   float2 v[E];
   if (P.init) {
     const uint32_t hmask = ~(uint32_t)P.hinit;
     const float h = P.hamp;
+    const bool lane_ok = (F & hmask) == 0;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-      const uint32_t x = F | reg_index<R>(r, RB);
-      v[r] = ((x & hmask) == 0) ? make_float2(h, 0.f) : make_float2(0.f, 0.f);
+      const bool ok = lane_ok && (reg_index<R>(r, RB) & hmask) == 0;
+      v[r] = ok ? make_float2(h, 0.f) : make_float2(0.f, 0.f);
     }
-  } else {
-    const float2* src = in + node * N;
+  } else if (active) {
+    const float2* row = in + node * N;
 #pragma unroll
-    for (int r = 0; r < E; ++r) v[r] = src[F | reg_index<R>(r, RB)];
+    for (int r = 0; r < E; ++r) v[r] = (row + (xo | reg_index<R>(r, RB)))[lane];
   }
-  wave_apply_ops<R>(v, ops + P.op_in, P.n_in, F, RB, lane, tab);
+  {
+    const uint2* src = (const uint2*)(ops + P.op_in);
+    const int nw = P.n_all * (int)(sizeof(DevOp) / sizeof(uint2));
+    for (int i = threadIdx.x; i < nw; i += kWaveThreads) wp_ops[i] = src[i];
+  }
+  init_phase_table(tab);  // and the barrier after the staging
+  if (!active) return;
+  const DevOp* sops = (const DevOp*)wp_ops;
+  wave_apply_ops<R>(v, sops, P.n_in, F, RB, (int)lane, tab);
   const float sc = P.scale;
-  if (P.m == 0) {
-    float2* dst = out + node * N;
-#pragma unroll
-    for (int r = 0; r < E; ++r)
-      dst[F | reg_index<R>(r, RB)] = make_float2(v[r].x * sc, v[r].y * sc);
-    return;
-  }
-  const int m = P.m;
-  for (int b = 0; b < (1 << m); ++b) {
-    float2 w[E];
-    uint32_t cmask, cval, zmask;
-    cut_factors(P.bq, m, b, P.upper, cmask, cval, zmask);
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-      const uint32_t x = F | reg_index<R>(r, RB);
-      float2 a = v[r];
-      if ((x & cmask) != cval) a = make_float2(0.f, 0.f);
-      if (__popc(x & zmask) & 1) a = make_float2(-a.x, -a.y);
-      w[r] = a;
+  const int nt = P.nt;
+  if constexpr (S == 0) {
+    wave_store<R>(out + node * N, v, sc, xo, lane, RB, nt);
+  } else {
+    const int m1 = P.sm[0];
+    for (int b1 = 0; b1 < (1 << m1); ++b1) {
+      float2 w[E];
+      wave_child<R>(w, v, P.sbq[0], m1, b1, P.upper, F, RB);
+      wave_apply_ops<R>(w, sops + P.sop[0], P.snops[0], F, RB, (int)lane, tab);
+      const uint64_t c1 = (node << m1) | (uint64_t)b1;
+      if constexpr (S == 1) {
+        wave_store<R>(out + c1 * N, w, sc, xo, lane, RB, nt);
+      } else {
+        const int m2 = P.sm[1];
+        for (int b2 = 0; b2 < (1 << m2); ++b2) {
+          float2 u[E];
+          wave_child<R>(u, w, P.sbq[1], m2, b2, P.upper, F, RB);
+          wave_apply_ops<R>(u, sops + P.sop[1], P.snops[1], F, RB, (int)lane, tab);
+          wave_store<R>(out + ((c1 << m2) | (uint64_t)b2) * N, u, sc, xo, lane, RB, nt);
+        }
+      }
     }
-    wave_apply_ops<R>(w, ops + P.op_out, P.n_out, F, RB, lane, tab);
-    float2* dst = out + ((node << m) | (uint64_t)b) * N;
-#pragma unroll
-    for (int r = 0; r < E; ++r)
-      dst[F | reg_index<R>(r, RB)] = make_float2(w[r].x * sc, w[r].y * sc);
   }
+}
+
+template <int R>
+static hipError_t launch_wpass_r(int S, dim3 g, dim3 b, size_t lds, hipStream_t st,
+                                 const PassDesc* d_desc, const DevOp* d_ops, const float2* in,
+                                 float2* out, uint64_t tiles, const uint32_t* tlist,
+                                 uint32_t n_list) {
+  switch (S) {
+    case 0:
+      hipLaunchKernelGGL((k_wpass<R, 0>), g, b, lds, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_wpass<R, 1>), g, b, lds, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_wpass<R, 2>), g, b, lds, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_pass(const PassDesc& h, const PassDesc* d_desc, const DevOp* d_ops,
                        const float2* in, float2* out, uint64_t n_in_nodes, const uint32_t* tlist,
                        uint32_t n_list, hipStream_t st) {
+  static_assert(kMaxStages == 2, "k_wpass and k_pass are written for at most two stages");
   if (tlist && (!h.wave || n_list == 0)) return hipErrorInvalidValue;
+  if (h.ns < 0 || h.ns > kMaxStages || h.n_all < 0 || h.n_all > kMaxPassOps)
+    return hipErrorInvalidValue;
   if (h.wave) {
     const int R = h.t - 6;
     const uint64_t tiles = tlist ? n_in_nodes * n_list : n_in_nodes << h.n_outer;
     const uint64_t blocks = (tiles + (kWaveThreads / 64) - 1) / (kWaveThreads / 64);
     if (blocks == 0 || blocks > 0x7fffffffull) return hipErrorInvalidValue;
     dim3 g((unsigned)blocks), b(kWaveThreads);
+    const size_t lds = (size_t)h.n_all * sizeof(DevOp);
     switch (R) {
-      case 1:
-        hipLaunchKernelGGL(k_wpass<1>, g, b, 0, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
-        break;
-      case 2:
-        hipLaunchKernelGGL(k_wpass<2>, g, b, 0, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
-        break;
-      case 3:
-        hipLaunchKernelGGL(k_wpass<3>, g, b, 0, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
-        break;
-      case 4:
-        hipLaunchKernelGGL(k_wpass<4>, g, b, 0, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
-        break;
-      case 5:
-        hipLaunchKernelGGL(k_wpass<5>, g, b, 0, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
-        break;
+      case 1: return launch_wpass_r<1>(h.ns, g, b, lds, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
+      case 2: return launch_wpass_r<2>(h.ns, g, b, lds, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
+      case 3: return launch_wpass_r<3>(h.ns, g, b, lds, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
+      case 4: return launch_wpass_r<4>(h.ns, g, b, lds, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
+      case 5: return launch_wpass_r<5>(h.ns, g, b, lds, st, d_desc, d_ops, in, out, tiles, tlist, n_list);
       default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
   }
   const uint64_t blocks = n_in_nodes << h.n_outer;
   if (blocks == 0 || blocks > 0x7fffffffull) return hipErrorInvalidValue;
-  const size_t lds = (size_t)(h.m > 0 ? 2 : 1) * ((size_t)8 << h.t);
+  const size_t lds = (size_t)(1 + h.ns) * ((size_t)8 << h.t);
   hipLaunchKernelGGL(k_pass, dim3((unsigned)blocks), dim3(kPassThreads), lds, st, d_desc, d_ops,
                      in, out);
   return hipGetLastError();
@@ -558,8 +674,8 @@ __device__ __forceinline__ void tail_apply_ops(float2 (&v)[R], const TailCtx<R>&
                                                const DevOp* __restrict__ ops, int nops) {
   for (int o = 0; o < nops; ++o) {
     const DevOp& op = ops[o];
-    if (op.kind == 0) {
-      const int w = op.target;
+    if (__builtin_amdgcn_readfirstlane(op.kind) == 0) {
+      const int w = __builtin_amdgcn_readfirstlane(op.target);
       // the general form: one code path per gate keeps the unrolled leaf
       // kernels small (a branch per gate kind there costs more than it saves)
       if (w < c.lg) {

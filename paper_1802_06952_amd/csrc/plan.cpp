@@ -15,9 +15,11 @@
 // is only applied to the output amplitudes.
 //
 // Levels up to a chosen depth are materialised as full half states by
-// passes over LDS tiles; the deeper levels are evaluated only at the
-// requested half values, on the subspace spanned by the non-diagonal targets
-// of those levels (the light cone), which these levels leave invariant.
+// passes over register tiles of one wavefront (LDS tiles for small halves);
+// a pass may descend several levels at once.  The deeper levels are evaluated
+// only at the requested half values, on the subspace spanned by the
+// non-diagonal targets of those levels (the light cone), which these levels
+// leave invariant.
 #include "plan.h"
 
 #include <algorithm>
@@ -177,15 +179,16 @@ Tree build_tree(const Side& s, int c, const Block& blk) {
 namespace {
 
 // Greedy pass packing: take ops in order while their non-diagonal targets fit
-// in the tile; an op that does not fit is deferred together with every later
-// op that does not commute with a deferred one.
+// in the tile and the pass holds fewer than `budget` ops; an op that does not
+// fit is deferred together with every later op that does not commute with a
+// deferred one.
 void absorb(const Side& s, const std::vector<int>& P, std::vector<int>& S, int tmax,
-            std::vector<int>& taken, std::vector<int>& deferred, bool one_op) {
+            std::vector<int>& taken, std::vector<int>& deferred, bool one_op, int& budget) {
   std::vector<char> nd_def(s.n, 0), any_def(s.n, 0);
   taken.clear();
   deferred.clear();
   for (int i : P) {
-    if (one_op && !taken.empty()) {
+    if ((one_op && !taken.empty()) || budget <= 0) {
       deferred.push_back(i);
       continue;
     }
@@ -207,6 +210,7 @@ void absorb(const Side& s, const std::vector<int>& P, std::vector<int>& S, int t
       if (nd) nd_def[o.q0] = 1;
     } else {
       taken.push_back(i);
+      --budget;
     }
   }
 }
@@ -238,57 +242,129 @@ double op_cost(const Side& s, const std::vector<int>& ops) {
   return c;
 }
 
-// Greedy packing of the materialised levels 0..ls into passes.
-void build_passes(const Side& s, const Tree& tree, int ls, int t, int b, bool one_op,
-                  const std::vector<uint64_t>& nodes, std::vector<PassPlan>& passes,
-                  double& cost, size_t& peak) {
+// Cost-model price and peak live states of one pass.
+void price_pass(const Side& s, const PassPlan& pp, const std::vector<uint64_t>& nodes,
+                double& cost, size_t& peak) {
   const double B = std::ldexp(8.0, s.n);
   const double N = std::ldexp(1.0, s.n);
-  std::vector<std::vector<int>> pending(ls + 1);
-  for (int l = 0; l <= ls; ++l) pending[l] = tree.levels[l].ops;
-  int cur = 0;
-  bool first = true;
-  cost = 0;
-  peak = 1;
-  passes.clear();
-  for (int guard = 0; guard < 100000; ++guard) {
-    PassPlan pp;
-    pp.level_in = cur;
-    pp.init = first;
-    first = false;
-    std::vector<int> S;
-    for (int q = 0; q < b; ++q) S.push_back(q);
-    std::vector<int> deferred;
-    absorb(s, pending[cur], S, t, pp.ops_in, deferred, one_op);
-    pending[cur] = deferred;
-    if (deferred.empty() && cur < ls && !(one_op && !pp.ops_in.empty())) {
-      std::vector<int> d2;
-      absorb(s, pending[cur + 1], S, t, pp.ops_out, d2, one_op);
-      pending[cur + 1] = d2;
-      pp.branch = true;
-      ++cur;
+  const double nin = (double)nodes[pp.level_in];
+  double bytes, alu;
+  if (pp.branch()) {
+    const double nout = (double)nodes[pp.level_out()];
+    bytes = (pp.init ? 0 : B * nin) + B * nout;
+    alu = op_cost(s, pp.ops_in);
+    for (size_t st = 0; st < pp.stages.size(); ++st)
+      alu += ((double)nodes[pp.level_in + st + 1] / nin) * (op_cost(s, pp.stages[st]) + 6);
+    alu *= N * nin;
+    peak = std::max<size_t>(peak, nodes[pp.level_in] + nodes[pp.level_out()]);
+  } else {
+    bytes = (pp.init ? 1 : 2) * B * nin;
+    alu = N * nin * (op_cost(s, pp.ops_in) + 4);
+    peak = std::max<size_t>(peak, nodes[pp.level_in]);
+  }
+  cost += std::max(bytes, alu * kBytesPerLaneOp) + kLaunchBytes;
+}
+
+// Packing of the materialised levels 0..ls into passes.  Inside a level the
+// pending ops go greedily into passes of at most t tile bits; the pass that
+// takes the last of them branches, and descends 1 .. max_stages levels at
+// once (each further stage only if the previous level's ops all fitted), so
+// the levels in between never reach memory.  The number of stages of every
+// branch pass is chosen for the lowest total cost (a search over the levels
+// where the passes land; the state after a branch pass is its landing level
+// and the ops of that level still pending).
+struct PassPacker {
+  const Side& s;
+  const Tree& tree;
+  int ls, t, tmin, b, max_stages;
+  bool one_op;
+  const std::vector<uint64_t>& nodes;
+  struct Res {
+    double cost = 0;
+    size_t peak = 1;
+    std::vector<PassPlan> passes;
+  };
+  std::map<std::pair<int, std::vector<int>>, Res> memo;
+
+  Res solve(int cur, std::vector<int> P, bool first) {
+    const auto key = std::make_pair(first ? -1 - cur : cur, P);
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+    Res r;
+    for (int guard = 0; guard < 100000; ++guard) {
+      if (cur == ls && P.empty() && !first) break;  // landed on the last level with nothing left
+      PassPlan pp;
+      pp.level_in = cur;
+      pp.init = first;
+      first = false;
+      std::vector<int> S;
+      for (int q = 0; q < b; ++q) S.push_back(q);
+      std::vector<int> deferred;
+      int budget = kMaxPassOps;
+      absorb(s, P, S, t, pp.ops_in, deferred, one_op, budget);
+      P = deferred;
+      const bool open = deferred.empty() && !(one_op && !pp.ops_in.empty());
+      if (!open || cur == ls) {
+        finish(pp, S);
+        price_pass(s, pp, nodes, r.cost, r.peak);
+        r.passes.push_back(pp);
+        if (cur == ls && P.empty()) break;
+        continue;
+      }
+      // branch: try every feasible number of stages
+      Res best;
+      bool have = false;
+      PassPlan bp = pp;
+      std::vector<int> BS = S;
+      int bud = budget;
+      for (int ns = 1; ns <= max_stages && cur + ns <= ls; ++ns) {
+        std::vector<int> taken, d2;
+        absorb(s, tree.levels[cur + ns].ops, BS, t, taken, d2, one_op, bud);
+        bp.stages.push_back(taken);
+        PassPlan fin = bp;
+        finish(fin, BS);
+        Res cand;
+        price_pass(s, fin, nodes, cand.cost, cand.peak);
+        Res rest = solve(cur + ns, d2, false);
+        cand.cost += rest.cost;
+        cand.peak = std::max(cand.peak, rest.peak);
+        cand.passes.push_back(fin);
+        cand.passes.insert(cand.passes.end(), rest.passes.begin(), rest.passes.end());
+        if (!have || cand.cost < best.cost) {
+          best = std::move(cand);
+          have = true;
+        }
+        if (!d2.empty() || bud <= 0) break;  // a further stage needs all of this level's ops
+      }
+      r.cost += best.cost;
+      r.peak = std::max(r.peak, best.peak);
+      r.passes.insert(r.passes.end(), best.passes.begin(), best.passes.end());
+      break;
     }
-    // fill the tile up to t bits with the lowest unused qubits
-    for (int q = 0; (int)S.size() < t && q < s.n; ++q)
+    memo[key] = r;
+    return r;
+  }
+
+  // fill the tile with the lowest unused qubits up to tmin bits (a tile holds
+  // at least the pass's targets; a smaller tile means fewer registers per
+  // lane and more wavefronts in flight)
+  void finish(PassPlan& pp, std::vector<int> S) const {
+    for (int q = 0; (int)S.size() < tmin && q < s.n; ++q)
       if (std::find(S.begin(), S.end(), q) == S.end()) S.push_back(q);
     std::sort(S.begin(), S.end());
     pp.tile = S;
-    const double nin = (double)nodes[pp.level_in];
-    double bytes, alu;
-    if (pp.branch) {
-      const double nout = (double)nodes[cur];
-      bytes = (pp.init ? 0 : B * nin) + B * nout;
-      alu = N * nin * (op_cost(s, pp.ops_in) + (nout / nin) * (op_cost(s, pp.ops_out) + 6));
-      peak = std::max<size_t>(peak, nodes[pp.level_in] + nodes[cur]);
-    } else {
-      bytes = (pp.init ? 1 : 2) * B * nin;
-      alu = N * nin * (op_cost(s, pp.ops_in) + 4);
-      peak = std::max<size_t>(peak, nodes[cur]);
-    }
-    cost += std::max(bytes, alu * kBytesPerLaneOp) + kLaunchBytes;
-    passes.push_back(pp);
-    if (cur == ls && pending[ls].empty()) break;
   }
+};
+
+void build_passes(const Side& s, const Tree& tree, int ls, int t, int tmin, int b, bool one_op,
+                  int max_stages, const std::vector<uint64_t>& nodes,
+                  std::vector<PassPlan>& passes, double& cost, size_t& peak) {
+  PassPacker pk{s, tree, ls, t, std::min(t, tmin), b,
+                one_op ? 1 : std::max(1, std::min(max_stages, kMaxStages)), one_op, nodes, {}};
+  PassPacker::Res r = pk.solve(0, tree.levels[0].ops, true);
+  passes = std::move(r.passes);
+  cost = r.cost;
+  peak = r.peak;
 }
 
 }  // namespace
@@ -302,12 +378,13 @@ bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, Side
   const double B = std::ldexp(8.0, s.n);
   // states of 7+ qubits use wave tiles: lanes over state bits 0..5 plus up to
   // 5 register bits; smaller states are staged whole in LDS
-  int t, b;
+  int t, tmin, b;
   if (s.n >= 7) {
     t = std::max(7, std::min({kn.tile_bits, s.n, 11}));
+    tmin = std::max(7, std::min(kn.min_tile_bits, t));
     b = 6;
   } else {
-    t = s.n;
+    t = tmin = s.n;
     b = std::max(0, std::min(kn.coalesce_bits, t - 1));
   }
 
@@ -335,7 +412,8 @@ bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, Side
     if (nlev > kMaxTailLevels || M > 16) continue;
     double cost = 0;
     size_t peak = 1;
-    build_passes(s, tree, ls, t, b, kn.one_op_per_pass, nodes, sp.passes, cost, peak);
+    build_passes(s, tree, ls, t, tmin, b, kn.one_op_per_pass, kn.max_stages, nodes, sp.passes, cost,
+                 peak);
     // leaf evaluation: the backward rows per requested value (arithmetic and
     // the W round trip), the contiguous gathers of the node amplitudes (the
     // light cone is relabelled onto the lowest state bits), and the per-value
@@ -387,8 +465,8 @@ bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, Side
   {
     double cost = 0;
     size_t peak = 1;
-    build_passes(r, best.tree, best.lstar, t, b, kn.one_op_per_pass, best.nodes, best.passes,
-                 cost, peak);
+    build_passes(r, best.tree, best.lstar, t, tmin, b, kn.one_op_per_pass, kn.max_stages, best.nodes,
+                 best.passes, cost, peak);
   }
   out = std::move(best);
   return true;
@@ -616,10 +694,14 @@ std::string dump_json(const Circuit& c, uint64_t upper_mask, const std::vector<C
       for (size_t p = 0; p < sp->passes.size(); ++p) {
         const PassPlan& pp = sp->passes[p];
         o << (p ? "," : "") << "{\"level_in\":" << pp.level_in << ",\"init\":" << (pp.init ? 1 : 0)
-          << ",\"branch\":" << (pp.branch ? 1 : 0) << ",\"ops_in\":[";
+          << ",\"branch\":" << pp.stages.size() << ",\"ops_in\":[";
         for (size_t i = 0; i < pp.ops_in.size(); ++i) o << (i ? "," : "") << pp.ops_in[i];
-        o << "],\"ops_out\":[";
-        for (size_t i = 0; i < pp.ops_out.size(); ++i) o << (i ? "," : "") << pp.ops_out[i];
+        o << "],\"stages\":[";
+        for (size_t st = 0; st < pp.stages.size(); ++st) {
+          o << (st ? "," : "") << "[";
+          for (size_t i = 0; i < pp.stages[st].size(); ++i) o << (i ? "," : "") << pp.stages[st][i];
+          o << "]";
+        }
         o << "],\"tile\":[";
         // tiles are printed as local qubit ids of the unrelabelled half
         std::vector<int> inv(sp->perm.size());

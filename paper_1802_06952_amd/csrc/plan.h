@@ -45,12 +45,18 @@ struct Tree {
 
 Tree build_tree(const Side& s, int c, const Block& blk);
 
+// A pass reads the states of tree level level_in, runs ops_in on them, and
+// with stages descends one level per stage: stage s branches on the cuts of
+// level level_in + s + 1 and runs stages[s] (ops of that level) on every
+// child.  It writes level level_in + stages.size().
 struct PassPlan {
   int level_in = 0;
   bool init = false;
-  bool branch = false;
-  std::vector<int> ops_in, ops_out;
+  std::vector<int> ops_in;
+  std::vector<std::vector<int>> stages;
   std::vector<int> tile;  // local qubits of the tile, ascending
+  bool branch() const { return !stages.empty(); }
+  int level_out() const { return level_in + (int)stages.size(); }
 };
 
 struct SidePlan {
@@ -66,13 +72,15 @@ struct SidePlan {
 };
 
 struct PlanKnobs {
-  int tile_bits = 10;
+  int tile_bits = 10;      // largest tile of a full-state pass
+  int min_tile_bits = 8;   // a pass's tile shrinks to its targets, but not below this
   int coalesce_bits = 5;
   int tail_max_qubits = 10;
   int force_lstar = -1;
   size_t mem_budget = 0;  // bytes; 0 = unlimited
   int S = 1;              // requested values of this half (for the cost model)
   bool one_op_per_pass = false;  // flat comparison form: every half op is its own pass
+  int max_stages = kMaxStages;   // tree levels one pass may descend (1 = one level per pass)
 };
 
 bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, SidePlan& out,

@@ -119,13 +119,22 @@ struct DevOp {
   uint32_t rr[kMaxRegBits];
 };
 
+// Branch stages of one pass at most: a pass may descend this many tree levels
+// at once (a parent tile gives 2^(m_1 + ... + m_S) children without the
+// intermediate levels reaching memory).
+constexpr int kMaxStages = 2;
+// Ops of one pass at most (its ops are staged in LDS).
+constexpr int kMaxPassOps = 128;
+
 // A full-state pass: every tile of 2^t amplitudes (the tile bits are state
-// bits tbit[0..t-1]) is loaded once, gets `n_in` ops, then for each of the
-// 2^m children of a branch (m = 0: a single output) the child's cut factors
-// and `n_out` ops, and is stored.  wave = 1: one wavefront owns a tile; its
-// 64 lanes hold state bits 0..5 (tbit[0..5]) and each lane holds 2^(t-6)
-// amplitudes in registers over the state bits tbit[6..t-1].  wave = 0: one
-// workgroup stages the tile in LDS (small states).
+// bits tbit[0..t-1]) is loaded once and gets `n_in` ops; with ns = 0 it is
+// stored.  With ns > 0 stages it branches: stage s decides the m_s cut bits
+// of the next tree level, and for each of their 2^m_s values the tile gets
+// that child's cut factors and the stage's ops; the last stage's results are
+// stored, at child (((node << m_1) | b_1) << m_2) | b_2 ...  wave = 1: one
+// wavefront owns a tile; its 64 lanes hold state bits 0..5 (tbit[0..5]) and
+// each lane holds 2^(t-6) amplitudes in registers over the state bits
+// tbit[6..t-1].  wave = 0: one workgroup stages the tile in LDS (small states).
 struct PassDesc {
   int wave;
   int n;             // state qubits
@@ -136,11 +145,15 @@ struct PassDesc {
   int init;          // 1: no input, start from the product state given by hinit
   uint64_t hinit;
   float hamp;        // amplitude of the initial product state
-  int op_in, n_in;   // range in the op table
-  int op_out, n_out;
-  int m;             // branch bits (0 = no branch)
-  int bq[kMaxBranch];  // state bit of the cut qubit of branch bit i (bit i = MSB first)
+  int op_in, n_in;   // range in the op table; the stages' ops follow it
+  int n_all;         // ops of the pass: n_in plus the stages' ops
+  int ns;            // branch stages (0 = no branch)
+  int sm[kMaxStages];              // cut bits of each stage
+  int sbq[kMaxStages][kMaxBranch]; // state bit of the cut qubit of each stage bit (MSB first)
+  int sop[kMaxStages];             // first op of each stage, counted from op_in
+  int snops[kMaxStages];           // ops of each stage
   int upper;         // 1: P_b factors, 0: Z^b factors
+  int nt;            // 1: stores bypass the caches (streaming outputs)
   float scale;       // exact power of two applied at the store (keeps unit-entry gates in range)
 };
 

@@ -4,6 +4,8 @@ rocprofv3 writes one SQLite database per run.  Two summaries are made here:
 
 * ``trace``: per-kernel call count, total and average duration from a
   ``--kernel-trace --stats`` run, plus each kernel's register and LDS use;
+* ``sq``: per-kernel MFMA utilisation and instruction counts from one ``--pmc``
+  run of SQ and GRBM counters;
 * ``counters``: HBM bytes per dispatch of one kernel family from two ``--pmc``
   runs (``FETCH_SIZE``, then ``WRITE_SIZE``, both in KiB per dispatch).  Each
   counter is divided by what it reads for a plain copy of known size made in
@@ -110,6 +112,38 @@ def counter_summary(fetch_dir: str, write_dir: str, kernel: str, calib_bytes: in
             "kernels_hip_sha256_16": kernel_source_hash()}
 
 
+def sq_summary(d: str, cmd: str, simds: int = 1024) -> str:
+    """Per-kernel averages of SQ/GRBM counters from one --pmc run: MFMA busy
+    cycles against GRBM_GUI_ACTIVE times the SIMD count (MFMA utilisation),
+    MFMA flops (each MOPS unit is 512 flops), and the VALU, SALU and LDS
+    instruction counts per dispatch."""
+    vals, names = _pmc(d)
+    per = collections.defaultdict(list)
+    for disp, cs in vals.items():
+        per[names[disp]].append(cs)
+    cols = ["SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE", "SQ_INSTS_VALU_MFMA_MOPS_F32",
+            "SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS",
+            "SQ_WAVES"]
+    out = [f"Command: `{cmd}`", "",
+           "rocprofv3 `--pmc` counters, averaged over the dispatches of each kernel. MFMA "
+           f"utilisation = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x {simds} SIMDs); MFMA "
+           "GFLOP = (MOPS_F32 + MOPS_BF16) x 512 / 1e9.", "",
+           "| kernel | dispatches | MFMA util | MFMA GFLOP (F32) | MFMA GFLOP (BF16) | VALU insts | "
+           "SALU insts | LDS insts | waves |", "|---|---|---|---|---|---|---|---|---|"]
+    for n in sorted(per, key=lambda k: -sum(x.get("GRBM_GUI_ACTIVE", 0) for x in per[k])):
+        rows = per[n]
+        avg = {c: sum(r.get(c, 0.0) for r in rows) / len(rows) for c in cols}
+        util = avg["SQ_VALU_MFMA_BUSY_CYCLES"] / max(1.0, avg["GRBM_GUI_ACTIVE"] * simds)
+        out.append(f"| `{n}` | {len(rows)} | {100 * util:.1f} % | "
+                   f"{avg['SQ_INSTS_VALU_MFMA_MOPS_F32'] * 512 / 1e9:.2f} | "
+                   f"{avg['SQ_INSTS_VALU_MFMA_MOPS_BF16'] * 512 / 1e9:.2f} | "
+                   f"{avg['SQ_INSTS_VALU']:.3g} | {avg['SQ_INSTS_SALU']:.3g} | "
+                   f"{avg['SQ_INSTS_LDS']:.3g} | {avg['SQ_WAVES']:.0f} |")
+    out.append("")
+    out.append(f"kernels.hip sha256[:16] = {kernel_source_hash()}")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -123,9 +157,14 @@ def main(argv=None):
     c.add_argument("--workload", required=True)
     c.add_argument("--calib-bytes", type=int, required=True)
     c.add_argument("--cmd", required=True)
+    q = sub.add_parser("sq")
+    q.add_argument("dir")
+    q.add_argument("--cmd", required=True)
     a = ap.parse_args(argv)
     if a.what == "trace":
         sys.stdout.write(trace_summary(a.dir, a.cmd))
+    elif a.what == "sq":
+        sys.stdout.write(sq_summary(a.dir, a.cmd))
     else:
         d = counter_summary(a.fetch_dir, a.write_dir, a.kernel, a.calib_bytes)
         d["workload"] = a.workload

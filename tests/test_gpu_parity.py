@@ -300,6 +300,46 @@ def test_cut_invariance_against_golden(row_name, cut_name, sub):
     assert_close(amp, ref, 1e-5)
 
 
+def test_coscheduled_uneven_pair_against_golden():
+    """The uneven pair run together: the 42-qubit circuit cut 18+24 and the
+    36-qubit circuit cut 16+20, each plan on a stream of its own (and each
+    plan's lower half on the plan's second stream), launched back to back so
+    that copies of all four half sizes are in flight at once.  Both results
+    against the row-cut goldens of the same circuits, twice over (the second
+    round reuses the registered bitstrings and cached plans)."""
+    Q = _lib()
+    import torch
+    cases = []
+    for row_name, cut_name, sub in (("grid6x7_d20", "grid6x7_d20_cols", None),
+                                    ("grid6x6_d16", "grid6x6_d16_stair", 4096)):
+        wr, wc = workload(row_name), workload(cut_name)
+        g = _golden(row_name)
+        bits = _golden_bits(wr, g)
+        ref = g["amp"]
+        if sub:
+            idx = np.random.default_rng(0).choice(bits.size, size=sub, replace=False)
+            bits, ref = bits[idx], ref[idx]
+        cases.append((wc, bits, ref))
+    streams = [torch.cuda.Stream() for _ in cases]
+    plans = [Q.Plan(wc.circuit_text(), wc.upper_mask) for wc, _, _ in cases]
+    try:
+        assert [(p.n_upper, p.n_lower) for p in plans] == [(18, 24), (16, 20)]
+        outs = [torch.empty(2 * b.size, dtype=torch.float32, device="cuda") for _, b, _ in cases]
+        for rnd in range(2):
+            say(f"case co-scheduled uneven pair, round {rnd}")
+            for p, (wc, bits, _), st, o in zip(plans, cases, streams, outs):
+                p.reset(keep_bitstrings=rnd > 0)
+                p.run_halves(0, 1 << p.n_cuts, bits if rnd == 0 else None, st)
+                p.amplitudes_device(0, o.data_ptr(), None, st)
+            torch.cuda.synchronize()
+            for (wc, _, ref), o in zip(cases, outs):
+                amp = o.cpu().numpy().view(np.complex64)
+                assert_close(amp, ref, 1e-5, what=wc.name)
+    finally:
+        for p in plans:
+            p.close()
+
+
 def test_grid6x8_slice_golden():
     """Copies [0, 64) of 65536 of a 48-qubit circuit: partial amplitudes vs the oracle."""
     Q = _lib()

@@ -221,6 +221,127 @@ def test_tree_schedule_replays_to_oracle(rows, cols, depth, mask):
         assert np.max(np.abs(got - ref)) < 1e-12
 
 
+def _run_op(psi, side, cq, oi, fixed):
+    """One half op; a cut op inside an op list is a cut fixed by the block."""
+    op = side["ops"][oi]
+    if op[0] == "cut":
+        _cut_factor(psi, side["n"], cq[op[3]], fixed(op[3]), side["upper"])
+    else:
+        _apply(psi, side["n"], op)
+
+
+def _level_states(side, cuts, upto, fixed):
+    """States of every node of tree levels 0..upto, level by level."""
+    n = side["n"]
+    loc = {g: i for i, g in enumerate(side["qubits"])}
+    cq = [loc[(k[1] if side["upper"] else k[2])] for k in cuts]
+    h = side["hinit"]
+    x = np.arange(1 << n)
+    psi0 = np.zeros(1 << n, dtype=complex)
+    psi0[(x & ~h) == 0] = 2.0 ** (-bin(h).count("1") / 2)
+    levels = side["levels"]
+    cur = {0: psi0}
+    for oi in levels[0]["ops"]:
+        _run_op(cur[0], side, cq, oi, fixed)
+    for li in range(1, upto + 1):
+        lv = levels[li]
+        m = len(lv["cuts"])
+        nxt = {}
+        for node, psi in cur.items():
+            for b in range(1 << m):
+                s = psi.copy()
+                for i, j in enumerate(lv["cuts"]):
+                    _cut_factor(s, n, cq[j], (b >> (m - 1 - i)) & 1, side["upper"])
+                for oi in lv["ops"]:
+                    _run_op(s, side, cq, oi, fixed)
+                nxt[(node << m) | b] = s
+        cur = nxt
+    return cur, cq
+
+
+def _pass_states(side, cq, fixed):
+    """States of the last materialised level as the passes compute them: each
+    pass runs ops_in on every node of its level, then descends one level per
+    branch stage (cut factors of that level's cuts, then the stage's ops)."""
+    n = side["n"]
+    levels = side["levels"]
+    h = side["hinit"]
+    x = np.arange(1 << n)
+    cur = None
+    for pp in side["passes"]:
+        li = pp["level_in"]
+        if pp["init"]:
+            psi0 = np.zeros(1 << n, dtype=complex)
+            psi0[(x & ~h) == 0] = 2.0 ** (-bin(h).count("1") / 2)
+            cur = {0: psi0}
+        for psi in cur.values():
+            for oi in pp["ops_in"]:
+                _run_op(psi, side, cq, oi, fixed)
+        for st, so in enumerate(pp["stages"]):
+            lv = levels[li + st + 1]
+            m = len(lv["cuts"])
+            nxt = {}
+            for node, psi in cur.items():
+                for b in range(1 << m):
+                    s = psi.copy()
+                    for i, j in enumerate(lv["cuts"]):
+                        _cut_factor(s, n, cq[j], (b >> (m - 1 - i)) & 1, side["upper"])
+                    for oi in so:
+                        _run_op(s, side, cq, oi, fixed)
+                    nxt[(node << m) | b] = s
+            cur = nxt
+    return cur
+
+
+@pytest.mark.parametrize("rows,cols,depth,mask,kw", [
+    (4, 4, 12, W.grid_rows_mask(4, 4, [0, 1]), {}),
+    (4, 4, 16, W.grid_cols_mask(4, 4, [0, 1]), {"tile_bits": 7}),
+    (3, 6, 16, W.grid_rows_mask(3, 6, [0]), {"tile_bits": 7, "materialize_level": 6}),
+    (4, 5, 14, W.grid_rows_mask(4, 5, [0, 1]), {"tile_bits": 8, "materialize_level": 4}),
+    (2, 6, 12, W.grid_cols_mask(2, 6, [0, 2, 4]), {"materialize_level": 3}),
+    (4, 5, 14, W.grid_rows_mask(4, 5, [0, 1]), {"plain": True}),
+])
+def test_pass_schedule_matches_tree_levels(rows, cols, depth, mask, kw):
+    """Every op of the materialised levels runs exactly once, in an order the
+    tree allows, when the passes (with their multi-level branch stages) are
+    replayed: the last materialised level comes out as the level-by-level
+    replay gives it, node for node."""
+    text = W.random_grid_circuit(rows, cols, depth, 5)
+    p = Q.Plan(text, mask, **kw)
+    d = p.dump(0, 1 << p.n_cuts)
+    p.close()
+    for side in d["sides"]:
+        ls = side["lstar"]
+        every = [i for lv in side["levels"][: ls + 1] for i in lv["ops"]]
+        ran = [i for pp in side["passes"] for i in pp["ops_in"] + [j for so in pp["stages"] for j in so]]
+        assert sorted(ran) == sorted(every)
+        assert all(pp["level_in"] + pp["branch"] <= ls for pp in side["passes"])
+        c = len(d["cuts"])
+        k0 = d["block"]["k0"]
+        fixed = lambda j: (k0 >> (c - 1 - j)) & 1
+        ref, cq = _level_states(side, d["cuts"], ls, fixed)
+        got = _pass_states(side, cq, fixed)
+        assert sorted(got) == sorted(ref)
+        for k in ref:
+            assert np.max(np.abs(got[k] - ref[k])) < 1e-12
+
+
+def test_multi_level_passes_are_used():
+    """On the 42-qubit workload the planner lands the passes two levels apart
+    where the ops fit, so fewer tree levels are written than materialised."""
+    from workloads import workload
+    w = workload("grid6x7_d20")
+    p = Q.Plan(w.circuit_text(), w.upper_mask)
+    d = p.dump(0, 1 << p.n_cuts)
+    one = Q.Plan(w.circuit_text(), w.upper_mask, max_stages=1).dump(0, 1 << p.n_cuts)
+    p.close()
+    for s2, s1 in zip(d["sides"], one["sides"]):
+        assert max(pp["branch"] for pp in s2["passes"]) == 2
+        assert max(pp["branch"] for pp in s1["passes"]) == 1
+        written = {pp["level_in"] + pp["branch"] for pp in s2["passes"] if pp["branch"]}
+        assert len(written) < s2["lstar"]
+
+
 @pytest.mark.parametrize("rows,cols,depth,two_qubit,mask", [
     (4, 4, 12, "cx", W.grid_rows_mask(4, 4, [0, 1])),
     (4, 4, 14, "cy", W.grid_rows_mask(4, 4, [0])),

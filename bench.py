@@ -587,6 +587,25 @@ def main() -> int:
     elif knobs:
         out["knobs_source"] = "paper_1802_06952_amd/tuned.json (autotuner, same inputs)"
 
+    # the same step as one HIP graph per step (qs_run_graph), on a stream of
+    # its own (a graph cannot be captured on the null stream)
+    gs = torch.cuda.Stream()
+    plan.run_graph(k0, k1, prec, d_out.data_ptr(), d_sums.data_ptr(), gs)   # eager step + capture
+    for _ in range(a.warmup):
+        plan.run_graph(k0, k1, prec, d_out.data_ptr(), d_sums.data_ptr(), gs)
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    for _ in range(a.steps):
+        plan.run_graph(k0, k1, prec, d_out.data_ptr(), d_sums.data_ptr(), gs)
+    torch.cuda.synchronize()
+    gms = (time.perf_counter() - tg0) * 1000.0 / a.steps
+    out["graph"] = {"value": round(m / (gms / 1000.0), 1), "unit": "amplitudes/s",
+                    "ms_per_step": round(gms, 4),
+                    "note": "the same step captured once into a HIP graph by the library "
+                            "(qs_run_graph) and replayed: one launch per step"}
+    step(prec)
+    torch.cuda.synchronize()
+
     # split-BF16 assembly on the same simulated halves
     if prec == 0:
         for _ in range(2):

@@ -291,6 +291,25 @@ qs_status qs_set_timing(qs_plan* plan, int enable);
  * QS_ERR_HIP. */
 qs_status qs_get_pass_timing(qs_plan* plan, double* out, size_t cap_records, size_t* n_records);
 
+/* One step of the hot path as a HIP graph: every copy in [copy_begin,
+ * copy_end) of both halves (qs_run_halves on the registered bitstrings) and
+ * the assembly with its FP64 sums (qs_amplitudes_device), launched as one
+ * graph on hip_stream.  The batching of Sec. 2.3.1 (many copies, many layer
+ * passes) then costs one launch per step.  The first call, and any call whose
+ * arguments or stream differ from the captured ones, runs one eager step
+ * (planning and filling the plan's buffer pool), captures the next step and
+ * launches it; later calls only launch the graph (asynchronous).  The graph
+ * is captured again after the plan released device memory (a new bitstring
+ * set, a full buffer pool).  Results are those of the eager calls, bit for
+ * bit.  Needs registered bitstrings (QS_ERR_STATE otherwise: call
+ * qs_run_halves with them once); d_out_c64 / d_out_sums as in
+ * qs_amplitudes_device (device memory, 2m floats / 2 doubles or NULL).
+ * hip_stream must not be the null stream (it cannot be captured).  Timing
+ * events are not recorded inside the graph.  Errors: QS_ERR_ARG, QS_ERR_STATE,
+ * QS_ERR_OOM, QS_ERR_HIP (capture or instantiation failed). */
+qs_status qs_run_graph(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end, qs_precision prec,
+                       float* d_out_c64, double* d_out_sums, void* hip_stream);
+
 /* ---------------------------------------------------------------- chain partitions
  *
  * Partitions into t parts (Sec. 3, Fig. 3): part_masks[0..t-1] are disjoint,

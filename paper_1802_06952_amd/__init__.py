@@ -29,7 +29,7 @@ _STATUS = {0: "QS_OK", -1: "QS_ERR_ARG", -2: "QS_ERR_PARSE", -3: "QS_ERR_UNSUPPO
 
 EXPORTED = ("qs_last_error", "qs_load_circuit", "qs_circuit_info", "qs_circuit_free",
             "qs_partition", "qs_plan_info", "qs_plan_dump", "qs_plan_free", "qs_run_halves",
-            "qs_amplitudes", "qs_amplitudes_device", "qs_amplitudes_device_static",
+            "qs_amplitudes", "qs_amplitudes_device", "qs_amplitudes_device_static", "qs_run_graph",
             "qs_half_amplitudes", "qs_plan_reset",
             "qs_get_timing", "qs_set_timing", "qs_get_pass_timing", "qs_score_cut", "qs_choose_cut",
             "qs_partition_chain", "qs_chain_info", "qs_chain_register", "qs_chain_amplitudes_device",
@@ -139,6 +139,7 @@ def _load() -> C.CDLL:
                                   C.POINTER(C.c_double), vp]
     lib.qs_amplitudes_device.argtypes = [vp, C.c_int, vp, vp, vp]
     lib.qs_amplitudes_device_static.argtypes = [vp, C.c_int, vp, vp, vp]
+    lib.qs_run_graph.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_int, vp, vp, vp]
     lib.qs_half_amplitudes.argtypes = [vp, C.c_int, C.c_uint64, C.c_uint64, C.POINTER(C.c_float),
                                        C.c_size_t, C.POINTER(C.c_size_t), vp]
     lib.qs_plan_reset.argtypes = [vp, C.c_int]
@@ -294,6 +295,12 @@ def qs_amplitudes_device_static(plan, prec: int, d_out_ptr: int, d_sums_ptr: int
     _check(_lib.qs_amplitudes_device_static(plan, prec, C.c_void_p(d_out_ptr),
                                             C.c_void_p(d_sums_ptr) if d_sums_ptr else None,
                                             _stream_handle(stream)))
+
+
+def qs_run_graph(plan, copy_begin: int, copy_end: int, prec: int, d_out_ptr: int,
+                 d_sums_ptr: int | None = None, stream=None) -> None:
+    _check(_lib.qs_run_graph(plan, copy_begin, copy_end, prec, C.c_void_p(d_out_ptr),
+                             C.c_void_p(d_sums_ptr) if d_sums_ptr else None, _stream_handle(stream)))
 
 
 def qs_half_amplitudes(plan, side: int, copy_begin: int, copy_end: int, n_values: int,
@@ -477,6 +484,10 @@ class Plan:
     def amplitudes_device_static(self, prec: int, d_out_ptr: int, d_sums_ptr: int | None = None,
                                  stream=None) -> None:
         qs_amplitudes_device_static(self._plan, prec, d_out_ptr, d_sums_ptr, stream)
+
+    def run_graph(self, copy_begin: int, copy_end: int, prec: int, d_out_ptr: int,
+                  d_sums_ptr: int | None = None, stream=None) -> None:
+        qs_run_graph(self._plan, copy_begin, copy_end, prec, d_out_ptr, d_sums_ptr, stream)
 
     def half_amplitudes(self, side: int, copy_begin: int, copy_end: int, n_values: int,
                         stream=None) -> np.ndarray:

@@ -63,6 +63,7 @@ struct Pool {
   std::vector<Ent> ents;
   size_t held = 0;
   DevAlloc* da = nullptr;
+  uint64_t frees = 0;  // counts trims (buffers handed back to the allocator)
   void* get(size_t bytes, void* stream) {
     if (bytes == 0) bytes = 256;
     Ent* best = nullptr;
@@ -109,6 +110,7 @@ struct Pool {
   void trim() {
     // idle buffers may still be read by queued kernels
     (void)hipDeviceSynchronize();
+    ++frees;
     std::vector<Ent> keep;
     for (Ent& e : ents) {
       if (e.used) keep.push_back(e);
@@ -236,6 +238,23 @@ struct qs_plan {
   // the lower half runs on aux, forked from and joined into the caller's stream
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // qs_run_graph: one captured step and what it was captured for; mem_gen
+  // counts every release of device memory the plan holds, so a graph whose
+  // buffers may have gone is captured again
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  uint64_t graph_k0 = 0, graph_k1 = 0, graph_gen = 0;
+  int graph_prec = -1;
+  void* graph_out = nullptr;
+  void* graph_sums = nullptr;
+  uint64_t mem_gen = 0;
+  uint64_t gen() const { return mem_gen + pool.frees; }
+  void drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+  }
   int timing = 0;  // 1: per kernel family; 2: also every full-state pass on its own
   std::vector<EvRec> events;
   struct PassRec {
@@ -252,6 +271,7 @@ struct qs_plan {
   qs_plan() { pool.da = &dalloc; }
   // cached block plans and their copy tables; the caller synchronises first
   void drop_block_plans() {
+    ++mem_gen;
     cache.clear();
     for (auto& kv : perms) {
       dalloc.put(kv.second.d_perm);
@@ -261,6 +281,7 @@ struct qs_plan {
   }
   ~qs_plan() {
     (void)hipDeviceSynchronize();
+    drop_graph();
     for (EvRec& e : events) {
       (void)hipEventDestroy(e.a);
       (void)hipEventDestroy(e.b);
@@ -777,6 +798,7 @@ qs_status register_bits(qs_plan* P, const uint64_t* bits, size_t m) {
       P->d_vals[k] = nullptr;
       P->d_idx[k] = nullptr;
     }
+    ++P->mem_gen;  // a captured step read the old tables
     P->stale = false;
   }
   for (size_t t = 0; t < m; ++t)
@@ -1394,6 +1416,13 @@ qs_status qs_amplitudes(qs_plan* plan, const uint64_t* bitstrings, size_t m, qs_
   return QS_OK;
 }
 
+static qs_status assemble_on(qs_plan* plan, qs_precision prec, float* d_out_c64,
+                             double* d_out_sums, hipStream_t st) {
+  if (!plan->registered || plan->blocks.empty()) return fail(QS_ERR_STATE, "no copies run");
+  Scratch sc{plan, st};
+  return assemble(plan, prec, (float2*)d_out_c64, d_out_sums, sc);
+}
+
 qs_status qs_amplitudes_device(qs_plan* plan, qs_precision prec, float* d_out_c64,
                                double* d_out_sums, void* hip_stream) {
   if (!plan || !d_out_c64) return fail(QS_ERR_ARG, "null pointer");
@@ -1428,6 +1457,75 @@ qs_status qs_amplitudes_device_static(qs_plan* plan, qs_precision prec, float* d
   s = assemble(plan, prec, (float2*)d_out_c64, d_out_sums, sc);
   plan->timing = timing;
   return s;
+}
+
+qs_status qs_run_graph(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end, qs_precision prec,
+                       float* d_out_c64, double* d_out_sums, void* hip_stream) {
+  if (!plan || !d_out_c64) return fail(QS_ERR_ARG, "null pointer");
+  if (prec != QS_PREC_FP32 && prec != QS_PREC_SPLIT_BF16) return fail(QS_ERR_ARG, "unknown precision");
+  const uint64_t total = 1ULL << plan->cuts.size();
+  if (copy_begin >= copy_end || copy_end > total) return fail(QS_ERR_ARG, "copy range outside [0, 2^c)");
+  if (!plan->registered) return fail(QS_ERR_STATE, "no bitstrings registered");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (!st) return fail(QS_ERR_ARG, "a graph is captured on a stream other than the null stream");
+  auto step = [&]() -> qs_status {
+    qs_status s = qs_plan_reset(plan, 1);
+    if (s == QS_OK) s = qs_run_halves(plan, copy_begin, copy_end, nullptr, 0, hip_stream);
+    if (s == QS_OK) s = assemble_on(plan, prec, d_out_c64, d_out_sums, st);
+    return s;
+  };
+  const bool same = plan->graph_exec && plan->graph_k0 == copy_begin &&
+                    plan->graph_k1 == copy_end && plan->graph_prec == (int)prec &&
+                    plan->graph_out == (void*)d_out_c64 && plan->graph_sums == (void*)d_out_sums &&
+                    plan->graph_gen == plan->gen() && plan->last_st == st;
+  if (same) {
+    HIPCHECK(hipGraphLaunch(plan->graph_exec, st));
+    return QS_OK;
+  }
+  plan->drop_graph();
+  // an eager step first: it plans and uploads whatever is not cached yet and
+  // leaves in the plan's pool every buffer a step takes, so that the captured
+  // step below makes no allocation, no copy from the host and no
+  // synchronisation
+  const int timing = plan->timing;
+  plan->timing = 0;  // no events inside the graph
+  qs_status s = step();
+  if (s != QS_OK) {
+    plan->timing = timing;
+    return s;
+  }
+  const uint64_t g0 = plan->gen();
+  HIPCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  s = step();
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(st, &g);
+  plan->timing = timing;
+  if (s != QS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (ec != hipSuccess) return fail(QS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+  if (plan->gen() != g0) {
+    // the captured step released memory (it had to make room): not replayable
+    (void)hipGraphDestroy(g);
+    return fail(QS_ERR_OOM, "the step does not fit the device without releasing buffers");
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(QS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  }
+  plan->graph = g;
+  plan->graph_exec = ex;
+  plan->graph_k0 = copy_begin;
+  plan->graph_k1 = copy_end;
+  plan->graph_prec = (int)prec;
+  plan->graph_out = d_out_c64;
+  plan->graph_sums = d_out_sums;
+  plan->graph_gen = g0;
+  HIPCHECK(hipGraphLaunch(ex, st));
+  return QS_OK;
 }
 
 qs_status qs_half_amplitudes(qs_plan* plan, int side, uint64_t copy_begin, uint64_t copy_end,

@@ -6,6 +6,8 @@ rocprofv3 writes one SQLite database per run.  Two summaries are made here:
   ``--kernel-trace --stats`` run, plus each kernel's register and LDS use;
 * ``sq``: per-kernel MFMA utilisation and instruction counts from one ``--pmc``
   run of SQ and GRBM counters;
+* ``launches``: one step dispatch by dispatch, durations from a trace run and
+  instruction counts from a ``--pmc`` run of the same command;
 * ``counters``: HBM bytes per dispatch of one kernel family from two ``--pmc``
   runs (``FETCH_SIZE``, then ``WRITE_SIZE``, both in KiB per dispatch).  Each
   counter is divided by what it reads for a plain copy of known size made in
@@ -112,11 +114,12 @@ def counter_summary(fetch_dir: str, write_dir: str, kernel: str, calib_bytes: in
             "kernels_hip_sha256_16": kernel_source_hash()}
 
 
-def sq_summary(d: str, cmd: str, simds: int = 1024) -> str:
+def sq_summary(d: str, cmd: str, simds: int = 1024, xcds: int = 8) -> str:
     """Per-kernel averages of SQ/GRBM counters from one --pmc run: MFMA busy
-    cycles against GRBM_GUI_ACTIVE times the SIMD count (MFMA utilisation),
-    MFMA flops (each MOPS unit is 512 flops), and the VALU, SALU and LDS
-    instruction counts per dispatch."""
+    cycles against the dispatch's GPU cycles times the SIMD count (MFMA
+    utilisation; GRBM_GUI_ACTIVE comes summed over the XCDs, each with its own
+    GRBM), MFMA flops (each MOPS unit is 512 flops), and the VALU, SALU and
+    LDS instruction counts per dispatch."""
     vals, names = _pmc(d)
     per = collections.defaultdict(list)
     for disp, cs in vals.items():
@@ -126,19 +129,66 @@ def sq_summary(d: str, cmd: str, simds: int = 1024) -> str:
             "SQ_WAVES"]
     out = [f"Command: `{cmd}`", "",
            "rocprofv3 `--pmc` counters, averaged over the dispatches of each kernel. MFMA "
-           f"utilisation = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x {simds} SIMDs); MFMA "
-           "GFLOP = (MOPS_F32 + MOPS_BF16) x 512 / 1e9.", "",
+           f"utilisation = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / {xcds} XCDs x {simds} "
+           "SIMDs); MFMA GFLOP = (MOPS_F32 + MOPS_BF16) x 512 / 1e9.", "",
            "| kernel | dispatches | MFMA util | MFMA GFLOP (F32) | MFMA GFLOP (BF16) | VALU insts | "
            "SALU insts | LDS insts | waves |", "|---|---|---|---|---|---|---|---|---|"]
     for n in sorted(per, key=lambda k: -sum(x.get("GRBM_GUI_ACTIVE", 0) for x in per[k])):
         rows = per[n]
         avg = {c: sum(r.get(c, 0.0) for r in rows) / len(rows) for c in cols}
-        util = avg["SQ_VALU_MFMA_BUSY_CYCLES"] / max(1.0, avg["GRBM_GUI_ACTIVE"] * simds)
+        util = avg["SQ_VALU_MFMA_BUSY_CYCLES"] / max(1.0, avg["GRBM_GUI_ACTIVE"] / xcds * simds)
         out.append(f"| `{n}` | {len(rows)} | {100 * util:.1f} % | "
                    f"{avg['SQ_INSTS_VALU_MFMA_MOPS_F32'] * 512 / 1e9:.2f} | "
                    f"{avg['SQ_INSTS_VALU_MFMA_MOPS_BF16'] * 512 / 1e9:.2f} | "
                    f"{avg['SQ_INSTS_VALU']:.3g} | {avg['SQ_INSTS_SALU']:.3g} | "
                    f"{avg['SQ_INSTS_LDS']:.3g} | {avg['SQ_WAVES']:.0f} |")
+    out.append("")
+    out.append(f"kernels.hip sha256[:16] = {kernel_source_hash()}")
+    return "\n".join(out) + "\n"
+
+
+def _dispatches(d: str):
+    """(name, microseconds) of every dispatch of a --kernel-trace run, in start order."""
+    con = _db(d)
+    return [(short_name(n), (e - b) / 1e3)
+            for n, b, e in con.execute("select name, start, end from kernels order by start")]
+
+
+def _last_step(seq, name_of):
+    """The dispatches of the last complete step with inputs already on the
+    device: a step ends with k_prob_final, and of all steps the ones with the
+    fewest copies are those (a step that uploads bitstrings copies more)."""
+    idx = [i for i, x in enumerate(seq) if "k_prob_final" in name_of(x)]
+    steps = [seq[a + 1: b + 1] for a, b in zip(idx, idx[1:])]
+    if not steps:
+        raise SystemExit("fewer than two steps in the run")
+    copies = [sum("copyBuffer" in name_of(x) for x in st) for st in steps]
+    return [st for st, c in zip(steps, copies) if c == min(copies)][-1]
+
+
+def launch_table(trace_dir: str, pmc_dir: str, cmd: str, clock_ghz: float = 2.4,
+                 simds: int = 1024) -> str:
+    """Every dispatch of one step: duration (from the trace run) and VALU, SALU
+    and LDS instruction counts (from the --pmc run of the same command).  The
+    VALU column is the share of the chip's VALU issue rate the dispatch used:
+    one wave64 instruction per SIMD every 4 cycles."""
+    vals, names = _pmc(pmc_dir)
+    P = _last_step([(names[k], vals[k]) for k in sorted(vals)], lambda x: x[0])
+    T = _last_step(_dispatches(trace_dir), lambda x: x[0])
+    if len(P) != len(T) or any(a[0] != b[0] for a, b in zip(P, T)):
+        raise SystemExit("the two runs dispatched different kernels")
+    out = [f"Command: `{cmd}`", "",
+           "One step, dispatch by dispatch: duration from the `--kernel-trace` run; instruction "
+           "counts from the `--pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS ...` run of the same "
+           f"command. VALU % = SQ_INSTS_VALU x 4 cycles / ({simds} SIMDs x duration x "
+           f"{clock_ghz} GHz).", "",
+           "| # | kernel | us | VALU insts | VALU % | SALU insts | LDS insts |",
+           "|---|---|---|---|---|---|---|"]
+    for i, ((n, c), (_, us)) in enumerate(zip(P, T)):
+        valu = c.get("SQ_INSTS_VALU", 0.0)
+        frac = valu * 4 / simds / (us * 1e-6 * clock_ghz * 1e9) if us > 0 else 0.0
+        out.append(f"| {i} | `{n}` | {us:.2f} | {valu:.3g} | {100 * frac:.1f} | "
+                   f"{c.get('SQ_INSTS_SALU', 0.0):.3g} | {c.get('SQ_INSTS_LDS', 0.0):.3g} |")
     out.append("")
     out.append(f"kernels.hip sha256[:16] = {kernel_source_hash()}")
     return "\n".join(out) + "\n"
@@ -160,11 +210,17 @@ def main(argv=None):
     q = sub.add_parser("sq")
     q.add_argument("dir")
     q.add_argument("--cmd", required=True)
+    lt = sub.add_parser("launches")
+    lt.add_argument("trace_dir")
+    lt.add_argument("pmc_dir")
+    lt.add_argument("--cmd", required=True)
     a = ap.parse_args(argv)
     if a.what == "trace":
         sys.stdout.write(trace_summary(a.dir, a.cmd))
     elif a.what == "sq":
         sys.stdout.write(sq_summary(a.dir, a.cmd))
+    elif a.what == "launches":
+        sys.stdout.write(launch_table(a.trace_dir, a.pmc_dir, a.cmd))
     else:
         d = counter_summary(a.fetch_dir, a.write_dir, a.kernel, a.calib_bytes)
         d["workload"] = a.workload

@@ -1370,49 +1370,81 @@ __global__ void k_zgemm_reduce(int M, int N, int splits, const float2* __restric
 // Split-BF16: each FP32 value a is split as hi = bf16(a) (round to nearest
 // even) and lo = bf16(a - hi); a product a*b is taken as
 // hi_a hi_b + hi_a lo_b + lo_a hi_b (the dropped lo_a lo_b is below 2^-16
-// relative), accumulated in FP32 on v_mfma_f32_16x16x32_bf16.  The split
-// operands are staged as four planes (re hi, re lo, im hi, im lo), each
-// row-major over the M (or N) index with the copy index contiguous, so that a
-// lane's eight consecutive k values are one 16-byte read.
+// relative), accumulated in FP32 on v_mfma_f32_16x16x32_bf16.  The operands
+// are read as FP32 complex values (both with the copy index contiguous, as for
+// the FP32 product) and split while they are staged: LDS holds four planes
+// (re hi, re lo, im hi, im lo), each row-major over the M (or N) index with
+// the copy index contiguous, so that a lane's eight consecutive k values are
+// one 16-byte read.
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBK = 32;
 
-__global__ void k_split_bf16(const float2* __restrict__ src, int ld, int K, int rows, int Kp,
-                             int rows_pad, __hip_bfloat16* __restrict__ dst) {
-  // src[row * ld + k]; dst[p][row][k], p = re_hi, re_lo, im_hi, im_lo; zero padding
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t plane = (size_t)rows_pad * Kp;
-  if (idx >= plane) return;
-  const int row = (int)(idx / Kp), k = (int)(idx % Kp);
-  const float2 v = (k < K && row < rows) ? src[(size_t)row * ld + k] : make_float2(0.f, 0.f);
-  const __hip_bfloat16 rh = __float2bfloat16(v.x);
-  const __hip_bfloat16 rl = __float2bfloat16(v.x - __bfloat162float(rh));
-  const __hip_bfloat16 ih = __float2bfloat16(v.y);
-  const __hip_bfloat16 il = __float2bfloat16(v.y - __bfloat162float(ih));
-  dst[idx] = rh;
-  dst[plane + idx] = rl;
-  dst[2 * plane + idx] = ih;
-  dst[3 * plane + idx] = il;
-}
-
 __device__ __forceinline__ bf16x8 bf_neg(bf16x8 v) {
-  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
   u32x4 u = __builtin_bit_cast(u32x4, v);
   u ^= 0x80008000u;
   return __builtin_bit_cast(bf16x8, u);
 }
 
-// Grouped form (goff != nullptr): blockIdx.z = group * nsplit + split; group g
-// takes the columns goff[g] .. goff[g+1]-1 (B rows, and the columns of the
-// partial product) and A rows g * a_grows .. (its M rows); blockIdx.x counts
-// the group's column tiles.  Plain form: blockIdx.z is the split.
+// hi and lo bf16 halves of two FP32 values, packed (element 0 in the low half);
+// conversions round to nearest even.
+__device__ __forceinline__ void split2(float a, float b, uint32_t& hi, uint32_t& lo) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  const f32x2 x = {a, b};
+  const bf16x2 h = __builtin_convertvector(x, bf16x2);
+  const bf16x2 l = __builtin_convertvector(x - __builtin_convertvector(h, f32x2), bf16x2);
+  hi = __builtin_bit_cast(uint32_t, h);
+  lo = __builtin_bit_cast(uint32_t, l);
+}
+
+// Eight consecutive complex values of one operand row (k .. k+7), split into
+// the four planes of that row in LDS; values past the operand (row >= rows or
+// k >= K) are zero.
+__device__ __forceinline__ void stage_split8(const float2* __restrict__ src, size_t ld, int row,
+                                             int rows, int k, int K,
+                                             __hip_bfloat16 (*plane)[kGBM][kBK + 8], int lrow,
+                                             int lk) {
+  float4 v[4];
+  const float2* r = src + (size_t)row * ld;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int kk = k + 2 * i;
+    const float2 a = (row < rows && kk < K) ? r[kk] : make_float2(0.f, 0.f);
+    const float2 b = (row < rows && kk + 1 < K) ? r[kk + 1] : make_float2(0.f, 0.f);
+    v[i] = make_float4(a.x, a.y, b.x, b.y);
+  }
+  u32x4 rh, rl, ih, il;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    uint32_t h, l;
+    split2(v[i].x, v[i].z, h, l);
+    rh[i] = h;
+    rl[i] = l;
+    split2(v[i].y, v[i].w, h, l);
+    ih[i] = h;
+    il[i] = l;
+  }
+  *(u32x4*)(&plane[0][lrow][lk]) = rh;
+  *(u32x4*)(&plane[1][lrow][lk]) = rl;
+  *(u32x4*)(&plane[2][lrow][lk]) = ih;
+  *(u32x4*)(&plane[3][lrow][lk]) = il;
+}
+
+// C (M x N) = A B^T over the copy index, split-BF16: A[(a_row0 + i) * lda + k],
+// B[j * ldb + k], both FP32 complex.  Tiles of 128 x 128 (four waves of
+// 64 x 64), k in steps of kBK, the copy index split over blockIdx.z as for the
+// FP32 product (partials reduced by k_zgemm_reduce).  Grouped form (goff !=
+// nullptr): blockIdx.z = group * nsplit + split; group g takes the columns
+// goff[g] .. goff[g+1]-1 (B rows, and the columns of the partial product) and
+// A rows g * a_grows .. (its M rows); blockIdx.x counts the group's column
+// tiles.  Plain form: blockIdx.z is the split.
 __global__ void __launch_bounds__(kGemmThreads)
-k_zgemm_tn_bf16x3(int M, int N, int Kp, int kper, const __hip_bfloat16* __restrict__ Ap,
-                  int Mp, const __hip_bfloat16* __restrict__ Bp, int Np, float2* __restrict__ out,
-                  int ldo, size_t split_stride, const int* __restrict__ goff, int nsplit,
-                  int a_grows) {
+k_zgemm_nt_bf16x3(int M, int N, int K, int kper, const float2* __restrict__ A, int lda,
+                  const float2* __restrict__ B, int ldb, float2* __restrict__ out, int ldo,
+                  size_t split_stride, const int* __restrict__ goff, int nsplit, int a_grows) {
   // LDS: [plane][row][k] with rows of kBK bf16 (64 bytes) plus 16 bytes of padding
   constexpr int RS = kBK + 8;
   __shared__ __attribute__((aligned(16))) __hip_bfloat16 As[4][kGBM][RS];
@@ -1431,8 +1463,8 @@ k_zgemm_tn_bf16x3(int M, int N, int Kp, int kper, const __hip_bfloat16* __restri
   const int i_blk = blockIdx.y * kGBM;
   const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
   const int kb = split * kper;
-  const int ke = min(Kp, kb + kper);
-  const size_t pa = (size_t)Mp * Kp, pb = (size_t)Np * Kp;
+  const int ke = min(K, kb + kper);
+  const float2* Ag = A + (size_t)a_row0 * lda;
   floatx4 ar[4][4], ai[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -1441,17 +1473,14 @@ k_zgemm_tn_bf16x3(int M, int N, int Kp, int kper, const __hip_bfloat16* __restri
       ar[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
       ai[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
   for (int k0 = kb; k0 < ke; k0 += kBK) {
-    // stage: 4 planes x 128 rows x 64 bytes per operand = 2048 16-byte chunks; 8 per thread
+    // stage: 128 rows x 4 runs of 8 k per operand = 512 runs; 2 per thread
 #pragma unroll
-    for (int x = 0; x < 8; ++x) {
-      const int c = tid + x * kGemmThreads;  // 0..2047
-      const int p = c >> 9, row = (c >> 2) & 127, q = c & 3;
-      const u32x4 va = *(const u32x4*)(Ap + p * pa + (size_t)(a_row0 + i_blk + row) * Kp + k0 + q * 8);
-      const u32x4 vb = *(const u32x4*)(Bp + p * pb + (size_t)(j_blk + row) * Kp + k0 + q * 8);
-      *(u32x4*)(&As[p][row][q * 8]) = va;
-      *(u32x4*)(&Bs[p][row][q * 8]) = vb;
+    for (int x = 0; x < 2; ++x) {
+      const int c = tid + x * kGemmThreads;  // 0..511
+      const int row = c >> 2, q = c & 3;
+      stage_split8(Ag, (size_t)lda, i_blk + row, M, k0 + q * 8, ke, As, row, q * 8);
+      stage_split8(B, (size_t)ldb, j_blk + row, jend, k0 + q * 8, ke, Bs, row, q * 8);
     }
     __syncthreads();
     bf16x8 fa[4][4];  // [a tile][plane]
@@ -1528,10 +1557,7 @@ size_t zgemm_workspace_bytes(int prec, int M, int N, int K) {
   const int kstep = prec == 0 ? kFK : kBK;
   const int Kp = prec == 0 ? K : round_up(K, kBK);
   const GemmShape g = gemm_shape(prec, M, N, Kp, kstep);
-  size_t b = (size_t)g.splits * M * N * sizeof(float2);
-  if (prec != 0)
-    b += 4 * (size_t)Kp * (round_up(M, kGBM) + round_up(N, kGBN)) * sizeof(__hip_bfloat16) + 256;
-  return b;
+  return (size_t)g.splits * M * N * sizeof(float2);
 }
 
 hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int lda,
@@ -1548,18 +1574,8 @@ hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int l
     hipLaunchKernelGGL((k_zgemm_nt_f32<4, kF32TN>), grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper,
                        A, lda, B, ldb, P, N, ss, (const int*)nullptr, 1, (size_t)0);
   } else {
-    const int Mp = round_up(M, kGBM), Np = round_up(N, kGBN);
-    char* base = (char*)work + (size_t)g.splits * ss * sizeof(float2);
-    base = (char*)(((uintptr_t)base + 255) & ~(uintptr_t)255);
-    __hip_bfloat16* Ap = (__hip_bfloat16*)base;
-    __hip_bfloat16* Bp = Ap + 4 * (size_t)Mp * Kp;
-    const size_t ta = (size_t)Mp * Kp, tb = (size_t)Np * Kp;
-    hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((ta + 255) / 256)), dim3(256), 0, st, A, lda,
-                       K, M, Kp, Mp, Ap);
-    hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, st, B, ldb,
-                       K, N, Kp, Np, Bp);
-    hipLaunchKernelGGL(k_zgemm_tn_bf16x3, grid, dim3(kGemmThreads), 0, st, M, N, Kp, g.kper, Ap,
-                       Mp, Bp, Np, P, N, ss, (const int*)nullptr, g.splits, 0);
+    hipLaunchKernelGGL(k_zgemm_nt_bf16x3, grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper, A, lda,
+                       B, ldb, P, N, ss, (const int*)nullptr, g.splits, 0);
   }
   const size_t tot = ss;
   hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, N,
@@ -1612,34 +1628,30 @@ hipError_t launch_zgemm_grouped(int M, int Ntot, int maxn, int K, int ngroups, c
   return hipGetLastError();
 }
 
-// Grouped split-BF16 product: as launch_zgemm_grouped, with both operands split
-// once for all groups (A as ngroups * M rows) and one launch of
-// k_zgemm_tn_bf16x3 over every group's column tiles.
+// Grouped split-BF16 product: as launch_zgemm_grouped, one launch of
+// k_zgemm_nt_bf16x3 over every group's column tiles (A holds ngroups * M rows
+// of K, group g's M rows at row g * M; B Ntot rows of K).
 struct GroupedBf16Shape {
-  int Kp, tpg, mt, splits, kper;
-  size_t rows_a, rows_b;  // split-plane rows, with the padding the tiles read
+  int tpg, mt, splits, kper;
 };
 
-GroupedBf16Shape grouped_bf16_shape(int M, int Ntot, int maxn, int K, int ngroups) {
+GroupedBf16Shape grouped_bf16_shape(int M, int maxn, int K, int ngroups) {
   GroupedBf16Shape g;
-  g.Kp = round_up(K, kBK);
+  const int Kp = round_up(K, kBK);
   g.tpg = (maxn + kGBN - 1) / kGBN;
   g.mt = (M + kGBM - 1) / kGBM;
   const int tiles = std::max(1, g.tpg * g.mt * ngroups);
   const int want = std::max(1, 256 / tiles);  // longer k loops, fewer partials
-  const int maxsplit = std::max(1, g.Kp / (4 * kBK));
+  const int maxsplit = std::max(1, Kp / (4 * kBK));
   g.splits = std::max(1, std::min({want, maxsplit, 64}));
-  g.kper = round_up((g.Kp + g.splits - 1) / g.splits, kBK);
-  g.splits = (g.Kp + g.kper - 1) / g.kper;
-  g.rows_a = (size_t)ngroups * M + kGBM;
-  g.rows_b = (size_t)round_up(Ntot, kGBN) + (size_t)g.tpg * kGBN;
+  g.kper = round_up((Kp + g.splits - 1) / g.splits, kBK);
+  g.splits = (Kp + g.kper - 1) / g.kper;
   return g;
 }
 
 size_t zgemm_grouped_bf16_workspace_bytes(int M, int Ntot, int maxn, int K, int ngroups) {
-  const GroupedBf16Shape g = grouped_bf16_shape(M, Ntot, maxn, K, ngroups);
-  return (size_t)g.splits * M * Ntot * sizeof(float2) +
-         4 * (size_t)g.Kp * (g.rows_a + g.rows_b) * sizeof(__hip_bfloat16) + 256;
+  const GroupedBf16Shape g = grouped_bf16_shape(M, maxn, K, ngroups);
+  return (size_t)g.splits * M * Ntot * sizeof(float2);
 }
 
 hipError_t launch_zgemm_grouped_bf16(int M, int Ntot, int maxn, int K, int ngroups,
@@ -1647,22 +1659,13 @@ hipError_t launch_zgemm_grouped_bf16(int M, int Ntot, int maxn, int K, int ngrou
                                      float2* C, int ldc, int accumulate, void* work,
                                      hipStream_t st, const uint32_t* cmap) {
   if (M <= 0 || Ntot <= 0 || K <= 0 || ngroups <= 0 || maxn <= 0) return hipErrorInvalidValue;
-  const GroupedBf16Shape g = grouped_bf16_shape(M, Ntot, maxn, K, ngroups);
+  const GroupedBf16Shape g = grouped_bf16_shape(M, maxn, K, ngroups);
   if ((size_t)ngroups * g.splits > 65535) return hipErrorInvalidValue;
   const size_t ss = (size_t)M * Ntot;
   float2* P = (float2*)work;
-  char* base = (char*)work + (size_t)g.splits * ss * sizeof(float2);
-  base = (char*)(((uintptr_t)base + 255) & ~(uintptr_t)255);
-  __hip_bfloat16* Ap = (__hip_bfloat16*)base;
-  __hip_bfloat16* Bp = Ap + 4 * g.rows_a * g.Kp;
-  const size_t ta = g.rows_a * g.Kp, tb = g.rows_b * g.Kp;
-  hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((ta + 255) / 256)), dim3(256), 0, st, A, K, K,
-                     ngroups * M, g.Kp, (int)g.rows_a, Ap);
-  hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, st, B, K, K,
-                     Ntot, g.Kp, (int)g.rows_b, Bp);
   dim3 grid(g.tpg, g.mt, ngroups * g.splits);
-  hipLaunchKernelGGL(k_zgemm_tn_bf16x3, grid, dim3(kGemmThreads), 0, st, M, Ntot, g.Kp, g.kper,
-                     Ap, (int)g.rows_a, Bp, (int)g.rows_b, P, Ntot, ss, d_goff, g.splits, M);
+  hipLaunchKernelGGL(k_zgemm_nt_bf16x3, grid, dim3(kGemmThreads), 0, st, M, Ntot, K, g.kper, A, K,
+                     B, K, P, Ntot, ss, d_goff, g.splits, M);
   hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((ss + 255) / 256)), dim3(256), 0, st, M, Ntot,
                      g.splits, P, ss, C, ldc, accumulate, cmap);
   return hipGetLastError();

@@ -1400,6 +1400,168 @@ __device__ __forceinline__ void split2(float a, float b, uint32_t& hi, uint32_t&
   lo = __builtin_bit_cast(uint32_t, l);
 }
 
+// Staged operand tiles: 128 rows of kBK complex FP32 values (256 bytes per
+// row, 32 KB per tile), written by direct global-to-LDS loads.  Inside a row
+// the 16-byte chunks (two complex values each) are stored at position
+// chunk ^ (row & 15), so that the sixteen rows a fragment read touches fall
+// on sixteen different bank groups.
+constexpr int kRowBytes = kBK * 8;
+constexpr int kTileBytes = kGBM * kRowBytes;
+
+__device__ __forceinline__ int chunk_pos(int row, int chunk) { return chunk ^ (row & 15); }
+
+// One operand tile, rows row0 .. row0 + 127 of src (row length K), copy
+// indices k0 .. k0 + kBK - 1.  Wave w loads tile rows 32 w .. 32 w + 31, four
+// rows per instruction (64 lanes x 16 bytes: lane l covers row 4 j + l / 16 at
+// position l % 16).  Rows past `rows` read the last row and chunks past K the
+// row's first chunk (valid addresses; the first give outputs that are not
+// stored, the second are zeroed when the fragments are read).
+__device__ __forceinline__ void stage_tile(const float2* __restrict__ src, size_t ld, int row0,
+                                           int rows, int k0, int K, char* tile, int wave,
+                                           int lane) {
+  const int pos = lane & 15;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int r = 32 * wave + 4 * j + (lane >> 4);
+    const int gr = min(row0 + r, rows - 1);
+    const int c = pos ^ (r & 15);
+    const int k = k0 + 2 * c + 1 < K ? k0 + 2 * c : 0;
+    const float2* g = src + (size_t)gr * ld + k;
+    char* l = tile + (32 * wave + 4 * j) * kRowBytes;
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)l, 16, 0, 0);
+  }
+}
+
+// The four bf16 planes (re hi, re lo, im hi, im lo) of one MFMA fragment: row
+// `row` of a staged tile, copy indices 8 g .. 8 g + 7; indices at or past kvalid
+// are zero.
+__device__ __forceinline__ void frag_planes(const char* tile, int row, int g, int kvalid,
+                                            bf16x8 (&pl)[4]) {
+  float4 v[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    v[j] = *(const float4*)(tile + row * kRowBytes + 16 * chunk_pos(row, 4 * g + j));
+  if (kvalid < kBK) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = 8 * g + 2 * j;
+      if (k >= kvalid) v[j].x = v[j].y = 0.f;
+      if (k + 1 >= kvalid) v[j].z = v[j].w = 0.f;
+    }
+  }
+  u32x4 rh, rl, ih, il;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint32_t h, l;
+    split2(v[j].x, v[j].z, h, l);
+    rh[j] = h;
+    rl[j] = l;
+    split2(v[j].y, v[j].w, h, l);
+    ih[j] = h;
+    il[j] = l;
+  }
+  pl[0] = __builtin_bit_cast(bf16x8, rh);
+  pl[1] = __builtin_bit_cast(bf16x8, rl);
+  pl[2] = __builtin_bit_cast(bf16x8, ih);
+  pl[3] = __builtin_bit_cast(bf16x8, il);
+}
+
+// C (M x N) = A B^T over the copy index, split-BF16: A[(a_row0 + i) * lda + k],
+// B[j * ldb + k], both FP32 complex.  Tiles of 128 x 128 (four waves of
+// 64 x 64), k in steps of kBK, the copy index split over blockIdx.z as for the
+// FP32 product (partials reduced by k_zgemm_reduce).  The next step's tiles
+// load into the second LDS buffer while the MFMAs consume the current one.
+// Grouped form (goff != nullptr): blockIdx.z = group * nsplit + split; group
+// g takes the columns goff[g] .. goff[g+1]-1 (B rows, and the columns of the
+// partial product) and A rows g * a_grows .. (its M rows); blockIdx.x counts
+// the group's column tiles.  Plain form: blockIdx.z is the split.
+__global__ void __launch_bounds__(kGemmThreads)
+k_zgemm_nt_bf16x3(int M, int N, int K, int kper, const float2* __restrict__ A, int lda,
+                  const float2* __restrict__ B, int ldb, float2* __restrict__ out, int ldo,
+                  size_t split_stride, const int* __restrict__ goff, int nsplit, int a_grows) {
+  __shared__ __attribute__((aligned(16))) char tiles[2][2][kTileBytes];  // [buffer][A, B]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  int bx, by, bz;
+  gemm_block(bx, by, bz);  // an XCD runs whole splits: their operand tiles share its L2
+  int split = bz, j_blk = bx * kGBN, jend = N, a_row0 = 0;
+  if (goff) {
+    const int g = bz / nsplit;
+    split = bz - g * nsplit;
+    j_blk = goff[g] + bx * kGBN;
+    jend = goff[g + 1];
+    if (j_blk >= jend) return;  // the whole tile lies past the group (uniform per block)
+    a_row0 = g * a_grows;
+  }
+  const int i_blk = by * kGBM;
+  const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
+  const int kb = split * kper;
+  const int ke = min(K, kb + kper);
+  const float2* Ag = A + (size_t)a_row0 * lda;
+  floatx4 ar[4][4], ai[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      ar[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+      ai[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+  if (kb < ke) {
+    stage_tile(Ag, (size_t)lda, i_blk, M, kb, K, tiles[0][0], wave, lane);
+    stage_tile(B, (size_t)ldb, j_blk, jend, kb, K, tiles[0][1], wave, lane);
+  }
+  int buf = 0;
+  for (int k0 = kb; k0 < ke; k0 += kBK, buf ^= 1) {
+    // this step's tiles have landed (this wave's loads, then every wave's)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (k0 + kBK < ke) {
+      stage_tile(Ag, (size_t)lda, i_blk, M, k0 + kBK, K, tiles[buf ^ 1][0], wave, lane);
+      stage_tile(B, (size_t)ldb, j_blk, jend, k0 + kBK, K, tiles[buf ^ 1][1], wave, lane);
+    }
+    const int kvalid = min(kBK, ke - k0);
+    const int g = lane >> 4, lr = lane & 15;
+    bf16x8 fa[4][4];  // [a tile][plane]
+#pragma unroll
+    for (int a = 0; a < 4; ++a) frag_planes(tiles[buf][0], wi + a * 16 + lr, g, kvalid, fa[a]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      bf16x8 fb[4];
+      frag_planes(tiles[buf][1], wj + b * 16 + lr, g, kvalid, fb);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        floatx4 r = ar[a][b], im = ai[a][b];
+        const bf16x8 nih = bf_neg(fa[a][2]), nil = bf_neg(fa[a][3]);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[0], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[1], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][1], fb[0], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, fb[2], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, fb[3], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nil, fb[2], r, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[2], im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[3], im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][1], fb[2], im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][2], fb[0], im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][2], fb[1], im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][3], fb[0], im, 0, 0, 0);
+        ar[a][b] = r;
+        ai[a][b] = im;
+      }
+    }
+  }
+  float2* o = out + (size_t)split * split_stride;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = i_blk + wi + a * 16 + 4 * (lane >> 4) + e;
+        const int j = j_blk + wj + b * 16 + (lane & 15);
+        if (i < M && j < jend) o[(size_t)i * ldo + j] = make_float2(ar[a][b][e], ai[a][b][e]);
+      }
+}
+
 // Eight consecutive complex values of one operand row (k .. k+7), split into
 // the four planes of that row in LDS; values past the operand (row >= rows or
 // k >= K) are zero.
@@ -1433,16 +1595,11 @@ __device__ __forceinline__ void stage_split8(const float2* __restrict__ src, siz
   *(u32x4*)(&plane[3][lrow][lk]) = il;
 }
 
-// C (M x N) = A B^T over the copy index, split-BF16: A[(a_row0 + i) * lda + k],
-// B[j * ldb + k], both FP32 complex.  Tiles of 128 x 128 (four waves of
-// 64 x 64), k in steps of kBK, the copy index split over blockIdx.z as for the
-// FP32 product (partials reduced by k_zgemm_reduce).  Grouped form (goff !=
-// nullptr): blockIdx.z = group * nsplit + split; group g takes the columns
-// goff[g] .. goff[g+1]-1 (B rows, and the columns of the partial product) and
-// A rows g * a_grows .. (its M rows); blockIdx.x counts the group's column
-// tiles.  Plain form: blockIdx.z is the split.
+// The same product with the operands staged through registers, value by
+// value: for an odd copy count (a single copy), where the 16-byte direct
+// loads of k_zgemm_nt_bf16x3 would run past a row.
 __global__ void __launch_bounds__(kGemmThreads)
-k_zgemm_nt_bf16x3(int M, int N, int K, int kper, const float2* __restrict__ A, int lda,
+k_zgemm_nt_bf16x3_reg(int M, int N, int K, int kper, const float2* __restrict__ A, int lda,
                   const float2* __restrict__ B, int ldb, float2* __restrict__ out, int ldo,
                   size_t split_stride, const int* __restrict__ goff, int nsplit, int a_grows) {
   // LDS: [plane][row][k] with rows of kBK bf16 (64 bytes) plus 16 bytes of padding
@@ -1574,8 +1731,12 @@ hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int l
     hipLaunchKernelGGL((k_zgemm_nt_f32<4, kF32TN>), grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper,
                        A, lda, B, ldb, P, N, ss, (const int*)nullptr, 1, (size_t)0);
   } else {
-    hipLaunchKernelGGL(k_zgemm_nt_bf16x3, grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper, A, lda,
-                       B, ldb, P, N, ss, (const int*)nullptr, g.splits, 0);
+    if (K & 1)
+      hipLaunchKernelGGL(k_zgemm_nt_bf16x3_reg, grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper, A,
+                         lda, B, ldb, P, N, ss, (const int*)nullptr, g.splits, 0);
+    else
+      hipLaunchKernelGGL(k_zgemm_nt_bf16x3, grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper, A, lda,
+                         B, ldb, P, N, ss, (const int*)nullptr, g.splits, 0);
   }
   const size_t tot = ss;
   hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, N,
@@ -1664,8 +1825,12 @@ hipError_t launch_zgemm_grouped_bf16(int M, int Ntot, int maxn, int K, int ngrou
   const size_t ss = (size_t)M * Ntot;
   float2* P = (float2*)work;
   dim3 grid(g.tpg, g.mt, ngroups * g.splits);
-  hipLaunchKernelGGL(k_zgemm_nt_bf16x3, grid, dim3(kGemmThreads), 0, st, M, Ntot, K, g.kper, A, K,
-                     B, K, P, Ntot, ss, d_goff, g.splits, M);
+  if (K & 1)
+    hipLaunchKernelGGL(k_zgemm_nt_bf16x3_reg, grid, dim3(kGemmThreads), 0, st, M, Ntot, K, g.kper, A,
+                       K, B, K, P, Ntot, ss, d_goff, g.splits, M);
+  else
+    hipLaunchKernelGGL(k_zgemm_nt_bf16x3, grid, dim3(kGemmThreads), 0, st, M, Ntot, K, g.kper, A, K,
+                       B, K, P, Ntot, ss, d_goff, g.splits, M);
   hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((ss + 255) / 256)), dim3(256), 0, st, M, Ntot,
                      g.splits, P, ss, C, ldc, accumulate, cmap);
   return hipGetLastError();

@@ -525,10 +525,10 @@ def main() -> int:
     cplx = tm["gemm_flops"] / a.steps          # 8 M N K, the complex-product count
     executed = cplx * (0.75 if prec == 0 else 3.0)
     peak = MFMA_PEAK_TFLOPS[prec]
-    roofs["gemm"] = {"kernel": "k_zgemm_nt_f32" if prec == 0 else "k_zgemm_tn_bf16x3", "bound": "mfma",
+    roofs["gemm"] = {"kernel": "k_zgemm_nt_f32" if prec == 0 else "k_zgemm_nt_bf16x3", "bound": "mfma",
                      "achieved": round(executed / t / 1e12, 2), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(executed / t / 1e12 / peak, 4),
-                     "traffic": _traffic_from_profile("k_zgemm_nt_f32" if prec == 0 else "k_zgemm_tn_bf16x3",
+                     "traffic": _traffic_from_profile("k_zgemm_nt_f32" if prec == 0 else "k_zgemm_nt_bf16x3",
                                                       w.name),
                      "complex_8mnk_tflops": round(cplx / t / 1e12, 2),
                      "note": "executed MFMA flops: 6 M N K (FP32, 3 real products) or 24 M N K (BF16)"}

@@ -493,6 +493,13 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
       if (!encode_ops(s, rev, tr.fixed, work_q, tops, err, true, &tail_regs))
         return fail(QS_ERR_UNSUPPORTED, err);
       tl.bnops = (int)(tops.size() - before);
+      tl.code = 0;
+      if (tl.bnops <= 8)
+        for (int o = 0; o < tl.bnops; ++o) {
+          const DevOp& op = tops[before + o];
+          const uint64_t b = op.kind == 1 ? 0x80u : (uint64_t)((op.mk & 7) << 3 | (op.target & 7));
+          tl.code |= b << (8 * o);
+        }
     }
   }
   {

@@ -364,9 +364,8 @@ __device__ __forceinline__ uint32_t reg_index(int r, const uint32_t (&RB)[R]) {
 // register split of the op); it is kept as 8 e, the byte offset of omega^e in
 // the phase table, where a failed projector points at the zero entry.
 template <int NB>
-__device__ __forceinline__ void diag_regs(float2 (&v)[1 << NB], const DevOp& op, uint32_t F,
-                                          const uint32_t (&RB)[NB > 0 ? NB : 1],
-                                          const float2* tab) {
+__device__ __forceinline__ void diag_offsets(uint32_t (&off)[1 << NB], const DevOp& op, uint32_t F,
+                                             const uint32_t (&RB)[NB > 0 ? NB : 1]) {
   constexpr int E = 1 << NB;
   // every field of the op is the same in all lanes: read into scalar registers
   const auto su = [](uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane(x); };
@@ -392,7 +391,6 @@ __device__ __forceinline__ void diag_regs(float2 (&v)[1 << NB], const DevOp& op,
       ex[r] = ex[low] + wk[top] + 32 * __popc(rr[top] & (uint32_t)low);
     }
   }
-  uint32_t off[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) off[r] = (uint32_t)ex[r] & 56u;
   if (__builtin_amdgcn_readfirstlane((uint32_t)op.pmask) != 0) {
@@ -413,6 +411,15 @@ __device__ __forceinline__ void diag_regs(float2 (&v)[1 << NB], const DevOp& op,
       if (!(lane_ok && reg_ok)) off[r] = 8u * (kPhaseEntries - 1);
     }
   }
+}
+
+template <int NB>
+__device__ __forceinline__ void diag_regs(float2 (&v)[1 << NB], const DevOp& op, uint32_t F,
+                                          const uint32_t (&RB)[NB > 0 ? NB : 1],
+                                          const float2* tab) {
+  constexpr int E = 1 << NB;
+  uint32_t off[E];
+  diag_offsets<NB>(off, op, F, RB);
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = cmul(v[r], *(const float2*)((const char*)tab + off[r]));
 }
@@ -904,6 +911,36 @@ __host__ __device__ constexpr int fused_row_stride(int K) {
   return 4 * (K / 4 + kFusedPadQ) + kFusedPadRow;
 }
 
+// The leaf amplitude of node rn, emission path j at value s, from the three
+// real products of the contraction (re = p1 - p2, im = p3 - p1 - p2), stored
+// at every copy it stands for: X[s][((rn << M) + j) << ne | e] times the end
+// cuts' factors at s (upper: the projector on bit e, lower: the sign), or only
+// at e = 0 without factors when the end cuts are folded into the assembly.
+__device__ __forceinline__ void tail_store(const TailDesc& T, float2* __restrict__ X, int si,
+                                           uint32_t s, int rn, int M, int ne, uint32_t j,
+                                           float p1, float p2, float p3) {
+  const float re = p1 - p2;
+  const float im = p3 - p1 - p2;
+  if (T.end_base) {
+    X[(size_t)si * T.ldx + (((size_t)rn << M) + j)] = make_float2(re, im);
+    return;
+  }
+  float2* dst = X + (size_t)si * T.ldx + ((((size_t)rn << M) + j) << ne);
+  for (int e = 0; e < (1 << ne); ++e) {
+    float2 f = make_float2(re, im);
+    for (int i = 0; i < ne; ++i) {
+      const uint32_t eb = (e >> (ne - 1 - i)) & 1;
+      const uint32_t sb = (s >> T.eq[i]) & 1;
+      if (T.upper) {
+        if (eb != sb) f = make_float2(0.f, 0.f);
+      } else if (eb & sb) {
+        f = make_float2(-f.x, -f.y);
+      }
+    }
+    dst[e] = f;
+  }
+}
+
 // One contraction unit of k_tail_fused: node tile `at` (16 nodes) against
 // NBT column tiles of the chunk starting at tile b0.  Lane group gq = lane/16
 // takes y in [gq K/4, (gq+1) K/4) as the MFMA k index; the node amplitudes
@@ -984,26 +1021,7 @@ __device__ __forceinline__ void fused_unit(const TailDesc& T, const float2* __re
     for (int e4 = 0; e4 < 4; ++e4) {
       const int rn = at * 16 + 4 * gq + e4;
       if (rn >= Nn) continue;
-      const float re = p1[bb][e4] - p2[bb][e4];
-      const float im = p3[bb][e4] - p1[bb][e4] - p2[bb][e4];
-      if (T.end_base) {
-        X[(size_t)si * T.ldx + (((size_t)rn << M) + j)] = make_float2(re, im);
-        continue;
-      }
-      float2* dst = X + (size_t)si * T.ldx + ((((size_t)rn << M) + j) << ne);
-      for (int e = 0; e < (1 << ne); ++e) {
-        float2 f = make_float2(re, im);
-        for (int i = 0; i < ne; ++i) {
-          const uint32_t eb = (e >> (ne - 1 - i)) & 1;
-          const uint32_t sb = (s >> T.eq[i]) & 1;
-          if (T.upper) {
-            if (eb != sb) f = make_float2(0.f, 0.f);
-          } else if (eb & sb) {
-            f = make_float2(-f.x, -f.y);
-          }
-        }
-        dst[e] = f;
-      }
+      tail_store(T, X, si, s, rn, M, ne, j, p1[bb][e4], p2[bb][e4], p3[bb][e4]);
     }
   }
 }
@@ -1139,6 +1157,325 @@ k_tail_fused(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
   }
 }
 
+// k_tail_ws: the same leaf evaluation with specialised waves, for at most
+// kWsMaxNodes materialised nodes.  Eight producer waves walk the leaf paths
+// (one depth-first chain each, its stack in registers as in k_tail_fused) and
+// write each chunk of kWsRows rows into one of two LDS buffers; four consumer
+// waves each hold one 16-node tile of the value's node amplitudes in
+// registers for the whole workgroup (read from HBM once, instead of once per
+// chunk) and contract the other buffer's chunk on FP32 MFMA.  One barrier per
+// chunk.  Waves w, w + 4 and w + 8 share a SIMD, so every SIMD runs two
+// producers and one consumer: the producers' vector work and the consumer's
+// MFMAs overlap instead of alternating.
+constexpr int kWsProducers = 8;
+constexpr int kWsConsumers = 4;
+constexpr int kWsThreads = 64 * (kWsProducers + kWsConsumers);
+constexpr int kWsRows = 32;                         // rows per chunk
+constexpr int kWsSteps = kWsRows / kWsProducers;    // paths per producer per chunk
+constexpr int kWsMaxNodes = 16 * kWsConsumers;
+constexpr int kWsMaxOps = 32;  // leaf-level ops whose DIAG offsets fit in LDS
+
+static bool tail_ws_ok(const TailDesc& h) {
+  if (!tail_fused_ok(h) || h.n_nodes < 1 || h.n_nodes > kWsMaxNodes) return false;
+  // every producer needs at least one whole chunk: 2^M >= kWsRows
+  if ((1 << h.M) < kWsRows) return false;
+  // the producers take the first two leaf levels' digits together: one cut bit each
+  if (h.nlev < 2 || h.lev[0].m != 1 || h.lev[1].m != 1) return false;
+  // ops decoded from the levels' byte codes (targets are light-cone bits 0..7)
+  for (int l = 0; l < h.nlev; ++l)
+    if (h.lev[l].bnops > 8) return false;
+  const int nops = h.lev[h.nlev - 1].bop0 + h.lev[h.nlev - 1].bnops - h.lev[0].bop0;
+  return nops <= kWsMaxOps;
+}
+
+// Lane-pair 2x2 gate on lane bit w in its unit-entry form, the partner's
+// amplitude read by ds_bpermute at lane ^ 2^w (the generic form for other
+// matrices).
+template <int R>
+__device__ __forceinline__ void ws_lane_mat(float2 (&v)[R], const DevOp& op, int mk, int w,
+                                            int lane) {
+  const int addr = (lane ^ (1 << w)) << 2;
+  const bool bit = (lane >> w) & 1;
+  const auto sh = [addr](float x) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
+  };
+  if (mk == MK_X) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float px = sh(v[r].x), py = sh(v[r].y);
+      v[r] = make_float2(v[r].x + py, v[r].y - px);
+    }
+  } else if (mk == MK_Y || mk == MK_YT) {
+    const float sg = (bit == (mk == MK_Y)) ? 1.f : -1.f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float px = sh(v[r].x), py = sh(v[r].y);
+      v[r] = make_float2(fmaf(sg, px, v[r].x), fmaf(sg, py, v[r].y));
+    }
+  } else if (mk == MK_H) {
+    const float sg = bit ? -1.f : 1.f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float px = sh(v[r].x), py = sh(v[r].y);
+      v[r] = make_float2(fmaf(sg, v[r].x, px), fmaf(sg, v[r].y, py));
+    }
+  } else {
+    lane_mat_m<R>(v, op, w, bit);
+  }
+}
+
+// dst = src times the cut factors of branch b over a level's cut bits (the
+// rule of cut_factors) on a producer's 64 x R vector: index F | r 2^6 with F =
+// value base | lane.  The condition splits into the lane's part (one test per
+// level visit) and the register's part, which is the same in every lane.
+template <int R>
+__device__ __forceinline__ void ws_cut(float2 (&dst)[R], const float2 (&src)[R],
+                                       const TailLevel& L, int b, int upper, uint32_t F) {
+  uint32_t cmask, cval, zmask;
+  cut_factors(L.bq, L.m, b, upper, cmask, cval, zmask);
+  cmask = (uint32_t)__builtin_amdgcn_readfirstlane(cmask);
+  cval = (uint32_t)__builtin_amdgcn_readfirstlane(cval);
+  zmask = (uint32_t)__builtin_amdgcn_readfirstlane(zmask);
+  constexpr uint32_t regm = (uint32_t)(R - 1) << 6;
+  const bool lane_ok = (F & cmask & ~regm) == (cval & ~regm);
+  const uint32_t lane_sg = (uint32_t)(__popc(F & zmask & ~regm) & 1) << 31;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t rb = (uint32_t)r << 6;
+    float2 a = src[r];
+    if ((rb & cmask) != (cval & regm)) {
+      a = make_float2(0.f, 0.f);
+    } else {
+      if (cmask | cval) a = lane_ok ? a : make_float2(0.f, 0.f);
+      if (zmask) {
+        const uint32_t sg = lane_sg ^ ((uint32_t)(__popc(rb & zmask) & 1) << 31);
+        a = make_float2(__uint_as_float(__float_as_uint(a.x) ^ sg),
+                        __uint_as_float(__float_as_uint(a.y) ^ sg));
+      }
+    }
+    dst[r] = a;
+  }
+}
+
+// Register-pair 2x2 gate on register bit rb with a given matrix kind.
+template <int R>
+__device__ __forceinline__ void ws_mat_reg(float2 (&v)[R], const DevOp& op, int mk, int rb) {
+  switch (mk) {
+    case MK_X: tail_mat_reg_u<R, MK_X>(v, rb); break;
+    case MK_Y: tail_mat_reg_u<R, MK_Y>(v, rb); break;
+    case MK_YT: tail_mat_reg_u<R, MK_YT>(v, rb); break;
+    case MK_H: tail_mat_reg_u<R, MK_H>(v, rb); break;
+    default: tail_mat_reg_m<R>(v, op.m, rb); break;
+  }
+}
+
+// The ops [o0, o0 + nops) of a producer of k_tail_ws on its 64 x R vector
+// (lanes: working bits 0..5, registers: bits 6..): MATs in their unit-entry
+// forms, DIAGs as table lookups at the offsets precomputed for this
+// workgroup's value (dof: one word per op and lane, byte r = 8 e of register
+// r, op index counted from the first leaf-level op).
+template <int R, int C>
+__device__ __forceinline__ void ws_apply_ops(float2 (&v)[C * R], const DevOp* __restrict__ ops,
+                                             int o0, int nops, uint64_t code, int rel0, int lane,
+                                             const uint32_t* dof, const float2* tab) {
+  // C vectors side by side: register ci R + r is register r of vector ci (the
+  // vector index acts as a register bit that no op touches).  Op o is byte o
+  // of the level's code; only a MAT with a general matrix reads its entries.
+  for (int o = 0; o < nops; ++o) {
+    const uint32_t b = (uint32_t)(code >> (8 * o)) & 0xffu;
+    if ((b & 0x80u) == 0) {
+      const int w = (int)(b & 7u), mk = (int)((b >> 3) & 7u);
+      const DevOp& op = ops[o0 + o];
+      if (w < 6) {
+        ws_lane_mat<C * R>(v, op, mk, w, lane);
+      } else {
+        if constexpr (R >= 2) { if (w == 6) ws_mat_reg<C * R>(v, op, mk, 0); }
+        if constexpr (R >= 4) { if (w == 7) ws_mat_reg<C * R>(v, op, mk, 1); }
+      }
+    } else {
+      const uint32_t pk = dof[(rel0 + o) * 64 + lane];
+#pragma unroll
+      for (int r = 0; r < C * R; ++r)
+        v[r] = cmul(v[r], *(const float2*)((const char*)tab + ((pk >> (8 * (r % R))) & 0xffu)));
+    }
+  }
+}
+
+template <int R>
+__global__ void __launch_bounds__(kWsThreads)
+k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
+          const float2* __restrict__ states, const uint32_t* __restrict__ svals, int s0,
+          float2* __restrict__ X) {
+  constexpr int K = 64 * R, KQ = K / 4;
+  constexpr int RS = fused_row_stride(K);
+  constexpr int NB = ilog2(R);
+  __shared__ __attribute__((aligned(16))) float2 wl[2][kWsRows * RS];  // chunk buffers
+  __shared__ uint32_t dof[kWsMaxOps * 64];  // DIAG table offsets at this value
+  __shared__ float2 tab[kPhaseEntries];
+  const TailDesc& T = *tdp;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int si = s0 + blockIdx.x;
+  const uint32_t s = svals[si];
+  const uint32_t qmask = (1u << T.q) - 1u;
+  const uint32_t base = s & ~qmask, ys = s & qmask;
+  const int nlev = T.nlev, M = T.M;
+  const int top0 = T.lev[0].bop0;
+  if (wave < kWsProducers) {
+    // every DIAG op of the leaf levels, at this value: index base | lane |
+    // register bits, the lane part fixed for the whole workgroup
+    const int ntop = T.lev[nlev - 1].bop0 + T.lev[nlev - 1].bnops - top0;
+    uint32_t RB[NB > 0 ? NB : 1];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) RB[k] = 1u << (6 + k);
+    if constexpr (NB == 0) RB[0] = 0;
+    for (int i = wave; i < ntop; i += kWsProducers) {
+      const DevOp& op = ops[top0 + i];
+      if (__builtin_amdgcn_readfirstlane(op.kind) == 1) {
+        uint32_t off[R];
+        diag_offsets<NB>(off, op, base | (uint32_t)lane, RB);
+        uint32_t pk = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) pk |= off[r] << (8 * r);
+        dof[i * 64 + lane] = pk;
+      }
+    }
+  }
+  init_phase_table(tab);  // and the barrier after the offsets
+  const uint32_t JP = (1u << M) / kWsProducers;  // paths per producer
+  const int nchunks = (int)(JP / kWsSteps);
+  if (wave < kWsProducers) {
+    // ---- producer: paths [wave JP, (wave + 1) JP), the kWsSteps = 4 paths
+    // j = wave JP + 4 ch + 2 b1 + b0 in chunk ch, at LDS row wave 4 + 2 b1 + b0
+    // (b0, b1: the digits of the first two leaf levels, one cut bit each).  The
+    // four share the vector above level 1; level 0's ops run on both values
+    // of b1 at once (one decode of each op for two vectors).
+    static_assert(kWsSteps == 4, "a chunk takes one group of four paths per producer");
+    const uint32_t F = base | (uint32_t)lane;
+    const uint32_t jw = (uint32_t)wave * JP;
+    float2 u[kFusedDepth - 1][R];  // the vector after depth D's ops, D < nlev - 1
+    uint32_t jprev = 0;
+    for (int ch = 0; ch <= nchunks; ++ch) {
+      if (ch < nchunks) {
+        float2* buf = wl[ch & 1];
+        const uint32_t jl = (uint32_t)ch * kWsSteps;
+        int d0 = -1;  // u[0..d0] still hold
+        if (jl > 0) {
+          // jw is a multiple of JP > jl: the changed digits are jl's (levels 2..)
+          const int hb = 31 - __builtin_clz(jl ^ jprev);
+          int lh = 0;
+          while (lh + 1 < nlev && T.lev[lh + 1].pos <= hb) ++lh;
+          d0 = nlev - 1 - lh;
+        }
+        jprev = jl;
+        const uint32_t j = jw + jl;
+#pragma unroll
+        for (int D = 0; D < kFusedDepth - 1; ++D) {
+          if (D < nlev - 1 && D > d0) {
+            const int l = nlev - 1 - D;
+            float2 v[R];
+            if (D == 0) {
+#pragma unroll
+              for (int r = 0; r < R; ++r)
+                v[r] = ((uint32_t)(lane + 64 * r) == ys) ? make_float2(T.tscale, 0.f)
+                                                         : make_float2(0.f, 0.f);
+            } else {
+              const TailLevel& L = T.lev[l + 1];
+              const int b = (int)((j >> L.pos) & ((1u << L.m) - 1u));
+              ws_cut<R>(v, u[D - 1], L, b, T.upper, F);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) u[D][r] = v[r];
+            ws_apply_ops<R, 1>(u[D], ops, T.lev[l].bop0, T.lev[l].bnops, T.lev[l].code,
+                               T.lev[l].bop0 - top0, lane, dof, tab);
+          }
+        }
+        // level 0 on the vector above it with level 1's cut factor for b1 = 0
+        // and for b1 = 1 (registers ci R + r), then level 0's cut for b0
+        float2 w[2 * R];
+        {
+          float2 top[R];
+#pragma unroll
+          for (int D = 0; D < kFusedDepth - 1; ++D)
+            if (D == nlev - 2) {
+#pragma unroll
+              for (int r = 0; r < R; ++r) top[r] = u[D][r];
+            }
+          float2 h[R];
+          ws_cut<R>(h, top, T.lev[1], 0, T.upper, F);
+#pragma unroll
+          for (int r = 0; r < R; ++r) w[r] = h[r];
+          ws_cut<R>(h, top, T.lev[1], 1, T.upper, F);
+#pragma unroll
+          for (int r = 0; r < R; ++r) w[R + r] = h[r];
+        }
+        ws_apply_ops<R, 2>(w, ops, T.lev[0].bop0, T.lev[0].bnops, T.lev[0].code,
+                           T.lev[0].bop0 - top0, lane, dof, tab);
+#pragma unroll
+        for (int st = 0; st < kWsSteps; ++st) {
+          float2 src[R], a[R];
+#pragma unroll
+          for (int r = 0; r < R; ++r) src[r] = w[(st >> 1) * R + r];
+          ws_cut<R>(a, src, T.lev[0], st & 1, T.upper, F);
+          float2* row = buf + (wave * kWsSteps + st) * RS;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int y = lane + 64 * r;
+            row[(y / KQ) * (KQ + kFusedPadQ) + (y % KQ)] = a[r];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  } else {
+    // ---- consumer: node tile `at` in registers; lane group gq = lane / 16
+    // takes y in [gq KQ, (gq + 1) KQ) as the MFMA k index
+    const int cw = wave - kWsProducers;
+    const int Nn = T.n_nodes, ne = T.n_end;
+    const int nat = (Nn + 15) >> 4;
+    const int nts = nat >= 3 ? 4 : nat;  // node-tile slots
+    const int at = cw % nts;
+    const int li = lane & 15, gq = lane >> 4;
+    const size_t N = (size_t)1 << T.n;
+    // nodes past the last one read a valid row and are not written
+    const float4* arow = (const float4*)(states + (size_t)min(at * 16 + li, Nn - 1) * N + base +
+                                         gq * KQ);
+    float4 A[KQ / 2];
+#pragma unroll
+    for (int i = 0; i < KQ / 2; ++i) A[i] = arow[i];
+    __syncthreads();
+    for (int ch = 0; ch < nchunks; ++ch) {
+      const float2* buf = wl[ch & 1];
+      if (at < nat) {
+        for (int ct = cw / nts; ct < kWsRows / 16; ct += kWsConsumers / nts) {
+          const float2* brow = buf + (ct * 16 + li) * RS + gq * (KQ + kFusedPadQ);
+          floatx4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, p3 = p1;
+#pragma unroll
+          for (int i = 0; i < KQ / 2; ++i) {
+            const float4 bv = *(const float4*)(brow + 2 * i);
+            const float4 av = A[i];
+            p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, p1, 0, 0, 0);
+            p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, p2, 0, 0, 0);
+            p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x + av.y, bv.x + bv.y, p3, 0, 0, 0);
+            p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, p1, 0, 0, 0);
+            p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, p2, 0, 0, 0);
+            p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z + av.w, bv.z + bv.w, p3, 0, 0, 0);
+          }
+          // column col = ct 16 + li is producer col / kWsSteps, step col % kWsSteps
+          const int col = ct * 16 + li;
+          const uint32_t j = (uint32_t)(col / kWsSteps) * JP + (uint32_t)(ch * kWsSteps + col % kWsSteps);
+#pragma unroll
+          for (int e4 = 0; e4 < 4; ++e4) {
+            const int rn = at * 16 + 4 * gq + e4;
+            if (rn < Nn) tail_store(T, X, si, s, rn, M, ne, j, p1[e4], p2[e4], p3[e4]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 size_t tail_w_bytes(const TailDesc& h, int ns) {
   return (size_t)ns * ((size_t)1 << h.M) * ((size_t)1 << h.q) * sizeof(float2);
 }
@@ -1150,7 +1487,18 @@ hipError_t launch_tail(const TailDesc& h, const TailDesc* d_desc, const DevOp* d
   if (h.fused) {
     const int R = 1 << (h.q - 6);
     if (!tail_fused_ok(h)) return hipErrorInvalidValue;
-    dim3 g((unsigned)ns), b(kFusedThreads);
+    dim3 g((unsigned)ns);
+    if (tail_ws_ok(h)) {
+      dim3 b(kWsThreads);
+      switch (R) {
+        case 1: hipLaunchKernelGGL(k_tail_ws<1>, g, b, 0, st, d_desc, d_ops, states, svals, s0, X); break;
+        case 2: hipLaunchKernelGGL(k_tail_ws<2>, g, b, 0, st, d_desc, d_ops, states, svals, s0, X); break;
+        case 4: hipLaunchKernelGGL(k_tail_ws<4>, g, b, 0, st, d_desc, d_ops, states, svals, s0, X); break;
+        default: return hipErrorInvalidValue;
+      }
+      return hipGetLastError();
+    }
+    dim3 b(kFusedThreads);
     switch (R) {
       case 1:
         hipLaunchKernelGGL(k_tail_fused<1>, g, b, 0, st, d_desc, d_ops, states, svals, s0, X);

@@ -164,6 +164,9 @@ struct TailLevel {
   int shift;             // position of the level's branch bits in the leaf index
   int pos;               // position of the level's branch bits in the emission index
   uint64_t kbit[kMaxBranch];  // copy-index contribution of each branch bit
+  // the level's ops, one byte each (levels of at most 8 ops, else 0):
+  // DIAG << 7 | MatKind << 3 | target
+  uint64_t code;
 };
 
 // Leaf evaluation restricted to the light cone.  Below the materialised

@@ -509,18 +509,22 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
       acc += td.lev[l].m;
     }
   }
+  td.n_nodes = (int)sp.nodes[sp.lstar];
   td.fused = tail_fused_ok(td) ? 1 : 0;
+  td.ws = td.fused && tail_ws_ok(td) ? 1 : 0;
   // copy-index contribution of each leaf path below the materialised level,
-  // indexed the way the leaf evaluation writes its output (lam, or the
-  // emission index of the fused kernel)
+  // indexed the way the leaf evaluation writes its output (lam, the emission
+  // index of the fused kernel, or its field-swapped form of the specialised one)
   pr->leaf_k.assign((size_t)1 << td.M, 0);
   for (size_t lam = 0; lam < pr->leaf_k.size(); ++lam) {
     uint64_t k = 0;
     for (int l = 0; l < td.nlev; ++l) {
       const TailLevel& tl = td.lev[l];
       const int at = td.fused ? tl.pos : tl.shift;
-      for (int i = 0; i < tl.m; ++i)
-        if ((lam >> (at + tl.m - 1 - i)) & 1) k |= tl.kbit[i];
+      for (int i = 0; i < tl.m; ++i) {
+        const int b = at + tl.m - 1 - i;
+        if ((lam >> (td.ws ? tail_ws_bit(b, td.M) : b)) & 1) k |= tl.kbit[i];
+      }
     }
     pr->leaf_k[lam] = k;
   }
@@ -565,7 +569,6 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
     ++td.split_levels;
   }
   td.upper = s.upper ? 1 : 0;
-  td.n_nodes = (int)sp.nodes[sp.lstar];
   td.S = S;
   td.ldx = 1 << (c - blk.p);  // row stride of X[s][nu]: the block's copies
   // lower half, product-set assembly: write only the copies with end bits 0

@@ -25,6 +25,9 @@ size_t tail_w_bytes(const TailDesc& h, int ns);
 // contraction of a value in one workgroup; then W is not used and the output
 // leaf paths come in emission order, see TailDesc::fused).
 bool tail_fused_ok(const TailDesc& h);
+// Whether the fused leaf evaluation of h can take the specialised-wave kernel
+// (see TailDesc::ws).
+bool tail_ws_ok(const TailDesc& h);
 hipError_t launch_tail(const TailDesc& h_desc, const TailDesc* d_desc, const DevOp* d_ops,
                        const float2* states, const uint32_t* svals, int s0, int ns, float2* W,
                        float2* X, hipStream_t st);

@@ -889,6 +889,16 @@ k_tail_mm(const TailDesc* __restrict__ tdp, const float2* __restrict__ W,
       }
 }
 
+// Workgroup barrier that orders LDS accesses only: it waits for this wave's
+// LDS operations but not for its global stores (a __syncthreads waits for
+// those as well, and the leaf kernels' output stores need no ordering with
+// the other waves).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // k_tail_fused: the rows and the contraction of one requested value s in one
 // workgroup, without the rows passing through HBM.  The 2^M leaf paths are
 // taken in emission order j (the digit of level l at bit pos(l) =
@@ -1139,7 +1149,7 @@ k_tail_fused(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
     // ---- contraction: C[node][col] = sum_y v_node[base + y] W[col][y]; a unit
     // is one 16-node tile with both 16-column tiles (or one, when there are
     // fewer than four node tiles)
@@ -1153,7 +1163,7 @@ k_tail_fused(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
       for (int un = wave; un < 2 * nat; un += kFusedWaves)
         fused_unit<R, 1>(T, states, base, wl, un >> 1, un & 1, ch, J4, si, s, X);
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -1175,7 +1185,7 @@ constexpr int kWsSteps = kWsRows / kWsProducers;    // paths per producer per ch
 constexpr int kWsMaxNodes = 16 * kWsConsumers;
 constexpr int kWsMaxOps = 32;  // leaf-level ops whose DIAG offsets fit in LDS
 
-static bool tail_ws_ok(const TailDesc& h) {
+bool tail_ws_ok(const TailDesc& h) {
   if (!tail_fused_ok(h) || h.n_nodes < 1 || h.n_nodes > kWsMaxNodes) return false;
   // every producer needs at least one whole chunk: 2^M >= kWsRows
   if ((1 << h.M) < kWsRows) return false;
@@ -1425,7 +1435,7 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
           }
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
   } else {
     // ---- consumer: node tile `at` in registers; lane group gq = lane / 16
@@ -1443,7 +1453,7 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
     float4 A[KQ / 2];
 #pragma unroll
     for (int i = 0; i < KQ / 2; ++i) A[i] = arow[i];
-    __syncthreads();
+    lds_barrier();
     for (int ch = 0; ch < nchunks; ++ch) {
       const float2* buf = wl[ch & 1];
       if (at < nat) {
@@ -1461,9 +1471,13 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
             p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, p2, 0, 0, 0);
             p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z + av.w, bv.z + bv.w, p3, 0, 0, 0);
           }
-          // column col = ct 16 + li is producer col / kWsSteps, step col % kWsSteps
+          // column col = ct 16 + li is producer col / kWsSteps, step col % kWsSteps:
+          // emission index (col / 4) JP + 4 ch + col % 4, written at 32 ch + col
+          // (tail_ws_bit), so that a chunk fills 32 consecutive copies of a node
+          static_assert(kWsRows == 32 && kWsSteps == 4 && kWsProducers == 8,
+                        "the output index of tail_ws_bit");
           const int col = ct * 16 + li;
-          const uint32_t j = (uint32_t)(col / kWsSteps) * JP + (uint32_t)(ch * kWsSteps + col % kWsSteps);
+          const uint32_t j = (uint32_t)ch * kWsRows + (uint32_t)col;
 #pragma unroll
           for (int e4 = 0; e4 < 4; ++e4) {
             const int rn = at * 16 + 4 * gq + e4;
@@ -1471,7 +1485,7 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
           }
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
   }
 }
@@ -1488,7 +1502,8 @@ hipError_t launch_tail(const TailDesc& h, const TailDesc* d_desc, const DevOp* d
     const int R = 1 << (h.q - 6);
     if (!tail_fused_ok(h)) return hipErrorInvalidValue;
     dim3 g((unsigned)ns);
-    if (tail_ws_ok(h)) {
+    if (h.ws) {
+      if (!tail_ws_ok(h)) return hipErrorInvalidValue;
       dim3 b(kWsThreads);
       switch (R) {
         case 1: hipLaunchKernelGGL(k_tail_ws<1>, g, b, 0, st, d_desc, d_ops, states, svals, s0, X); break;

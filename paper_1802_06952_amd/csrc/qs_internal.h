@@ -179,6 +179,14 @@ struct TailLevel {
 // transposed leaf levels backwards from the unit vector at s (k_tail_bwd).
 // The contraction over y is a small complex GEMM per s (k_tail_mm).  Cuts
 // with no later non-commuting gate multiply the result by their factor at s.
+// Output position of emission bit b of a leaf path under the specialised-wave
+// leaf evaluation (M >= 5 path bits; see TailDesc::ws).
+inline int tail_ws_bit(int b, int M) {
+  if (b < 2) return b;
+  if (b < M - 3) return b + 3;
+  return b - (M - 5);
+}
+
 struct TailDesc {
   int n;
   int q;
@@ -199,6 +207,12 @@ struct TailDesc {
   // then come in emission order j (the digit of level l at bit sum_{l'<l} m_l')
   // instead of lam (the digit of level l at bit lev[l].shift)
   int fused;
+  // 1 (with fused): the leaf evaluation with specialised waves, whose output
+  // index swaps two fields of the emission index j so that each chunk of 32
+  // paths lands on 32 consecutive copies: with j = st | c << 2 | p << (M - 3)
+  // (st: the first two levels' digits, c: the chunk, p: the producer wave) the
+  // paths are written at st | p << 2 | c << 5 (tail_ws_index)
+  int ws;
   // 1: write only the copies whose end bits are all 0, without end factors,
   // at nu0 = node * 2^M + lam (ldx = copies of the block >> n_end).  Used for
   // lower halves: the other copies differ from these by the signs of the end

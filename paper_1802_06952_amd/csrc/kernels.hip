@@ -1576,7 +1576,9 @@ static inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 // Each of the 2 x 2 waves owns TM x TN MFMA tiles (16 x 16 each), so the
 // workgroup tile is (32 TM) x (32 TN).
 constexpr int kFK = 16;
-constexpr int kFPad = 4;
+// Row padding of the staged tiles (complex values): odd, so that the threads
+// that store different k of one row (8 or 4 k apart) land on different banks.
+constexpr int kFPad = 1;
 // Launch shape, measured at 1024 x 1024 outputs over 16384 copies against
 // 128 x 64 tiles and other split counts: 128 x 128 tiles (255 VGPRs, two
 // waves per SIMD), the split count sized so that every workgroup is resident

@@ -653,7 +653,8 @@ def main() -> int:
 
     if not a.no_configs and a.workload == "grid6x7_d20":
         from workloads import workload as _wl
-        tk = tuned_knobs(Q, ("grid6x6_d16", "grid6x7_d20_cols", "grid6x6_d16_stair"))
+        tk = tuned_knobs(Q, ("grid6x6_d16", "grid6x7_d20_cols", "grid6x6_d16_stair",
+                             "grid8x8_d22_slice64"))
         # 36 qubits, 18+18 halves, all 4096 copies, 2^16 bitstrings: small enough that launch
         # latency, not bandwidth, sets its time
         r = time_workload(Q, _wl("grid6x6_d16"), 0, a.steps, a.warmup, stream, tk.get("grid6x6_d16"))
@@ -667,9 +668,11 @@ def main() -> int:
         # one GPU's slice of the 64-qubit circuit (32+32 halves, copies [0, 64) of 65536)
         c5 = {}
         for p_, name in ((0, "fp32"), (1, "split_bf16")):
-            r = time_workload(Q, _wl("grid8x8_d22_slice64"), p_, max(2, a.steps // 5), 1, stream)
+            r = time_workload(Q, _wl("grid8x8_d22_slice64"), p_, max(2, a.steps // 5), 1, stream,
+                              tk.get("grid8x8_d22_slice64"))
             r.pop("amplitudes")
             c5[name] = r
+        c5["knobs"] = tk.get("grid8x8_d22_slice64") or "cost model defaults"
         c5["workload"] = ("grid8x8_d22_slice64: 8x8 grid (64 qubits), depth 22, rows 0-3 | 4-7, "
                           "copies [0, 64) of 65536, 1024 x 1024 bitstrings, partial amplitudes")
         out["config5"] = c5

@@ -325,18 +325,21 @@ def coscheduled_pair(Q, names, prec, steps, warmup, knobs) -> dict:
 
 
 def per_pass_table(recs) -> list:
-    """Every full-state pass of a step with its launch time averaged over the
-    timed steps: [half, pass, input level, stages, tiles, MB, us, GB/s]."""
+    """Every full-state pass launch of a step with its time averaged over the
+    timed steps: [half, first pass, input level, stages, tiles, MB, us, GB/s,
+    passes run by the launch]."""
     acc = {}
     for r in recs:
         k = (r["side"], r["pass"])
-        e = acc.setdefault(k, [r["level_in"], r["stages"], r["tiles"], r["bytes"], 0.0, 0])
+        e = acc.setdefault(k, [r["level_in"], r["stages"], r["tiles"], r["bytes"], 0.0, 0,
+                               r.get("passes", 1)])
         e[4] += r["ms"]
         e[5] += 1
     rows = []
-    for (side, pi), (li, st, tiles, b, ms, cnt) in sorted(acc.items()):
+    for (side, pi), (li, st, tiles, b, ms, cnt, npass) in sorted(acc.items()):
         us = ms * 1000.0 / cnt
-        rows.append([side, pi, li, st, tiles, round(b / 1e6, 2), round(us, 2), round(b / (us * 1e3), 1)])
+        rows.append([side, pi, li, st, tiles, round(b / 1e6, 2), round(us, 2),
+                     round(b / (us * 1e3), 1), npass])
     return rows
 
 
@@ -575,7 +578,7 @@ def main() -> int:
         "setup_s": round(setup_s, 3),
         "roofline": roof,
         "roofline_by_family": roofs,
-        "pass_launches": {"columns": ["half", "pass", "level_in", "stages", "tiles", "MB", "us", "GB/s"],
+        "pass_launches": {"columns": ["half", "pass", "level_in", "stages", "tiles", "MB", "us", "GB/s", "passes"],
                           "rows": pass_table},
         "schedule": "halves on one stream" if a.one_stream else "halves on two streams, concurrent",
         "ms_per_step_one_stream_timed": round(ms_one_stream, 4),

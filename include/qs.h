@@ -106,6 +106,10 @@ typedef struct {
                              planner picks where each pass lands */
   int min_tile_bits;      /* smallest tile of a full-state pass (7..tile_bits, 0 = 8): a pass's
                              tile holds its gates' qubits, padded up to this many */
+  int no_exchange;        /* 1: every full-state pass is a launch of its own; 0: runs of passes
+                             without a branch whose register bits fit in 3 more bits run as
+                             one launch on workgroup tiles that pass through LDS between the
+                             passes (one HBM read and write per run; same results) */
   qs_allocator alloc;     /* every device buffer of the plan (states, gathered half amplitudes,
                              descriptors, copy tables, assembly workspace) comes from here */
 } qs_options;
@@ -281,12 +285,14 @@ qs_status qs_get_timing(qs_plan* plan, double* out11);
 qs_status qs_set_timing(qs_plan* plan, int enable);
 
 /* Every full-state pass launch timed since qs_set_timing(plan, 2), in launch
- * order, as 7 doubles: half (0 upper, 1 lower), pass index in that half's
- * schedule, input tree level, branch stages (tree levels descended), wavefront
- * tiles (or workgroups) launched, algorithmic bytes (8 B per amplitude of every
- * state read and written; the last pass only its listed tiles), milliseconds
- * (HIP events on the launch stream).  Writes min(n, cap_records) records to
- * out (caller-owned, 7 * cap_records doubles) and the total count to
+ * order, as 8 doubles: half (0 upper, 1 lower), index in that half's schedule
+ * of the launch's first pass, input tree level, branch stages (tree levels
+ * descended), wavefront tiles (or workgroups) of one pass, algorithmic bytes
+ * (8 B per amplitude of every state read and written; the last pass only its
+ * listed tiles), milliseconds (HIP events on the launch stream), and the
+ * number of passes the launch ran (more than one for a group of passes that
+ * exchange their tiles through LDS).  Writes min(n, cap_records) records to
+ * out (caller-owned, 8 * cap_records doubles) and the total count to
  * *n_records.  Synchronises with the recorded events.  Errors: QS_ERR_ARG,
  * QS_ERR_HIP. */
 qs_status qs_get_pass_timing(qs_plan* plan, double* out, size_t cap_records, size_t* n_records);

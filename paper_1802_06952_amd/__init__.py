@@ -63,7 +63,8 @@ class qs_options(C.Structure):
     _fields_ = [("tile_bits", C.c_int), ("coalesce_bits", C.c_int), ("tail_max_qubits", C.c_int),
                 ("materialize_level", C.c_int), ("plain", C.c_int), ("mem_budget", C.c_size_t),
                 ("one_stream", C.c_int), ("copies_per_launch", C.c_uint64),
-                ("max_stages", C.c_int), ("min_tile_bits", C.c_int), ("alloc", qs_allocator)]
+                ("max_stages", C.c_int), ("min_tile_bits", C.c_int), ("no_exchange", C.c_int),
+                ("alloc", qs_allocator)]
 
 
 class TorchAllocator:
@@ -319,19 +320,20 @@ def qs_set_timing(plan, enable) -> None:
     _check(_lib.qs_set_timing(plan, int(enable)))
 
 
-PASS_TIMING_FIELDS = ("side", "pass", "level_in", "stages", "tiles", "bytes", "ms")
+PASS_TIMING_FIELDS = ("side", "pass", "level_in", "stages", "tiles", "bytes", "ms", "passes")
 
 
 def qs_get_pass_timing(plan) -> list[dict]:
     n = C.c_size_t(0)
     _check(_lib.qs_get_pass_timing(plan, None, 0, C.byref(n)))
-    out = np.zeros(7 * max(1, n.value), dtype=np.float64)
+    nf = len(PASS_TIMING_FIELDS)
+    out = np.zeros(nf * max(1, n.value), dtype=np.float64)
     _check(_lib.qs_get_pass_timing(plan, out.ctypes.data_as(C.POINTER(C.c_double)), n.value,
                                    C.byref(n)))
     recs = []
-    for r in out[: 7 * n.value].reshape(-1, 7):
+    for r in out[: nf * n.value].reshape(-1, nf):
         d = dict(zip(PASS_TIMING_FIELDS, r.tolist()))
-        for k in ("side", "pass", "level_in", "stages", "tiles"):
+        for k in ("side", "pass", "level_in", "stages", "tiles", "passes"):
             d[k] = int(d[k])
         recs.append(d)
     return recs
@@ -448,12 +450,12 @@ class Plan:
                  coalesce_bits: int = 0, tail_max_qubits: int = 0, materialize_level: int = -1,
                  plain: bool = False, mem_budget: int = 0, one_stream: bool = False,
                  copies_per_launch: int = 0, max_stages: int = 0, min_tile_bits: int = 0,
-                 alloc="torch"):
+                 no_exchange: bool = False, alloc="torch"):
         self.allocator = _allocator(alloc)
         self._circ = qs_load_circuit(circuit_text)
         opts = qs_options(tile_bits, coalesce_bits, tail_max_qubits, materialize_level,
                           1 if plain else 0, mem_budget, 1 if one_stream else 0, copies_per_launch,
-                          max_stages, min_tile_bits)
+                          max_stages, min_tile_bits, 1 if no_exchange else 0)
         if self.allocator is not None:
             opts.alloc = self.allocator.struct
         try:

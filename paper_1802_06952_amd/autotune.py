@@ -12,10 +12,14 @@ C ABI and keeps the fastest.  The knobs searched:
   evaluation covers (all copies, or a quarter of them per block);
 * ``materialize_level``: the last materialised tree level (the cost model's
   choice, or forced one level either side of it);
-* ``tail_max_qubits``: the largest light cone of the leaf evaluation: 8 or 10.
+* ``tail_max_qubits``: the largest light cone of the leaf evaluation: 8 or 10;
+* ``no_exchange``: whether runs of passes may share a launch and exchange their
+  workgroup tiles through LDS (0) or run one launch per pass (1).
 
 The search is coordinate descent from the cost model's defaults: each knob in
-turn takes every value with the others fixed, and the best is kept.  A result
+turn takes every value with the others fixed, and the best is kept; the tile
+width and the grouping are searched together (a wider tile changes whether
+grouping pays).  A result
 is stored in a JSON file under the workload's name, with the SHA-256 of the
 circuit text, cut, copy range and bitstrings it was measured on; a reader
 uses the stored knobs only if that key still matches.
@@ -94,7 +98,7 @@ def knob_values(n_cuts: int, k0: int, k1: int, model_levels: list[int]) -> dict:
             if base + d >= 0 and base + d not in lv:
                 lv.append(base + d)
     return {"tile_bits": [10, 9, 11], "max_stages": [2, 1], "copies_per_launch": cpl,
-            "materialize_level": lv, "tail_max_qubits": [10, 8]}
+            "materialize_level": lv, "tail_max_qubits": [10, 8], "no_exchange": [0, 1]}
 
 
 def autotune(text: str, mask: int, bits, k0: int, k1: int, reps: int = 3, stream=None,
@@ -111,6 +115,11 @@ def autotune(text: str, mask: int, bits, k0: int, k1: int, reps: int = 3, stream
     values = knob_values(n_cuts, k0, k1, model_levels)
     cur = {k: v[0] for k, v in values.items()}
     tried = {}
+    # axes of the descent: tile width and grouping jointly, then one knob each
+    axes = [[{"tile_bits": t, "no_exchange": e} for t in values["tile_bits"]
+             for e in values["no_exchange"]]]
+    axes += [[{k: v} for v in vals] for k, vals in values.items()
+             if k not in ("tile_bits", "no_exchange")]
 
     def measure(opts):
         key = json.dumps(opts, sort_keys=True)
@@ -127,11 +136,14 @@ def autotune(text: str, mask: int, bits, k0: int, k1: int, reps: int = 3, stream
 
     t_start = time.perf_counter()
     default_ms = best_ms = measure(cur)
-    for knob, vals in values.items():
-        for v in vals[1:]:
+    for axis in axes:
+        base = cur
+        for part in axis:
             if time.perf_counter() - t_start > budget_s:
                 break
-            cand = dict(cur, **{knob: v})
+            cand = dict(base, **part)
+            if cand == base:
+                continue
             ms = measure(cand)
             if ms < best_ms:
                 best_ms, cur = ms, cand

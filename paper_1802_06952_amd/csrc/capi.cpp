@@ -159,9 +159,11 @@ struct Prepared {
   DevAlloc* da = nullptr;  // owner of dev
   SidePlan sp;
   std::vector<PassDesc> pds;
+  std::vector<XPassDesc> xds;  // exchange groups
+  std::vector<int> xidx;       // per pass: its group's index in xds (first pass only), or -1
   TailDesc td{};
   char* dev = nullptr;  // descriptors, tail desc, ops, node copy indices (owned)
-  size_t o_pd = 0, o_td = 0, o_ops = 0, o_nk = 0, o_lk = 0, o_sv = 0, o_tl = 0;
+  size_t o_pd = 0, o_td = 0, o_ops = 0, o_nk = 0, o_lk = 0, o_sv = 0, o_tl = 0, o_xd = 0;
   uint32_t n_list = 0;  // tiles of the last pass that the leaf evaluation reads (0 = all)
   // lower half with end_base: the end-cut bits sig of every requested value,
   // the values sorted by sig (rows) and the group starts (goff); d_rows in the blob
@@ -258,13 +260,13 @@ struct qs_plan {
   int timing = 0;  // 1: per kernel family; 2: also every full-state pass on its own
   std::vector<EvRec> events;
   struct PassRec {
-    int side, pass, level_in, stages;
+    int side, pass, level_in, stages, passes;
     uint64_t tiles;
     double bytes;
     hipEvent_t a, b;
   };
   std::vector<PassRec> pass_events;
-  std::vector<double> pass_log;  // 7 doubles per timed pass launch (qs_get_pass_timing)
+  std::vector<double> pass_log;  // 8 doubles per timed pass launch (qs_get_pass_timing)
   double tms[4] = {0, 0, 0, 0};
   double counts[4] = {0, 0, 0, 0};
   double pass_bytes = 0, gemm_flops = 0, tail_flops = 0;
@@ -338,6 +340,7 @@ PlanKnobs knobs_of(qs_plan* p, int S) {
   k.one_op_per_pass = p->opts.plain != 0;
   if (p->opts.max_stages > 0) k.max_stages = std::min(p->opts.max_stages, kMaxStages);
   if (p->opts.min_tile_bits > 0) k.min_tile_bits = p->opts.min_tile_bits;
+  k.exchange = p->opts.no_exchange == 0;
   return k;
 }
 
@@ -444,6 +447,8 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
     const double nin = (double)sp.nodes[pp.level_in];
     if (pp.branch())
       last_bytes = (pp.init ? 0.0 : nin * SB) + (double)sp.nodes[pp.level_out()] * SB;
+    else if (pp.xg == 0)
+      last_bytes = 0;  // a later phase of an exchange group: its traffic is the group's
     else
       last_bytes = (pp.init ? 1.0 : 2.0) * nin * SB;
     pr->pass_bytes += last_bytes;
@@ -458,6 +463,53 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
       carry = (k + carry) & 1;
     }
     pr->pds.push_back(d);
+  }
+  // exchange groups: one descriptor per group, at the group's first pass
+  pr->xidx.assign(sp.passes.size(), -1);
+  for (size_t pi = 0; pi < sp.passes.size(); ++pi) {
+    const PassPlan& pp = sp.passes[pi];
+    if (pp.xg < 2) continue;
+    XPassDesc x{};
+    x.G = pp.xg;
+    x.pd0 = (int)pi;
+    x.R = (int)pp.tile.size() - 6;
+    x.n = s.n;
+    x.nu = (int)pp.xu.size();
+    if (x.G > kMaxXPhases || pi + x.G > sp.passes.size() || x.nu != x.R + kXWaveBits ||
+        x.R < kXMinRegBits || x.R > kMaxRegBits || 6 + x.nu > s.n)
+      return fail(QS_ERR_UNSUPPORTED, "internal: exchange group shape");
+    std::vector<int> inu(s.n, -1);
+    for (int i = 0; i < x.nu; ++i) {
+      x.ubit[i] = pp.xu[i];
+      if (pp.xu[i] < 6 || pp.xu[i] >= s.n) return fail(QS_ERR_UNSUPPORTED, "internal: exchange bits");
+      inu[pp.xu[i]] = i;
+    }
+    x.n_outer = 0;
+    for (int q = 6; q < s.n; ++q)
+      if (inu[q] < 0) x.obit[x.n_outer++] = q;
+    for (int p = 0; p < x.G; ++p) {
+      const PassPlan& ph = sp.passes[pi + p];
+      if ((int)ph.tile.size() != 6 + x.R || ph.branch() || (p > 0 && ph.xg != 0))
+        return fail(QS_ERR_UNSUPPORTED, "internal: exchange group phase");
+      std::vector<char> isreg(x.nu, 0);
+      for (int k = 0; k < x.R; ++k) {
+        const int q = ph.tile[6 + k];
+        if (q < 0 || q >= s.n || inu[q] < 0) return fail(QS_ERR_UNSUPPORTED, "internal: exchange register bit");
+        x.rpos[p][k] = inu[q];
+        isreg[inu[q]] = 1;
+      }
+      int j = 0;
+      for (int i = 0; i < x.nu; ++i)
+        if (!isreg[i]) {
+          if (j == kXWaveBits) return fail(QS_ERR_UNSUPPORTED, "internal: exchange wave bits");
+          x.wpos[p][j++] = i;
+        }
+      if (j != kXWaveBits) return fail(QS_ERR_UNSUPPORTED, "internal: exchange wave bits");
+    }
+    x.init = pp.init ? 1 : 0;
+    x.nt = pr->pds[pi + x.G - 1].nt;
+    pr->xidx[pi] = (int)pr->xds.size();
+    pr->xds.push_back(x);
   }
   TailDesc& td = pr->td;
   td.n = s.n;
@@ -679,9 +731,10 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   }
   pr->n_list = (uint32_t)tl.size();
   const size_t b_tl = tl.size() * sizeof(uint32_t);
+  const size_t b_xd = pr->xds.size() * sizeof(XPassDesc);
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t total = al(b_pd) + al(b_td) + al(b_ops) + al(b_nk) + al(b_lk) + al(b_sv) +
-                       al(b_tl) + al(b_rows);
+                       al(b_tl) + al(b_rows) + al(b_xd);
   std::vector<char> host(total, 0);
   pr->o_pd = 0;
   pr->o_td = al(b_pd);
@@ -691,6 +744,7 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   pr->o_sv = pr->o_lk + al(b_lk);
   pr->o_tl = pr->o_sv + al(b_sv);
   pr->o_rows = pr->o_tl + al(b_tl);
+  pr->o_xd = pr->o_rows + al(b_rows);
   if (b_pd) std::memcpy(host.data() + pr->o_pd, pr->pds.data(), b_pd);
   std::memcpy(host.data() + pr->o_td, &td, b_td);
   if (!ops.empty()) std::memcpy(host.data() + pr->o_ops, ops.data(), ops.size() * sizeof(DevOp));
@@ -699,6 +753,7 @@ qs_status prepare_side(qs_plan* P, int sidx, const Block& blk, Prepared** out) {
   std::memcpy(host.data() + pr->o_sv, sv.data(), b_sv);
   if (b_tl) std::memcpy(host.data() + pr->o_tl, tl.data(), b_tl);
   if (b_rows) std::memcpy(host.data() + pr->o_rows, rows_v.data(), b_rows);
+  if (b_xd) std::memcpy(host.data() + pr->o_xd, pr->xds.data(), b_xd);
   pr->dev = (char*)P->dalloc.get(total);
   if (!pr->dev) return fail(QS_ERR_OOM, "descriptor buffer");
   HIPCHECK(hipMemcpy(pr->dev, host.data(), total, hipMemcpyHostToDevice));
@@ -720,6 +775,7 @@ qs_status run_side(qs_plan* P, int sidx, const Prepared& pr, float2* X, hipStrea
     Timer tm(P, st, 0);
     for (size_t pi = 0; pi < sp.passes.size(); ++pi) {
       const PassPlan& pp = sp.passes[pi];
+      if (pp.xg == 0) continue;  // a later phase of the exchange group launched before
       const PassDesc* dd = (const PassDesc*)(pr.dev + pr.o_pd) + pi;
       const bool last = pi + 1 == sp.passes.size() && pr.n_list > 0;
       const uint32_t* tl = last ? (const uint32_t*)(pr.dev + pr.o_tl) : nullptr;
@@ -734,7 +790,12 @@ qs_status run_side(qs_plan* P, int sidx, const Prepared& pr, float2* X, hipStrea
         HIPCHECK(hipEventCreate(&ea));
         HIPCHECK(hipEventRecord(ea, st));
       }
-      if (pp.branch()) {
+      if (pp.xg >= 2) {
+        const int xi = pr.xidx[pi];
+        if (xi < 0) return fail(QS_ERR_UNSUPPORTED, "internal: exchange group descriptor");
+        HIPCHECK(launch_xpass(pr.xds[xi], (const XPassDesc*)(pr.dev + pr.o_xd) + xi,
+                              (const PassDesc*)(pr.dev + pr.o_pd), d_ops, cur, cur_nodes, st));
+      } else if (pp.branch()) {
         const uint64_t on = sp.nodes[pp.level_out()];
         float2* nxt = (float2*)P->pool.get(SB * on, st);
         if (!nxt) return fail(QS_ERR_OOM, "tree level states");
@@ -753,6 +814,7 @@ qs_status run_side(qs_plan* P, int sidx, const Prepared& pr, float2* X, hipStrea
         const uint64_t nin = pp.init ? 1 : sp.nodes[pp.level_in];
         const uint64_t tiles = tl ? nin * nl : (nin << h.n_outer);
         P->pass_events.push_back(qs_plan::PassRec{sidx, (int)pi, pp.level_in, (int)pp.stages.size(),
+                                                  std::max(1, pp.xg),
                                                   tiles, pr.pass_bytes_each[pi], ea, eb});
       }
       ++tm.launches;
@@ -996,6 +1058,7 @@ PlanKnobs dump_knobs(const qs_plan* plan, int k) {
   kn.one_op_per_pass = plan->opts.plain != 0;
   if (plan->opts.max_stages > 0) kn.max_stages = std::min(plan->opts.max_stages, kMaxStages);
   if (plan->opts.min_tile_bits > 0) kn.min_tile_bits = plan->opts.min_tile_bits;
+  kn.exchange = plan->opts.no_exchange == 0;
   return kn;
 }
 
@@ -1044,7 +1107,7 @@ qs_status qs_partition(const qs_circuit* circ, uint64_t upper_mask, const qs_opt
     p->opts.materialize_level = -1;
   }
   if (p->opts.tile_bits < 0 || p->opts.coalesce_bits < 0 || p->opts.tail_max_qubits < 0 ||
-      p->opts.max_stages < 0 || p->opts.min_tile_bits < 0)
+      p->opts.max_stages < 0 || p->opts.min_tile_bits < 0 || p->opts.no_exchange < 0)
     return fail(QS_ERR_ARG, "negative option");
   if ((p->opts.alloc.alloc == nullptr) != (p->opts.alloc.free == nullptr))
     return fail(QS_ERR_ARG, "allocator needs both alloc and free");
@@ -1615,9 +1678,9 @@ qs_status qs_get_timing(qs_plan* plan, double* out10) {
     HIPCHECK(hipEventSynchronize(e.b));
     float ms = 0;
     HIPCHECK(hipEventElapsedTime(&ms, e.a, e.b));
-    const double rec[7] = {(double)e.side, (double)e.pass, (double)e.level_in, (double)e.stages,
-                           (double)e.tiles, e.bytes, (double)ms};
-    plan->pass_log.insert(plan->pass_log.end(), rec, rec + 7);
+    const double rec[8] = {(double)e.side, (double)e.pass, (double)e.level_in, (double)e.stages,
+                           (double)e.tiles, e.bytes, (double)ms, (double)e.passes};
+    plan->pass_log.insert(plan->pass_log.end(), rec, rec + 8);
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
   }
@@ -1649,9 +1712,9 @@ qs_status qs_get_pass_timing(qs_plan* plan, double* out, size_t cap_records, siz
   double fam[11];
   const qs_status st = qs_get_timing(plan, fam);
   if (st != QS_OK) return st;
-  const size_t n = plan->pass_log.size() / 7;
+  const size_t n = plan->pass_log.size() / 8;
   const size_t k = std::min(n, cap_records);
-  if (k) std::memcpy(out, plan->pass_log.data(), k * 7 * sizeof(double));
+  if (k) std::memcpy(out, plan->pass_log.data(), k * 8 * sizeof(double));
   *n_records = n;
   return QS_OK;
 }

@@ -17,6 +17,12 @@ hipError_t launch_pass(const PassDesc& h_desc, const PassDesc* d_desc, const Dev
                        const float2* in, float2* out, uint64_t n_in_nodes, const uint32_t* tlist,
                        uint32_t n_list, hipStream_t st);
 
+// The passes of one exchange group (XPassDesc) in one launch, in place on
+// `state` (nodes states of 2^n amplitudes); d_pds points at the plan's
+// PassDesc array (the group's passes from h.pd0).
+hipError_t launch_xpass(const XPassDesc& h, const XPassDesc* d_desc, const PassDesc* d_pds,
+                        const DevOp* d_ops, float2* state, uint64_t nodes, hipStream_t st);
+
 // Light-cone leaf evaluation for the requested values s0 .. s0+ns-1: the
 // backward rows into W (tail_w_bytes(h, ns) bytes), then the contraction with
 // the materialised node states into X[k * ldx + s_index].

@@ -598,6 +598,125 @@ k_wpass(const PassDesc* __restrict__ pdp, const DevOp* __restrict__ ops, const f
   }
 }
 
+// ------------------------------------------------------------------ exchange group
+//
+// k_xpass: the passes of an exchange group (XPassDesc) as phases of one
+// launch.  A workgroup of kXWaves waves owns the amplitudes of one node whose
+// bits outside the lanes and U are fixed (2^(6 + R + kXWaveBits) of them).  In
+// phase p each wave holds a wave tile of that pass (lanes: state bits 0..5,
+// registers: the pass's R register bits) at its own combination of the other
+// bits of U, applies the pass's ops, and writes the tile to LDS at position
+// (bits of U, compressed) 64 + lane; after a barrier the next phase reads it
+// back in its own split.  Phase 0 reads HBM (or starts from the product
+// state), the last phase writes HBM: one read and one write for the group.
+// Each phase's op list is staged in LDS when it fits.
+constexpr int kXWaves = 1 << kXWaveBits;
+constexpr int kXThreads = 64 * kXWaves;
+constexpr int kXOpsBytes = 14 * 1024;
+
+template <int R>
+__global__ void __launch_bounds__(kXThreads)
+k_xpass(const XPassDesc* __restrict__ xdp, const PassDesc* __restrict__ pds,
+        const DevOp* __restrict__ ops, float2* state) {
+  constexpr int E = 1 << R;
+  constexpr int T = 6 + R + kXWaveBits;
+  __shared__ __attribute__((aligned(16))) float2 xt[1 << T];
+  __shared__ __attribute__((aligned(16))) uint2 xops[kXOpsBytes / sizeof(uint2)];
+  __shared__ float2 tab[kPhaseEntries];
+  const XPassDesc& X = *xdp;
+  const uint32_t lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t wt = blockIdx.x;
+  const int nouter = X.n_outer;
+  const uint64_t node = wt >> nouter;
+  const uint64_t tile = wt & ((1ull << nouter) - 1);
+  uint32_t xo = 0;
+  for (int j = 0; j < nouter; ++j) xo |= (uint32_t)((tile >> j) & 1) << X.obit[j];
+  xo = __builtin_amdgcn_readfirstlane(xo);
+  float2* row = state + node * (1ull << X.n);
+  float2 v[E];
+  for (int p = 0; p < X.G; ++p) {
+    const PassDesc& P = pds[X.pd0 + p];
+    uint32_t RB[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) RB[k] = 1u << P.tbit[6 + k];
+    // this wave's bits of U outside the pass's registers, and its LDS offset
+    uint32_t wb = 0, wpos = 0;
+#pragma unroll
+    for (int j = 0; j < kXWaveBits; ++j)
+      if ((wave >> j) & 1) {
+        wb |= 1u << X.ubit[X.wpos[p][j]];
+        wpos |= 1u << X.wpos[p][j];
+      }
+    const uint32_t F = xo | wb | lane;
+    // the phase's ops: staged in LDS when they fit
+    const int nw = P.n_in * (int)(sizeof(DevOp) / sizeof(uint2));
+    const bool staged = nw <= (int)(kXOpsBytes / sizeof(uint2));
+    if (staged) {
+      const uint2* src = (const uint2*)(ops + P.op_in);
+      for (int i = threadIdx.x; i < nw; i += kXThreads) xops[i] = src[i];
+    }
+    if (p == 0) {
+      if (X.init) {
+        const uint32_t hmask = ~(uint32_t)P.hinit;
+        const float h = P.hamp;
+        const bool lane_ok = (F & hmask) == 0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const bool ok = lane_ok && (reg_index<R>(r, RB) & hmask) == 0;
+          v[r] = ok ? make_float2(h, 0.f) : make_float2(0.f, 0.f);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < E; ++r) v[r] = (row + (xo | wb | reg_index<R>(r, RB)))[lane];
+      }
+      init_phase_table(tab);  // and the barrier after the staging
+    } else {
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        uint32_t u = wpos;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+          if ((r >> k) & 1) u |= 1u << X.rpos[p][k];
+        v[r] = xt[(u << 6) | lane];
+      }
+      __syncthreads();  // ops staged, and every wave has read its tile
+    }
+    wave_apply_ops<R>(v, staged ? (const DevOp*)xops : ops + P.op_in, P.n_in, F, RB, (int)lane,
+                      tab);
+    const float sc = P.scale;
+    if (p + 1 < X.G) {
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        uint32_t u = wpos;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+          if ((r >> k) & 1) u |= 1u << X.rpos[p][k];
+        xt[(u << 6) | lane] = make_float2(v[r].x * sc, v[r].y * sc);
+      }
+      __syncthreads();  // the tile is in LDS, and every wave is done with the staged ops
+    } else {
+      wave_store<R>(row, v, sc, xo | wb, lane, RB, X.nt);
+    }
+  }
+}
+
+hipError_t launch_xpass(const XPassDesc& h, const XPassDesc* d_desc, const PassDesc* d_pds,
+                        const DevOp* d_ops, float2* state, uint64_t nodes, hipStream_t st) {
+  if (h.G < 2 || h.G > kMaxXPhases || h.nu != h.R + kXWaveBits || 6 + h.nu + h.n_outer != h.n)
+    return hipErrorInvalidValue;
+  const uint64_t blocks = nodes << h.n_outer;
+  if (blocks == 0 || blocks > 0x7fffffffull) return hipErrorInvalidValue;
+  dim3 g((unsigned)blocks), b(kXThreads);
+  switch (h.R) {
+    case 3: hipLaunchKernelGGL(k_xpass<3>, g, b, 0, st, d_desc, d_pds, d_ops, state); break;
+    case 4: hipLaunchKernelGGL(k_xpass<4>, g, b, 0, st, d_desc, d_pds, d_ops, state); break;
+    case 5: hipLaunchKernelGGL(k_xpass<5>, g, b, 0, st, d_desc, d_pds, d_ops, state); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <int R>
 static hipError_t launch_wpass_r(int S, dim3 g, dim3 b, size_t lds, hipStream_t st,
                                  const PassDesc* d_desc, const DevOp* d_ops, const float2* in,

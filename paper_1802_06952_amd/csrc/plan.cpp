@@ -279,6 +279,7 @@ struct PassPacker {
   int ls, t, tmin, b, max_stages;
   bool one_op;
   const std::vector<uint64_t>& nodes;
+  bool exchange;
   struct Res {
     double cost = 0;
     size_t peak = 1;
@@ -302,6 +303,7 @@ struct PassPacker {
       std::vector<int> deferred;
       int budget = kMaxPassOps;
       absorb(s, P, S, t, pp.ops_in, deferred, one_op, budget);
+      if (!deferred.empty() && try_group(pp, P, r)) continue;
       P = deferred;
       const bool open = deferred.empty() && !(one_op && !pp.ops_in.empty());
       if (!open || cur == ls) {
@@ -345,6 +347,65 @@ struct PassPacker {
     return r;
   }
 
+  // Exchange group instead of the pass pp: gates are taken into a workgroup
+  // tile of kXWaveBits more bits (U: its non-lane bits), and the taken
+  // sequence splits into phases of at most R = t - 6 non-lane targets each;
+  // consecutive phases exchange the tile through LDS (k_xpass), so the group
+  // reads and writes the states once.  Used when the wide tile still leaves
+  // ops for a later pass (the group never ends a level's schedule) and takes
+  // more ops than the plain pass; emits the phases into r and leaves the
+  // deferred ops in P.
+  bool try_group(const PassPlan& pp, std::vector<int>& P, Res& r) const {
+    const int R = t - b;
+    if (!exchange || one_op || b != 6 || R < kXMinRegBits || t + kXWaveBits > s.n) return false;
+    std::vector<int> SX;
+    for (int q = 0; q < b; ++q) SX.push_back(q);
+    std::vector<int> taken, def;
+    int budget = kMaxPassOps;
+    absorb(s, P, SX, t + kXWaveBits, taken, def, one_op, budget);
+    if (def.empty() || taken.size() <= pp.ops_in.size()) return false;
+    // phases: the longest runs of the taken sequence with at most R non-lane targets
+    std::vector<std::vector<int>> ph(1), regs(1);
+    for (int i : taken) {
+      const HOp& o = s.ops[i];
+      if (o.kind == OP_MAT && o.q0 >= b &&
+          std::find(regs.back().begin(), regs.back().end(), o.q0) == regs.back().end()) {
+        if ((int)regs.back().size() == R) {
+          ph.emplace_back();
+          regs.emplace_back();
+        }
+        regs.back().push_back(o.q0);
+      }
+      ph.back().push_back(i);
+    }
+    if (ph.size() < 2 || ph.size() > (size_t)kMaxXPhases) return false;
+    std::vector<int> U(SX.begin() + b, SX.end());
+    for (int q = b; (int)U.size() < R + kXWaveBits && q < s.n; ++q)
+      if (std::find(U.begin(), U.end(), q) == U.end()) U.push_back(q);
+    std::sort(U.begin(), U.end());
+    for (size_t k = 0; k < ph.size(); ++k) {
+      PassPlan g;
+      g.level_in = pp.level_in;
+      g.init = pp.init && k == 0;
+      g.ops_in = ph[k];
+      std::vector<int> T = regs[k];
+      for (int q : U)
+        if ((int)T.size() < R && std::find(T.begin(), T.end(), q) == T.end()) T.push_back(q);
+      for (int q = 0; q < b; ++q) T.push_back(q);
+      std::sort(T.begin(), T.end());
+      g.tile = T;
+      g.xg = k == 0 ? (int)ph.size() : 0;
+      if (k == 0) g.xu = U;
+      r.passes.push_back(g);
+    }
+    // price: one read and one write of the states, the phases' arithmetic
+    PassPlan whole = pp;
+    whole.ops_in = taken;
+    price_pass(s, whole, nodes, r.cost, r.peak);
+    P = def;
+    return true;
+  }
+
   // fill the tile with the lowest unused qubits up to tmin bits (a tile holds
   // at least the pass's targets; a smaller tile means fewer registers per
   // lane and more wavefronts in flight)
@@ -357,10 +418,11 @@ struct PassPacker {
 };
 
 void build_passes(const Side& s, const Tree& tree, int ls, int t, int tmin, int b, bool one_op,
-                  int max_stages, const std::vector<uint64_t>& nodes,
+                  int max_stages, bool exchange, const std::vector<uint64_t>& nodes,
                   std::vector<PassPlan>& passes, double& cost, size_t& peak) {
   PassPacker pk{s, tree, ls, t, std::min(t, tmin), b,
-                one_op ? 1 : std::max(1, std::min(max_stages, kMaxStages)), one_op, nodes, {}};
+                one_op ? 1 : std::max(1, std::min(max_stages, kMaxStages)), one_op, nodes, exchange,
+                {}};
   PassPacker::Res r = pk.solve(0, tree.levels[0].ops, true);
   passes = std::move(r.passes);
   cost = r.cost;
@@ -412,8 +474,8 @@ bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, Side
     if (nlev > kMaxTailLevels || M > 16) continue;
     double cost = 0;
     size_t peak = 1;
-    build_passes(s, tree, ls, t, tmin, b, kn.one_op_per_pass, kn.max_stages, nodes, sp.passes, cost,
-                 peak);
+    build_passes(s, tree, ls, t, tmin, b, kn.one_op_per_pass, kn.max_stages, kn.exchange, nodes,
+                 sp.passes, cost, peak);
     // leaf evaluation: the backward rows per requested value (arithmetic and
     // the W round trip), the contiguous gathers of the node amplitudes (the
     // light cone is relabelled onto the lowest state bits), and the per-value
@@ -465,8 +527,8 @@ bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, Side
   {
     double cost = 0;
     size_t peak = 1;
-    build_passes(r, best.tree, best.lstar, t, tmin, b, kn.one_op_per_pass, kn.max_stages, best.nodes,
-                 best.passes, cost, peak);
+    build_passes(r, best.tree, best.lstar, t, tmin, b, kn.one_op_per_pass, kn.max_stages,
+                 kn.exchange, best.nodes, best.passes, cost, peak);
   }
   out = std::move(best);
   return true;
@@ -694,7 +756,7 @@ std::string dump_json(const Circuit& c, uint64_t upper_mask, const std::vector<C
       for (size_t p = 0; p < sp->passes.size(); ++p) {
         const PassPlan& pp = sp->passes[p];
         o << (p ? "," : "") << "{\"level_in\":" << pp.level_in << ",\"init\":" << (pp.init ? 1 : 0)
-          << ",\"branch\":" << pp.stages.size() << ",\"ops_in\":[";
+          << ",\"branch\":" << pp.stages.size() << ",\"xg\":" << pp.xg << ",\"ops_in\":[";
         for (size_t i = 0; i < pp.ops_in.size(); ++i) o << (i ? "," : "") << pp.ops_in[i];
         o << "],\"stages\":[";
         for (size_t st = 0; st < pp.stages.size(); ++st) {

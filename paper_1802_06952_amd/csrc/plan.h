@@ -55,6 +55,12 @@ struct PassPlan {
   std::vector<int> ops_in;
   std::vector<std::vector<int>> stages;
   std::vector<int> tile;  // local qubits of the tile, ascending
+  // Exchange groups: consecutive passes without a branch that run as the
+  // phases of one launch on workgroup tiles (group_passes).  xg: passes of the
+  // group that starts here (1: a pass of its own, 0: covered by an earlier
+  // pass); xu (first pass of a group): the tile's non-lane state bits, ascending.
+  int xg = 1;
+  std::vector<int> xu;
   bool branch() const { return !stages.empty(); }
   int level_out() const { return level_in + (int)stages.size(); }
 };
@@ -81,6 +87,7 @@ struct PlanKnobs {
   int S = 1;              // requested values of this half (for the cost model)
   bool one_op_per_pass = false;  // flat comparison form: every half op is its own pass
   int max_stages = kMaxStages;   // tree levels one pass may descend (1 = one level per pass)
+  bool exchange = true;          // merge runs of passes into exchange groups
 };
 
 bool plan_side(const Side& s, int c, const Block& blk, const PlanKnobs& kn, SidePlan& out,

@@ -157,6 +157,32 @@ struct PassDesc {
   float scale;       // exact power of two applied at the store (keeps unit-entry gates in range)
 };
 
+// Exchange groups of passes (PassPlan::xg): wave bits per workgroup, the
+// most passes per group, and the fewest register bits of a grouped pass.
+constexpr int kXWaveBits = 3;
+constexpr int kMaxXPhases = 8;
+constexpr int kXMinRegBits = 3;
+
+// One launch of an exchange group: G consecutive passes (PassDescs pd0 ..
+// pd0 + G - 1, no branch stages, R register bits each) on workgroup tiles of
+// 6 lane bits and the nu = R + kXWaveBits state bits ubit[] (ascending); the
+// other state bits obit[] are fixed per workgroup.  In phase p, register bit k
+// of the pass is bit rpos[p][k] of U and wave bit j is bit wpos[p][j] of U.
+struct XPassDesc {
+  int G;
+  int pd0;
+  int R;
+  int n;
+  int nu;
+  int ubit[kMaxRegBits + kXWaveBits];
+  int n_outer;
+  int obit[64];
+  int rpos[kMaxXPhases][kMaxRegBits];
+  int wpos[kMaxXPhases][kXWaveBits];
+  int init;  // phase 0 starts from the product state (PassDesc::init of the first pass)
+  int nt;    // streaming stores (the last pass's setting)
+};
+
 struct TailLevel {
   int m;                 // cut bits decided at this level
   int bq[kMaxBranch];    // state bit of each cut qubit (bit 0 = MSB of b)

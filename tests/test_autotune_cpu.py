@@ -19,6 +19,7 @@ def test_knob_grid_defaults_first():
     assert v["materialize_level"][0] == -1
     assert sorted(v["materialize_level"][1:]) == [5, 6, 7, 8]
     assert v["tail_max_qubits"] == [10, 8]
+    assert v["no_exchange"] == [0, 1]
 
 
 def test_knob_grid_span_not_power_of_two():
@@ -50,7 +51,7 @@ def test_committed_cache_is_well_formed():
     for name, e in store.items():
         assert len(e["key"]) == 24
         assert set(e["opts"]) <= {"tile_bits", "max_stages", "copies_per_launch",
-                                  "materialize_level", "tail_max_qubits"}
+                                  "materialize_level", "tail_max_qubits", "no_exchange"}
         assert e["ms"] <= e["default_ms"] + 1e-9
 
 
@@ -71,7 +72,7 @@ def test_coordinate_descent_finds_separable_minimum(monkeypatch):
     """With a cost that is a sum of per-knob terms, one sweep of coordinate
     descent reaches the global minimum of the grid."""
     best = {"tile_bits": 9, "max_stages": 1, "copies_per_launch": 0,
-            "materialize_level": 4, "tail_max_qubits": 8}
+            "materialize_level": 4, "tail_max_qubits": 8, "no_exchange": 1}
 
     def cost(text, mask, bits, k0, k1, opts, reps, stream):
         return 1.0 + sum(0.1 * (opts[k] != v) for k, v in best.items())
@@ -81,10 +82,11 @@ def test_coordinate_descent_finds_separable_minimum(monkeypatch):
     r = at.autotune("c", 1, np.zeros(4, dtype=np.uint64), 0, 16)
     assert r["opts"] == best
     assert r["ms"] == pytest.approx(1000.0)
-    assert r["default_ms"] == pytest.approx(1000.0 + 400.0)
+    assert r["default_ms"] == pytest.approx(1000.0 + 500.0)
     # every tried set is recorded once, the default first
     assert r["tried"][0]["opts"] == {"tile_bits": 10, "max_stages": 2, "copies_per_launch": 0,
-                                     "materialize_level": -1, "tail_max_qubits": 10}
+                                     "materialize_level": -1, "tail_max_qubits": 10,
+                                     "no_exchange": 0}
     assert len({json.dumps(t["opts"], sort_keys=True) for t in r["tried"]}) == len(r["tried"])
 
 

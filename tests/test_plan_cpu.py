@@ -342,6 +342,66 @@ def test_multi_level_passes_are_used():
         assert len(written) < s2["lstar"]
 
 
+X_WAVE_BITS = 3  # wave bits of an exchange group's workgroup tile
+
+
+@pytest.mark.parametrize("name,knobs", [
+    ("grid6x7_d20", {}),
+    ("grid6x6_d16", {"tile_bits": 9}),
+    ("grid8x8_d22_slice64", {"tile_bits": 11}),
+])
+def test_exchange_groups_are_well_formed(name, knobs):
+    """Every exchange group in the dump: consecutive phases without a branch
+    on one level, each phase's tile is the six lane bits plus R register bits
+    of the group's R + 3 bits, every 2x2 gate of a phase acts on its tile, the
+    first phase alone may start from the product state, and no group ends a
+    side's schedule.  With no_exchange every pass stands alone and the ops are
+    the same, in the same order."""
+    from workloads import workload
+    w = workload(name)
+    p = Q.Plan(w.circuit_text(), w.upper_mask, **knobs)
+    k1 = w.copy_end if w.copy_end is not None else (1 << p.n_cuts)
+    d = p.dump(w.copy_begin, k1)
+    p.close()
+    q = Q.Plan(w.circuit_text(), w.upper_mask, no_exchange=True, **knobs)
+    d0 = q.dump(w.copy_begin, k1)
+    q.close()
+    groups = 0
+    for s, s0 in zip(d["sides"], d0["sides"]):
+        ps = s["passes"]
+        assert all(pp["xg"] == 1 for pp in s0["passes"])
+        flat = [i for pp in ps for st in [pp["ops_in"]] + pp["stages"] for i in st]
+        flat0 = [i for pp in s0["passes"] for st in [pp["ops_in"]] + pp["stages"] for i in st]
+        assert sorted(flat) == sorted(flat0)
+        assert ps[-1]["xg"] == 1
+        i = 0
+        while i < len(ps):
+            G = ps[i]["xg"]
+            assert G >= 1
+            if G == 1:
+                i += 1
+                continue
+            groups += 1
+            R = len(ps[i]["tile"]) - 6
+            U = set()
+            for k in range(i, i + G):
+                pp = ps[k]
+                assert pp["xg"] == (G if k == i else 0)
+                assert pp["branch"] == 0 and pp["level_in"] == ps[i]["level_in"]
+                assert pp["init"] == (k == 0 and ps[i]["init"] == 1) or pp["init"] == 0
+                t = pp["tile"]  # local qubit ids; perm gives their state bits
+                tb = sorted(s["perm"][x] for x in t)
+                assert tb[:6] == list(range(6)) and len(tb) == 6 + R and len(set(tb)) == len(tb)
+                U |= set(tb[6:])
+                for op in pp["ops_in"]:
+                    o = s["ops"][op]
+                    if o[0] in ("h", "sx", "sy"):
+                        assert o[1] in t
+            assert len(U) <= R + X_WAVE_BITS
+            i += G
+    assert groups >= 1
+
+
 @pytest.mark.parametrize("rows,cols,depth,two_qubit,mask", [
     (4, 4, 12, "cx", W.grid_rows_mask(4, 4, [0, 1])),
     (4, 4, 14, "cy", W.grid_rows_mask(4, 4, [0])),

@@ -1833,6 +1833,178 @@ k_zgemm_nt_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int 
       }
 }
 
+// k_zgemm_nt_f32d: the same FP32 product with the operand tiles copied from
+// HBM straight into a ring of kF32Stages LDS buffers (global_load_lds_dwordx4,
+// no staging registers), so that the loads of step k + 2 are in flight while
+// step k is multiplied.  A tile is row-major over the copy index (kFK complex
+// values, 128 bytes a row); 16-byte chunk c of row r (copies 2c, 2c + 1) sits
+// at position c ^ ((r >> 1) & 7), so that the sixteen rows of a fragment read
+// fall on different banks.  A lane reads one chunk per tile row it feeds and
+// uses its two copies in two MFMA steps (lane group g takes copies 2g and
+// 2g + 1 of each eight-copy block).  Even K only (16-byte loads of complex
+// pairs); grouped and plain forms as k_zgemm_nt_f32.
+constexpr int kF32Stages = 3;
+constexpr int kFRowBytes = kFK * 8;
+
+__device__ __forceinline__ int f32_pos(int row, int c) { return c ^ ((row >> 1) & 7); }
+
+// Rows row0 .. row0 + ROWS - 1 of src (rows of length K; rows past `rows` read
+// the last row), copies k0 .. k0 + kFK - 1 (chunks past K read the row's first
+// chunk: valid addresses, zeroed when the fragments are read).  Instruction j
+// of wave w fills the 1 KB segment j * 4 + w (eight rows).
+template <int ROWS>
+__device__ __forceinline__ void f32_stage(const float2* __restrict__ src, size_t ld, int row0,
+                                          int rows, int k0, int K, char* tile, int wave,
+                                          int lane) {
+  constexpr int PER = ROWS * (kFRowBytes / 16) / kGemmThreads;
+  static_assert(PER >= 1 && ROWS * (kFRowBytes / 16) % kGemmThreads == 0, "staging map");
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int seg = j * (kGemmThreads / 64) + wave;
+    const int r = seg * 8 + (lane >> 3);
+    const int c = f32_pos(r, lane & 7);
+    const int gr = min(row0 + r, rows - 1);
+    const int k = k0 + 2 * c + 1 < K ? k0 + 2 * c : 0;
+    __builtin_amdgcn_global_load_lds(src + (size_t)gr * ld + k,
+                                     (__attribute__((address_space(3))) void*)(tile + seg * 1024),
+                                     16, 0, 0);
+  }
+}
+
+template <int TM, int TN>
+__global__ void __launch_bounds__(kGemmThreads)
+k_zgemm_nt_f32d(int M, int N, int K, int kper, const float2* __restrict__ A, int lda,
+                const float2* __restrict__ B, int ldb, float2* __restrict__ out, int ldo,
+                size_t split_stride, const int* __restrict__ goff, int nsplit, size_t a_gstride) {
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int ABYTES = BM * kFRowBytes, BBYTES = BN * kFRowBytes;
+  // loads per thread per step: one 16-byte chunk each
+  constexpr int LPT = (BM + BN) * (kFRowBytes / 16) / kGemmThreads;
+  static_assert(LPT == 6, "the wait count below assumes six loads per step");
+  // one array per stage, so that the compiler can tell a stage's reads from
+  // the other stages' loads in flight
+  __shared__ __attribute__((aligned(16))) char ring0[ABYTES + BBYTES];
+  __shared__ __attribute__((aligned(16))) char ring1[ABYTES + BBYTES];
+  __shared__ __attribute__((aligned(16))) char ring2[ABYTES + BBYTES];
+  static_assert(kF32Stages == 3, "three stage arrays");
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  int bx, by, bz;
+  gemm_block(bx, by, bz);
+  if (goff) {
+    const int g = bz / nsplit;
+    bz -= g * nsplit;
+    const int c0 = goff[g];
+    N = goff[g + 1] - c0;
+    A += (size_t)g * a_gstride;
+    B += (size_t)c0 * ldb;
+    out += c0;
+  }
+  if (bx * BN >= N) return;  // a column tile past a group's end (the whole workgroup)
+  const int i_blk = by * BM, j_blk = bx * BN;
+  const int wi = (wave >> 1) * (16 * TM), wj = (wave & 1) * (16 * TN);
+  const int kb = bz * kper;
+  const int ke = min(K, kb + kper);
+  const int nk = ke > kb ? (ke - kb + kFK - 1) / kFK : 0;
+  floatx4 p1[TM][TN], p2[TM][TN], p3[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      p1[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+      p2[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+      p3[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+  auto issue = [&](int t, char* buf) {
+    f32_stage<BM>(A, (size_t)lda, i_blk, M, kb + t * kFK, K, buf, wave, lane);
+    f32_stage<BN>(B, (size_t)ldb, j_blk, N, kb + t * kFK, K, buf + ABYTES, wave, lane);
+  };
+  if (nk > 0) issue(0, ring0);
+  if (nk > 1) issue(1, ring1);
+  const int g = lane >> 4, li = lane & 15;
+  auto step = [&](int t, const char* buf, char* nxt) {
+    // this step's chunks have landed: this wave's (at most the next step's
+    // loads still in flight), then every wave's.  A bare s_barrier: the
+    // workgroup has no LDS writes of its own to order, and every wave's reads
+    // of the stage that the next loads overwrite were consumed before it got
+    // here (a fenced barrier would also wait for the next step's loads).
+    if (t + 1 < nk)
+      asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (t + 2 < nk) issue(t + 2, nxt);
+    const int kvalid = min(kFK, ke - (kb + t * kFK));
+#pragma unroll
+    for (int kk = 0; kk < kFK; kk += 8) {
+      float4 av[TM], bv[TN];
+      const int c = kk / 2 + g;
+#pragma unroll
+      for (int a = 0; a < TM; ++a) {
+        const int r = wi + a * 16 + li;
+        av[a] = *(const float4*)(buf + r * kFRowBytes + 16 * f32_pos(r, c));
+      }
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        const int r = wj + b * 16 + li;
+        bv[b] = *(const float4*)(buf + ABYTES + r * kFRowBytes + 16 * f32_pos(r, c));
+      }
+      if (kvalid < kFK) {
+        // copies past this split's end (or past K) are zero
+        const int k = kk + 2 * g;
+        const bool z0 = k >= kvalid, z1 = k + 1 >= kvalid;
+#pragma unroll
+        for (int a = 0; a < TM; ++a) {
+          if (z0) av[a].x = av[a].y = 0.f;
+          if (z1) av[a].z = av[a].w = 0.f;
+        }
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          if (z0) bv[b].x = bv[b].y = 0.f;
+          if (z1) bv[b].z = bv[b].w = 0.f;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          p1[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[b].x, p1[a][b], 0, 0, 0);
+          p2[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].y, bv[b].y, p2[a][b], 0, 0, 0);
+          p3[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x + av[a].y, bv[b].x + bv[b].y,
+                                                          p3[a][b], 0, 0, 0);
+        }
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          p1[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].z, bv[b].z, p1[a][b], 0, 0, 0);
+          p2[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].w, bv[b].w, p2[a][b], 0, 0, 0);
+          p3[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].z + av[a].w, bv[b].z + bv[b].w,
+                                                          p3[a][b], 0, 0, 0);
+        }
+    }
+  };
+  for (int t = 0; t < nk; t += 3) {
+    step(t, ring0, ring2);
+    if (t + 1 < nk) step(t + 1, ring1, ring0);
+    if (t + 2 < nk) step(t + 2, ring2, ring1);
+  }
+  float2* o = out + (size_t)bz * split_stride;
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = i_blk + wi + a * 16 + 4 * (lane >> 4) + e;
+        const int j = j_blk + wj + b * 16 + (lane & 15);
+        if (i < M && j < N)
+          o[(size_t)i * ldo + j] = make_float2(p1[a][b][e] - p2[a][b][e],
+                                               p3[a][b][e] - p1[a][b][e] - p2[a][b][e]);
+      }
+}
+
 // C[i][j] = (accumulate ? C[i][j] : 0) + sum over splits of P[z][i][j], in split order.
 // (column j goes to C column cmap[j] when cmap is given)
 __global__ void k_zgemm_reduce(int M, int N, int splits, const float2* __restrict__ P,
@@ -2266,8 +2438,12 @@ hipError_t launch_zgemm_grouped(int M, int Ntot, int maxn, int K, int ngroups, c
   float2* P = (float2*)work;
   dim3 grid((maxn + g.bn - 1) / g.bn, (M + g.bm - 1) / g.bm, ngroups * g.splits);
   if (grid.z > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_zgemm_nt_f32<4, kGroupTN>), grid, dim3(kGemmThreads), 0, st, M, Ntot, K,
-                     g.kper, A, K, B, K, P, Ntot, ss, d_goff, g.splits, a_gstride);
+  if (K & 1)
+    hipLaunchKernelGGL((k_zgemm_nt_f32<4, kGroupTN>), grid, dim3(kGemmThreads), 0, st, M, Ntot, K,
+                       g.kper, A, K, B, K, P, Ntot, ss, d_goff, g.splits, a_gstride);
+  else
+    hipLaunchKernelGGL((k_zgemm_nt_f32d<4, kGroupTN>), grid, dim3(kGemmThreads), 0, st, M, Ntot, K,
+                       g.kper, A, K, B, K, P, Ntot, ss, d_goff, g.splits, a_gstride);
   hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((ss + 255) / 256)), dim3(256), 0, st, M, Ntot,
                      g.splits, P, ss, C, ldc, accumulate, cmap);
   return hipGetLastError();

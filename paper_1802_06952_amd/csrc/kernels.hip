@@ -1833,6 +1833,12 @@ k_zgemm_nt_f32(int M, int N, int K, int kper, const float2* __restrict__ A, int 
       }
 }
 
+// s_waitcnt immediates (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt in
+// 6:4, lgkmcnt in 11:8): wait until at most n vector memory operations of this
+// wave are outstanding, whatever the other counters.  Issued through the
+// builtin, so that the compiler's own wait insertion knows they happened.
+constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+
 // k_zgemm_nt_f32d: the same FP32 product with the operand tiles copied from
 // HBM straight into a ring of kF32Stages LDS buffers (global_load_lds_dwordx4,
 // no staging registers), so that the loads of step k + 2 are in flight while
@@ -1929,9 +1935,9 @@ k_zgemm_nt_f32d(int M, int N, int K, int kper, const float2* __restrict__ A, int
     // of the stage that the next loads overwrite were consumed before it got
     // here (a fenced barrier would also wait for the next step's loads).
     if (t + 1 < nk)
-      asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+      __builtin_amdgcn_s_waitcnt(waitcnt_vm(LPT));
     else
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
     if (t + 2 < nk) issue(t + 2, nxt);
@@ -2063,27 +2069,32 @@ __device__ __forceinline__ void split2(float a, float b, uint32_t& hi, uint32_t&
 // on sixteen different bank groups.
 constexpr int kRowBytes = kBK * 8;
 constexpr int kTileBytes = kGBM * kRowBytes;
+// Waves of the split-BF16 product: 2 x 4 waves of 64 x 32 outputs each, two
+// waves per SIMD (a 64 x 64 wave tile needs more than 256 registers)
+constexpr int kBfWaves = 8;
+constexpr int kBfThreads = 64 * kBfWaves;
 
 __device__ __forceinline__ int chunk_pos(int row, int chunk) { return chunk ^ (row & 15); }
 
 // One operand tile, rows row0 .. row0 + 127 of src (row length K), copy
-// indices k0 .. k0 + kBK - 1.  Wave w loads tile rows 32 w .. 32 w + 31, four
-// rows per instruction (64 lanes x 16 bytes: lane l covers row 4 j + l / 16 at
-// position l % 16).  Rows past `rows` read the last row and chunks past K the
+// indices k0 .. k0 + kBK - 1.  Wave w of the product's kBfWaves loads tile rows
+// 16 w .. 16 w + 15, four rows per instruction (64 lanes x 16 bytes: lane l
+// covers row 4 j + l / 16 at position l % 16).  Rows past `rows` read the last row and chunks past K the
 // row's first chunk (valid addresses; the first give outputs that are not
 // stored, the second are zeroed when the fragments are read).
 __device__ __forceinline__ void stage_tile(const float2* __restrict__ src, size_t ld, int row0,
                                            int rows, int k0, int K, char* tile, int wave,
                                            int lane) {
   const int pos = lane & 15;
+  constexpr int RW = kGBM / kBfWaves;  // rows per wave
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int r = 32 * wave + 4 * j + (lane >> 4);
+  for (int j = 0; j < RW / 4; ++j) {
+    const int r = RW * wave + 4 * j + (lane >> 4);
     const int gr = min(row0 + r, rows - 1);
     const int c = pos ^ (r & 15);
     const int k = k0 + 2 * c + 1 < K ? k0 + 2 * c : 0;
     const float2* g = src + (size_t)gr * ld + k;
-    char* l = tile + (32 * wave + 4 * j) * kRowBytes;
+    char* l = tile + (RW * wave + 4 * j) * kRowBytes;
     __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)l, 16, 0, 0);
   }
 }
@@ -2123,19 +2134,24 @@ __device__ __forceinline__ void frag_planes(const char* tile, int row, int g, in
 }
 
 // C (M x N) = A B^T over the copy index, split-BF16: A[(a_row0 + i) * lda + k],
-// B[j * ldb + k], both FP32 complex.  Tiles of 128 x 128 (four waves of
-// 64 x 64), k in steps of kBK, the copy index split over blockIdx.z as for the
+// B[j * ldb + k], both FP32 complex.  Tiles of 128 x 128 (eight waves of
+// 64 x 32), k in steps of kBK, the copy index split over blockIdx.z as for the
 // FP32 product (partials reduced by k_zgemm_reduce).  The next step's tiles
 // load into the second LDS buffer while the MFMAs consume the current one.
 // Grouped form (goff != nullptr): blockIdx.z = group * nsplit + split; group
 // g takes the columns goff[g] .. goff[g+1]-1 (B rows, and the columns of the
 // partial product) and A rows g * a_grows .. (its M rows); blockIdx.x counts
 // the group's column tiles.  Plain form: blockIdx.z is the split.
-__global__ void __launch_bounds__(kGemmThreads)
+__global__ void __launch_bounds__(kBfThreads)
 k_zgemm_nt_bf16x3(int M, int N, int K, int kper, const float2* __restrict__ A, int lda,
                   const float2* __restrict__ B, int ldb, float2* __restrict__ out, int ldo,
                   size_t split_stride, const int* __restrict__ goff, int nsplit, int a_grows) {
-  __shared__ __attribute__((aligned(16))) char tiles[2][2][kTileBytes];  // [buffer][A, B]
+  // [A, B] of each buffer, one array per buffer: the compiler then keeps the
+  // next step's loads in flight while this step's tiles are read
+  __shared__ __attribute__((aligned(16))) char tA0[kTileBytes];
+  __shared__ __attribute__((aligned(16))) char tB0[kTileBytes];
+  __shared__ __attribute__((aligned(16))) char tA1[kTileBytes];
+  __shared__ __attribute__((aligned(16))) char tB1[kTileBytes];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   int bx, by, bz;
@@ -2150,40 +2166,40 @@ k_zgemm_nt_bf16x3(int M, int N, int K, int kper, const float2* __restrict__ A, i
     a_row0 = g * a_grows;
   }
   const int i_blk = by * kGBM;
-  const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
+  const int wi = (wave >> 2) * 64, wj = (wave & 3) * 32;
   const int kb = split * kper;
   const int ke = min(K, kb + kper);
   const float2* Ag = A + (size_t)a_row0 * lda;
-  floatx4 ar[4][4], ai[4][4];
+  floatx4 ar[4][2], ai[4][2];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < 2; ++b) {
       ar[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
       ai[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-  if (kb < ke) {
-    stage_tile(Ag, (size_t)lda, i_blk, M, kb, K, tiles[0][0], wave, lane);
-    stage_tile(B, (size_t)ldb, j_blk, jend, kb, K, tiles[0][1], wave, lane);
-  }
-  int buf = 0;
-  for (int k0 = kb; k0 < ke; k0 += kBK, buf ^= 1) {
-    // this step's tiles have landed (this wave's loads, then every wave's)
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-    if (k0 + kBK < ke) {
-      stage_tile(Ag, (size_t)lda, i_blk, M, k0 + kBK, K, tiles[buf ^ 1][0], wave, lane);
-      stage_tile(B, (size_t)ldb, j_blk, jend, k0 + kBK, K, tiles[buf ^ 1][1], wave, lane);
-    }
+  auto issue = [&](int k0, char* ta, char* tb) {
+    stage_tile(Ag, (size_t)lda, i_blk, M, k0, K, ta, wave, lane);
+    stage_tile(B, (size_t)ldb, j_blk, jend, k0, K, tb, wave, lane);
+  };
+  const int g = lane >> 4, lr = lane & 15;
+  auto step = [&](int k0, const char* ca, const char* cb, char* na, char* nb) {
+    // this step's tiles have landed (this wave's loads, then every wave's).
+    // A bare s_barrier: the workgroup writes LDS only through these loads, and
+    // every wave consumed its reads of the buffer the next loads overwrite
+    // before it got here.
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (k0 + kBK < ke) issue(k0 + kBK, na, nb);
     const int kvalid = min(kBK, ke - k0);
-    const int g = lane >> 4, lr = lane & 15;
     bf16x8 fa[4][4];  // [a tile][plane]
 #pragma unroll
-    for (int a = 0; a < 4; ++a) frag_planes(tiles[buf][0], wi + a * 16 + lr, g, kvalid, fa[a]);
+    for (int a = 0; a < 4; ++a) frag_planes(ca, wi + a * 16 + lr, g, kvalid, fa[a]);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < 2; ++b) {
       bf16x8 fb[4];
-      frag_planes(tiles[buf][1], wj + b * 16 + lr, g, kvalid, fb);
+      frag_planes(cb, wj + b * 16 + lr, g, kvalid, fb);
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         floatx4 r = ar[a][b], im = ai[a][b];
@@ -2204,12 +2220,17 @@ k_zgemm_nt_bf16x3(int M, int N, int K, int kper, const float2* __restrict__ A, i
         ai[a][b] = im;
       }
     }
+  };
+  if (kb < ke) issue(kb, tA0, tB0);
+  for (int k0 = kb; k0 < ke; k0 += 2 * kBK) {
+    step(k0, tA0, tB0, tA1, tB1);
+    if (k0 + kBK < ke) step(k0 + kBK, tA1, tB1, tA0, tB0);
   }
   float2* o = out + (size_t)split * split_stride;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int i = i_blk + wi + a * 16 + 4 * (lane >> 4) + e;
@@ -2391,7 +2412,7 @@ hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int l
       hipLaunchKernelGGL(k_zgemm_nt_bf16x3_reg, grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper, A,
                          lda, B, ldb, P, N, ss, (const int*)nullptr, g.splits, 0);
     else
-      hipLaunchKernelGGL(k_zgemm_nt_bf16x3, grid, dim3(kGemmThreads), 0, st, M, N, K, g.kper, A, lda,
+      hipLaunchKernelGGL(k_zgemm_nt_bf16x3, grid, dim3(kBfThreads), 0, st, M, N, K, g.kper, A, lda,
                          B, ldb, P, N, ss, (const int*)nullptr, g.splits, 0);
   }
   const size_t tot = ss;
@@ -2489,7 +2510,7 @@ hipError_t launch_zgemm_grouped_bf16(int M, int Ntot, int maxn, int K, int ngrou
     hipLaunchKernelGGL(k_zgemm_nt_bf16x3_reg, grid, dim3(kGemmThreads), 0, st, M, Ntot, K, g.kper, A,
                        K, B, K, P, Ntot, ss, d_goff, g.splits, M);
   else
-    hipLaunchKernelGGL(k_zgemm_nt_bf16x3, grid, dim3(kGemmThreads), 0, st, M, Ntot, K, g.kper, A, K,
+    hipLaunchKernelGGL(k_zgemm_nt_bf16x3, grid, dim3(kBfThreads), 0, st, M, Ntot, K, g.kper, A, K,
                        B, K, P, Ntot, ss, d_goff, g.splits, M);
   hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((ss + 255) / 256)), dim3(256), 0, st, M, Ntot,
                      g.splits, P, ss, C, ldc, accumulate, cmap);

@@ -1042,19 +1042,21 @@ __host__ __device__ constexpr int fused_row_stride(int K) {
 
 // The leaf amplitude of node rn, emission path j at value s, from the three
 // real products of the contraction (re = p1 - p2, im = p3 - p1 - p2), stored
-// at every copy it stands for: X[s][((rn << M) + j) << ne | e] times the end
-// cuts' factors at s (upper: the projector on bit e, lower: the sign), or only
-// at e = 0 without factors when the end cuts are folded into the assembly.
-__device__ __forceinline__ void tail_store(const TailDesc& T, float2* __restrict__ X, int si,
+// at every copy it stands for: Xs[((rn << M) + j) << ne | e] (Xs = X[s], the
+// value's output row, whose length ldx fits an int) times the end cuts'
+// factors at s (upper: the projector on bit e, lower: the sign), or only at
+// e = 0 without factors when the end cuts are folded into the assembly.
+__device__ __forceinline__ void tail_store(const TailDesc& T, float2* __restrict__ Xs,
                                            uint32_t s, int rn, int M, int ne, uint32_t j,
                                            float p1, float p2, float p3) {
   const float re = p1 - p2;
   const float im = p3 - p1 - p2;
+  const uint32_t o = ((uint32_t)rn << M) + j;
   if (T.end_base) {
-    X[(size_t)si * T.ldx + (((size_t)rn << M) + j)] = make_float2(re, im);
+    Xs[o] = make_float2(re, im);
     return;
   }
-  float2* dst = X + (size_t)si * T.ldx + ((((size_t)rn << M) + j) << ne);
+  float2* dst = Xs + (o << ne);
   for (int e = 0; e < (1 << ne); ++e) {
     float2 f = make_float2(re, im);
     for (int i = 0; i < ne; ++i) {
@@ -1150,7 +1152,7 @@ __device__ __forceinline__ void fused_unit(const TailDesc& T, const float2* __re
     for (int e4 = 0; e4 < 4; ++e4) {
       const int rn = at * 16 + 4 * gq + e4;
       if (rn >= Nn) continue;
-      tail_store(T, X, si, s, rn, M, ne, j, p1[bb][e4], p2[bb][e4], p3[bb][e4]);
+      tail_store(T, X + (size_t)si * T.ldx, s, rn, M, ne, j, p1[bb][e4], p2[bb][e4], p3[bb][e4]);
     }
   }
 }
@@ -1566,6 +1568,7 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
     const int at = cw % nts;
     const int li = lane & 15, gq = lane >> 4;
     const size_t N = (size_t)1 << T.n;
+    float2* const Xs = X + (size_t)si * T.ldx;
     // nodes past the last one read a valid row and are not written
     const float4* arow = (const float4*)(states + (size_t)min(at * 16 + li, Nn - 1) * N + base +
                                          gq * KQ);
@@ -1579,9 +1582,13 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
         for (int ct = cw / nts; ct < kWsRows / 16; ct += kWsConsumers / nts) {
           const float2* brow = buf + (ct * 16 + li) * RS + gq * (KQ + kFusedPadQ);
           floatx4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, p3 = p1;
+          // the next fragment is read while this one's products run
+          float4 bn = *(const float4*)brow;
 #pragma unroll
           for (int i = 0; i < KQ / 2; ++i) {
-            const float4 bv = *(const float4*)(brow + 2 * i);
+            const float4 bv = bn;
+            if (i + 1 < KQ / 2) bn = *(const float4*)(brow + 2 * i + 2);
+            __builtin_amdgcn_sched_barrier(0);
             const float4 av = A[i];
             p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, p1, 0, 0, 0);
             p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, p2, 0, 0, 0);
@@ -1589,6 +1596,7 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
             p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, p1, 0, 0, 0);
             p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, p2, 0, 0, 0);
             p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z + av.w, bv.z + bv.w, p3, 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
           }
           // column col = ct 16 + li is producer col / kWsSteps, step col % kWsSteps:
           // emission index (col / 4) JP + 4 ch + col % 4, written at 32 ch + col
@@ -1600,7 +1608,7 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
 #pragma unroll
           for (int e4 = 0; e4 < 4; ++e4) {
             const int rn = at * 16 + 4 * gq + e4;
-            if (rn < Nn) tail_store(T, X, si, s, rn, M, ne, j, p1[e4], p2[e4], p3[e4]);
+            if (rn < Nn) tail_store(T, Xs, s, rn, M, ne, j, p1[e4], p2[e4], p3[e4]);
           }
         }
       }

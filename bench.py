@@ -506,9 +506,9 @@ def main() -> int:
     t = per_step["tail"] / 1000.0
     if t > 0:
         achieved = tm["tail_flops"] / a.steps / t / 1e12
-        roofs["tail"] = {"kernel": "k_tail_fused", "bound": "alu", "achieved": round(achieved, 3),
+        roofs["tail"] = {"kernel": "k_tail_ws+k_tail_fused", "bound": "alu", "achieved": round(achieved, 3),
                          "peak": 157.3, "unit": "TFLOP/s", "frac": round(achieved / 157.3, 4),
-                         "traffic": _traffic_from_profile("k_tail_fused", w.name),
+                         "traffic": _traffic_from_profile("k_tail_ws+k_tail_fused", w.name),
                          "note": "14 flops per amplitude per 2x2 gate on the light-cone rows, "
                                  "8 per complex multiply-add in the per-value contraction"}
     # layer and branch passes: algorithmic bytes = 8 B read + 8 B written per
@@ -517,9 +517,9 @@ def main() -> int:
     avg_launch_s = per_step["pass"] / 1000.0 / max(1.0, launches["pass"])
     per_launch = bytes_per_step / max(1.0, launches["pass"])
     achieved = per_launch / avg_launch_s / 1e9
-    roofs["pass"] = {"kernel": "k_wpass", "bound": "hbm", "achieved": round(achieved, 1),
+    roofs["pass"] = {"kernel": "k_wpass+k_xpass", "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": _traffic_from_profile("k_wpass", w.name),
+                     "traffic": _traffic_from_profile("k_wpass+k_xpass", w.name),
                      "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": avg_launch_s * 1e6}
     # assembly: executed MFMA flops (FP32: three real products per complex
     # one, 6 M N K; split-BF16: twelve BF16 products, 24 M N K) over the GEMM
@@ -528,10 +528,10 @@ def main() -> int:
     cplx = tm["gemm_flops"] / a.steps          # 8 M N K, the complex-product count
     executed = cplx * (0.75 if prec == 0 else 3.0)
     peak = MFMA_PEAK_TFLOPS[prec]
-    roofs["gemm"] = {"kernel": "k_zgemm_nt_f32" if prec == 0 else "k_zgemm_nt_bf16x3", "bound": "mfma",
+    roofs["gemm"] = {"kernel": "k_zgemm_nt_f32d" if prec == 0 else "k_zgemm_nt_bf16x3", "bound": "mfma",
                      "achieved": round(executed / t / 1e12, 2), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(executed / t / 1e12 / peak, 4),
-                     "traffic": _traffic_from_profile("k_zgemm_nt_f32" if prec == 0 else "k_zgemm_nt_bf16x3",
+                     "traffic": _traffic_from_profile("k_zgemm_nt_f32d" if prec == 0 else "k_zgemm_nt_bf16x3",
                                                       w.name),
                      "complex_8mnk_tflops": round(cplx / t / 1e12, 2),
                      "note": "executed MFMA flops: 6 M N K (FP32, 3 real products) or 24 M N K (BF16)"}

@@ -87,7 +87,15 @@ def _is_copy(name: str) -> bool:
     return "copy" in name.lower() or "elementwise" in name.lower()
 
 
+def _in_family(name: str, kernels) -> bool:
+    """Whether a dispatch name (``qs::k_x<...>``) is one of the kernels named."""
+    return name.split("<")[0] in {f"qs::{k}" for k in kernels}
+
+
 def counter_summary(fetch_dir: str, write_dir: str, kernel: str, calib_bytes: int) -> dict:
+    """HBM bytes per dispatch of a kernel family; ``kernel`` names one kernel
+    or several joined by ``+`` (their dispatches are averaged together)."""
+    ks = kernel.split("+")
     f, fn = _pmc(fetch_dir)
     w, wn = _pmc(write_dir)
 
@@ -99,8 +107,8 @@ def counter_summary(fetch_dir: str, write_dir: str, kernel: str, calib_bytes: in
 
     cf = calib(f, fn, "FETCH_SIZE")
     cw = calib(w, wn, "WRITE_SIZE")
-    fk = [f[k].get("FETCH_SIZE", 0.0) for k in f if fn[k].startswith(f"qs::{kernel}")]
-    wk = [w[k].get("WRITE_SIZE", 0.0) for k in w if wn[k].startswith(f"qs::{kernel}")]
+    fk = [f[k].get("FETCH_SIZE", 0.0) for k in f if _in_family(fn[k], ks)]
+    wk = [w[k].get("WRITE_SIZE", 0.0) for k in w if _in_family(wn[k], ks)]
     if not fk or not wk:
         raise SystemExit(f"no dispatch of {kernel}")
     fetch = sum(fk) / len(fk) * 1024.0 / cf

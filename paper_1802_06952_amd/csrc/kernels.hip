@@ -1293,11 +1293,14 @@ k_tail_fused(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
 // (one depth-first chain each, its stack in registers as in k_tail_fused) and
 // write each chunk of kWsRows rows into one of two LDS buffers; four consumer
 // waves each hold one 16-node tile of the value's node amplitudes in
-// registers for the whole workgroup (read from HBM once, instead of once per
-// chunk) and contract the other buffer's chunk on FP32 MFMA.  One barrier per
-// chunk.  Waves w, w + 4 and w + 8 share a SIMD, so every SIMD runs two
-// producers and one consumer: the producers' vector work and the consumer's
-// MFMAs overlap instead of alternating.
+// registers (read from HBM once per value, instead of once per chunk) and
+// contract the other buffer's chunk on FP32 MFMA.  One barrier per chunk.
+// Waves w, w + 4 and w + 8 share a SIMD, so every SIMD runs two producers and
+// one consumer: the producers' vector work and the consumer's MFMAs overlap
+// instead of alternating.  The workgroups are persistent: each takes the
+// values blockIdx.x, blockIdx.x + gridDim.x, ... and runs one pipeline over
+// all their chunks, so the producers start a value while the consumers finish
+// the one before (the DIAG offset table is double-buffered for that).
 constexpr int kWsProducers = 8;
 constexpr int kWsConsumers = 4;
 constexpr int kWsThreads = 64 * (kWsProducers + kWsConsumers);
@@ -1305,6 +1308,11 @@ constexpr int kWsRows = 32;                         // rows per chunk
 constexpr int kWsSteps = kWsRows / kWsProducers;    // paths per producer per chunk
 constexpr int kWsMaxNodes = 16 * kWsConsumers;
 constexpr int kWsMaxOps = 32;  // leaf-level ops whose DIAG offsets fit in LDS
+// Row stride of the chunk buffers (complex): quarters of K/4 + kFusedPadQ,
+// plus 4 so that the stride is 12 mod 32 complex.  A consumer's fragment read
+// takes 16 B at one column of 16 rows; with a stride of 24 mod 64 dwords the
+// rows of each group of eight start 8 dwords apart modulo 64, on distinct banks.
+__host__ __device__ constexpr int ws_row_stride(int K) { return 4 * (K / 4 + kFusedPadQ) + 4; }
 
 bool tail_ws_ok(const TailDesc& h) {
   if (!tail_fused_ok(h) || h.n_nodes < 1 || h.n_nodes > kWsMaxNodes) return false;
@@ -1435,31 +1443,32 @@ __device__ __forceinline__ void ws_apply_ops(float2 (&v)[C * R], const DevOp* __
 template <int R>
 __global__ void __launch_bounds__(kWsThreads)
 k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
-          const float2* __restrict__ states, const uint32_t* __restrict__ svals, int s0,
+          const float2* __restrict__ states, const uint32_t* __restrict__ svals, int s0, int ns,
           float2* __restrict__ X) {
   constexpr int K = 64 * R, KQ = K / 4;
-  constexpr int RS = fused_row_stride(K);
+  constexpr int RS = ws_row_stride(K);
   constexpr int NB = ilog2(R);
   __shared__ __attribute__((aligned(16))) float2 wl[2][kWsRows * RS];  // chunk buffers
-  __shared__ uint32_t dof[kWsMaxOps * 64];  // DIAG table offsets at this value
+  __shared__ uint32_t dof[2][kWsMaxOps * 64];  // DIAG table offsets, by value parity
   __shared__ float2 tab[kPhaseEntries];
   const TailDesc& T = *tdp;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int si = s0 + blockIdx.x;
-  const uint32_t s = svals[si];
+  const int G = (int)gridDim.x;
+  const int nv = (ns - (int)blockIdx.x + G - 1) / G;  // values of this workgroup
   const uint32_t qmask = (1u << T.q) - 1u;
-  const uint32_t base = s & ~qmask, ys = s & qmask;
   const int nlev = T.nlev, M = T.M;
   const int top0 = T.lev[0].bop0;
-  if (wave < kWsProducers) {
-    // every DIAG op of the leaf levels, at this value: index base | lane |
-    // register bits, the lane part fixed for the whole workgroup
-    const int ntop = T.lev[nlev - 1].bop0 + T.lev[nlev - 1].bnops - top0;
+  const int ntop = T.lev[nlev - 1].bop0 + T.lev[nlev - 1].bnops - top0;
+  // every DIAG op of the leaf levels at value v (index base | lane | register
+  // bits, the lane part fixed for the whole value), by the producers
+  auto offsets = [&](int v) {
+    const uint32_t base = svals[s0 + (int)blockIdx.x + v * G] & ~qmask;
     uint32_t RB[NB > 0 ? NB : 1];
 #pragma unroll
     for (int k = 0; k < NB; ++k) RB[k] = 1u << (6 + k);
     if constexpr (NB == 0) RB[0] = 0;
+    uint32_t* d = dof[v & 1];
     for (int i = wave; i < ntop; i += kWsProducers) {
       const DevOp& op = ops[top0 + i];
       if (__builtin_amdgcn_readfirstlane(op.kind) == 1) {
@@ -1468,29 +1477,35 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
         uint32_t pk = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) pk |= off[r] << (8 * r);
-        dof[i * 64 + lane] = pk;
+        d[i * 64 + lane] = pk;
       }
     }
-  }
+  };
+  if (wave < kWsProducers && nv > 0) offsets(0);
   init_phase_table(tab);  // and the barrier after the offsets
   const uint32_t JP = (1u << M) / kWsProducers;  // paths per producer
   const int nchunks = (int)(JP / kWsSteps);
+  const int total = nv * nchunks;                // chunks of the pipeline
   if (wave < kWsProducers) {
-    // ---- producer: paths [wave JP, (wave + 1) JP), the kWsSteps = 4 paths
-    // j = wave JP + 4 ch + 2 b1 + b0 in chunk ch, at LDS row wave 4 + 2 b1 + b0
-    // (b0, b1: the digits of the first two leaf levels, one cut bit each).  The
-    // four share the vector above level 1; level 0's ops run on both values
-    // of b1 at once (one decode of each op for two vectors).
+    // ---- producer: paths [wave JP, (wave + 1) JP) of each value, the
+    // kWsSteps = 4 paths j = wave JP + 4 ch + 2 b1 + b0 in chunk ch, at LDS row
+    // wave 4 + 2 b1 + b0 (b0, b1: the digits of the first two leaf levels, one
+    // cut bit each).  The four share the vector above level 1; level 0's ops
+    // run on both values of b1 at once (one decode of each op for two vectors).
     static_assert(kWsSteps == 4, "a chunk takes one group of four paths per producer");
-    const uint32_t F = base | (uint32_t)lane;
     const uint32_t jw = (uint32_t)wave * JP;
     float2 u[kFusedDepth - 1][R];  // the vector after depth D's ops, D < nlev - 1
     uint32_t jprev = 0;
-    for (int ch = 0; ch <= nchunks; ++ch) {
-      if (ch < nchunks) {
-        float2* buf = wl[ch & 1];
+    for (int g = 0; g <= total; ++g) {
+      if (g < total) {
+        const int v = g / nchunks, ch = g - v * nchunks;
+        const uint32_t s = svals[s0 + (int)blockIdx.x + v * G];
+        const uint32_t ys = s & qmask;
+        const uint32_t F = (s & ~qmask) | (uint32_t)lane;
+        const uint32_t* dv = dof[v & 1];
+        float2* buf = wl[g & 1];
         const uint32_t jl = (uint32_t)ch * kWsSteps;
-        int d0 = -1;  // u[0..d0] still hold
+        int d0 = -1;  // u[0..d0] still hold (none at a value's first chunk)
         if (jl > 0) {
           // jw is a multiple of JP > jl: the changed digits are jl's (levels 2..)
           const int hb = 31 - __builtin_clz(jl ^ jprev);
@@ -1504,21 +1519,21 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
         for (int D = 0; D < kFusedDepth - 1; ++D) {
           if (D < nlev - 1 && D > d0) {
             const int l = nlev - 1 - D;
-            float2 v[R];
+            float2 x[R];
             if (D == 0) {
 #pragma unroll
               for (int r = 0; r < R; ++r)
-                v[r] = ((uint32_t)(lane + 64 * r) == ys) ? make_float2(T.tscale, 0.f)
+                x[r] = ((uint32_t)(lane + 64 * r) == ys) ? make_float2(T.tscale, 0.f)
                                                          : make_float2(0.f, 0.f);
             } else {
               const TailLevel& L = T.lev[l + 1];
               const int b = (int)((j >> L.pos) & ((1u << L.m) - 1u));
-              ws_cut<R>(v, u[D - 1], L, b, T.upper, F);
+              ws_cut<R>(x, u[D - 1], L, b, T.upper, F);
             }
 #pragma unroll
-            for (int r = 0; r < R; ++r) u[D][r] = v[r];
+            for (int r = 0; r < R; ++r) u[D][r] = x[r];
             ws_apply_ops<R, 1>(u[D], ops, T.lev[l].bop0, T.lev[l].bnops, T.lev[l].code,
-                               T.lev[l].bop0 - top0, lane, dof, tab);
+                               T.lev[l].bop0 - top0, lane, dv, tab);
           }
         }
         // level 0 on the vector above it with level 1's cut factor for b1 = 0
@@ -1541,7 +1556,7 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
           for (int r = 0; r < R; ++r) w[R + r] = h[r];
         }
         ws_apply_ops<R, 2>(w, ops, T.lev[0].bop0, T.lev[0].bnops, T.lev[0].code,
-                           T.lev[0].bop0 - top0, lane, dof, tab);
+                           T.lev[0].bop0 - top0, lane, dv, tab);
 #pragma unroll
         for (int st = 0; st < kWsSteps; ++st) {
           float2 src[R], a[R];
@@ -1555,6 +1570,9 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
             row[(y / KQ) * (KQ + kFusedPadQ) + (y % KQ)] = a[r];
           }
         }
+        // the next value's offsets, into the other table (its last reader,
+        // the value before this one, finished before the previous barrier)
+        if (ch == nchunks - 1 && v + 1 < nv) offsets(v + 1);
       }
       lds_barrier();
     }
@@ -1568,16 +1586,23 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
     const int at = cw % nts;
     const int li = lane & 15, gq = lane >> 4;
     const size_t N = (size_t)1 << T.n;
-    float2* const Xs = X + (size_t)si * T.ldx;
     // nodes past the last one read a valid row and are not written
-    const float4* arow = (const float4*)(states + (size_t)min(at * 16 + li, Nn - 1) * N + base +
-                                         gq * KQ);
+    const float2* const arow0 = states + (size_t)min(at * 16 + li, Nn - 1) * N + gq * KQ;
     float4 A[KQ / 2];
+    auto load_a = [&](int v) {
+      const uint32_t base = svals[s0 + (int)blockIdx.x + v * G] & ~qmask;
+      const float4* arow = (const float4*)(arow0 + base);
 #pragma unroll
-    for (int i = 0; i < KQ / 2; ++i) A[i] = arow[i];
+      for (int i = 0; i < KQ / 2; ++i) A[i] = arow[i];
+    };
+    if (nv > 0) load_a(0);
     lds_barrier();
-    for (int ch = 0; ch < nchunks; ++ch) {
-      const float2* buf = wl[ch & 1];
+    for (int g = 0; g < total; ++g) {
+      const int v = g / nchunks, ch = g - v * nchunks;
+      const int si = s0 + (int)blockIdx.x + v * G;
+      const uint32_t s = svals[si];
+      float2* const Xs = X + (size_t)si * T.ldx;
+      const float2* buf = wl[g & 1];
       if (at < nat) {
         for (int ct = cw / nts; ct < kWsRows / 16; ct += kWsConsumers / nts) {
           const float2* brow = buf + (ct * 16 + li) * RS + gq * (KQ + kFusedPadQ);
@@ -1612,9 +1637,28 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
           }
         }
       }
+      // the next value's node tile, once this value's products have read A
+      if (ch == nchunks - 1 && v + 1 < nv) load_a(v + 1);
       lds_barrier();
     }
   }
+}
+
+// Compute units of the current device (cached per device; 0 on error).
+static int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+  if (dev >= 64) {
+    int n = 0;
+    return hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess ? n : 0;
+  }
+  if (cus[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    cus[dev] = n;
+  }
+  return cus[dev];
 }
 
 size_t tail_w_bytes(const TailDesc& h, int ns) {
@@ -1631,11 +1675,15 @@ hipError_t launch_tail(const TailDesc& h, const TailDesc* d_desc, const DevOp* d
     dim3 g((unsigned)ns);
     if (h.ws) {
       if (!tail_ws_ok(h)) return hipErrorInvalidValue;
-      dim3 b(kWsThreads);
+      // persistent workgroups: one per compute unit (the LDS holds one), each
+      // taking every G-th value
+      const int G = std::min(ns, device_cus());
+      if (G <= 0) return hipErrorInvalidValue;
+      dim3 gw((unsigned)G), b(kWsThreads);
       switch (R) {
-        case 1: hipLaunchKernelGGL(k_tail_ws<1>, g, b, 0, st, d_desc, d_ops, states, svals, s0, X); break;
-        case 2: hipLaunchKernelGGL(k_tail_ws<2>, g, b, 0, st, d_desc, d_ops, states, svals, s0, X); break;
-        case 4: hipLaunchKernelGGL(k_tail_ws<4>, g, b, 0, st, d_desc, d_ops, states, svals, s0, X); break;
+        case 1: hipLaunchKernelGGL(k_tail_ws<1>, gw, b, 0, st, d_desc, d_ops, states, svals, s0, ns, X); break;
+        case 2: hipLaunchKernelGGL(k_tail_ws<2>, gw, b, 0, st, d_desc, d_ops, states, svals, s0, ns, X); break;
+        case 4: hipLaunchKernelGGL(k_tail_ws<4>, gw, b, 0, st, d_desc, d_ops, states, svals, s0, ns, X); break;
         default: return hipErrorInvalidValue;
       }
       return hipGetLastError();

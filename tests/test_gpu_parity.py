@@ -220,6 +220,25 @@ def test_grid6x7_d20_full_size_subset(prec):
     assert abs(stats[1] - 1.0) < 0.05
 
 
+def test_grid6x7_d20_values_past_the_first_round():
+    """1024 values per half: the leaf evaluation's persistent workgroups (one
+    per compute unit) take several values each, one pipeline over all their
+    chunks.  Blocks of 256 x 256 values run alone (one value per workgroup)
+    give the same amplitudes as the same values inside the full set."""
+    Q = _lib()
+    w = workload("grid6x7_d20")
+    bits, u, l = product_bitstrings(w.n, w.upper_mask, w.n_u, w.n_l, w.seed_u, w.seed_l)
+    say(f"case grid6x7_d20 full set m={bits.size}")
+    amp, _ = run_plan(Q, w.circuit_text(), w.upper_mask, bits)
+    full = amp.reshape(w.n_u, w.n_l)
+    B = bits.reshape(w.n_u, w.n_l)
+    for ku, kl in [(1, 3), (3, 1), (2, 2), (0, 0)]:
+        ru, rl = slice(256 * ku, 256 * (ku + 1)), slice(256 * kl, 256 * (kl + 1))
+        say(f"case grid6x7_d20 block upper {ku} lower {kl}")
+        sub, _ = run_plan(Q, w.circuit_text(), w.upper_mask, np.ascontiguousarray(B[ru, rl]).reshape(-1))
+        assert_close(full[ru, rl].reshape(-1), sub, TOL[0], f"block {ku},{kl}")
+
+
 def test_plain_form_and_device_outputs():
     Q = _lib()
     import torch

@@ -1046,13 +1046,13 @@ __host__ __device__ constexpr int fused_row_stride(int K) {
 // value's output row, whose length ldx fits an int) times the end cuts'
 // factors at s (upper: the projector on bit e, lower: the sign), or only at
 // e = 0 without factors when the end cuts are folded into the assembly.
-__device__ __forceinline__ void tail_store(const TailDesc& T, float2* __restrict__ Xs,
+__device__ __forceinline__ void tail_store(const TailDesc& T, int end_base, float2* __restrict__ Xs,
                                            uint32_t s, int rn, int M, int ne, uint32_t j,
                                            float p1, float p2, float p3) {
   const float re = p1 - p2;
   const float im = p3 - p1 - p2;
   const uint32_t o = ((uint32_t)rn << M) + j;
-  if (T.end_base) {
+  if (end_base) {
     Xs[o] = make_float2(re, im);
     return;
   }
@@ -1152,7 +1152,8 @@ __device__ __forceinline__ void fused_unit(const TailDesc& T, const float2* __re
     for (int e4 = 0; e4 < 4; ++e4) {
       const int rn = at * 16 + 4 * gq + e4;
       if (rn >= Nn) continue;
-      tail_store(T, X + (size_t)si * T.ldx, s, rn, M, ne, j, p1[bb][e4], p2[bb][e4], p3[bb][e4]);
+      tail_store(T, T.end_base, X + (size_t)si * T.ldx, s, rn, M, ne, j, p1[bb][e4], p2[bb][e4],
+                 p3[bb][e4]);
     }
   }
 }
@@ -1581,6 +1582,8 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
     // takes y in [gq KQ, (gq + 1) KQ) as the MFMA k index
     const int cw = wave - kWsProducers;
     const int Nn = T.n_nodes, ne = T.n_end;
+    const int endb = __builtin_amdgcn_readfirstlane(T.end_base);
+    const int ldx = __builtin_amdgcn_readfirstlane(T.ldx);
     const int nat = (Nn + 15) >> 4;
     const int nts = nat >= 3 ? 4 : nat;  // node-tile slots
     const int at = cw % nts;
@@ -1601,7 +1604,7 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
       const int v = g / nchunks, ch = g - v * nchunks;
       const int si = s0 + (int)blockIdx.x + v * G;
       const uint32_t s = svals[si];
-      float2* const Xs = X + (size_t)si * T.ldx;
+      float2* const Xs = X + (size_t)si * ldx;
       const float2* buf = wl[g & 1];
       if (at < nat) {
         for (int ct = cw / nts; ct < kWsRows / 16; ct += kWsConsumers / nts) {
@@ -1615,12 +1618,15 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
             if (i + 1 < KQ / 2) bn = *(const float4*)(brow + 2 * i + 2);
             __builtin_amdgcn_sched_barrier(0);
             const float4 av = A[i];
+            // the sums first, then the six products in a fixed order
+            const float sa0 = av.x + av.y, sb0 = bv.x + bv.y, sa1 = av.z + av.w, sb1 = bv.z + bv.w;
+            __builtin_amdgcn_sched_barrier(0);
             p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, p1, 0, 0, 0);
             p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, p2, 0, 0, 0);
-            p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x + av.y, bv.x + bv.y, p3, 0, 0, 0);
+            p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(sa0, sb0, p3, 0, 0, 0);
             p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, p1, 0, 0, 0);
             p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, p2, 0, 0, 0);
-            p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z + av.w, bv.z + bv.w, p3, 0, 0, 0);
+            p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(sa1, sb1, p3, 0, 0, 0);
             __builtin_amdgcn_sched_barrier(0);
           }
           // column col = ct 16 + li is producer col / kWsSteps, step col % kWsSteps:
@@ -1633,7 +1639,7 @@ k_tail_ws(const TailDesc* __restrict__ tdp, const DevOp* __restrict__ ops,
 #pragma unroll
           for (int e4 = 0; e4 < 4; ++e4) {
             const int rn = at * 16 + 4 * gq + e4;
-            if (rn < Nn) tail_store(T, Xs, s, rn, M, ne, j, p1[e4], p2[e4], p3[e4]);
+            if (rn < Nn) tail_store(T, endb, Xs, s, rn, M, ne, j, p1[e4], p2[e4], p3[e4]);
           }
         }
       }

@@ -965,6 +965,7 @@ qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_s
   const int nb = prob_partial_blocks(m);
   double* d_part = (double*)sc.get((2 * (size_t)nb + 2) * sizeof(double));
   if (!d_part) return fail(QS_ERR_OOM, "assembly buffers");
+  bool sums_done = false;  // the product path gathers and sums in one kernel
   if (plan->list_mode) {
     // the bitstrings are far from a product set: one sum over the copies per
     // bitstring (FP32 accumulation for either precision)
@@ -1033,12 +1034,15 @@ qs_status assemble(qs_plan* plan, qs_precision prec, float2* d_amps, double* d_s
     }
     if (run) {
       Timer tm(plan, st, 3);
-      HIPCHECK(launch_gather_amps(C, N, plan->d_idx[0], plan->d_idx[1], m, d_amps, phi_of(plan), st));
-      tm.launches += 1;
+      HIPCHECK(launch_gather_prob_sums(C, N, plan->d_idx[0], plan->d_idx[1], m, d_amps,
+                                       phi_of(plan), d_part, d_sums ? d_sums : d_part + 2 * nb,
+                                       st));
+      tm.launches += 2;
     }
+    sums_done = true;
     sc.put(C);
   }
-  if (run) {
+  if (run && !sums_done) {
     Timer tm(plan, st, 3);
     HIPCHECK(launch_prob_sums(d_amps, m, d_part, d_sums ? d_sums : d_part + 2 * nb, st));
     tm.launches += 2;
@@ -1395,6 +1399,17 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
     const int ne = bmap.ne;
     const uint64_t K0 = Kb >> ne;
     const int NL = (int)plan->vals[1].size();
+    // the lower rows' order with folded end cuts (rows, then group starts),
+    // copied ahead of the lower half's passes: off the path from its leaf
+    // evaluation to the product
+    uint32_t* dr = nullptr;
+    if (ne > 0) {
+      const size_t nr = (size_t)NL + (1u << ne) + 1;
+      dr = (uint32_t*)plan->pool.get(nr * sizeof(uint32_t), ss[1]);
+      if (!dr) return fail(QS_ERR_OOM, "row order");
+      HIPCHECK(hipMemcpyAsync(dr, prs[1]->dev + prs[1]->o_rows, nr * sizeof(uint32_t),
+                              hipMemcpyDeviceToDevice, ss[1]));
+    }
     for (int sidx = 0; sidx < 2; ++sidx) {
       const size_t bytes = (sidx == 1 ? K0 : Kb) * plan->vals[sidx].size() * sizeof(float2);
       br.X[sidx] = (float2*)plan->pool.get(bytes, ss[sidx]);
@@ -1411,11 +1426,6 @@ qs_status qs_run_halves(qs_plan* plan, uint64_t copy_begin, uint64_t copy_end,
       if (!XL) return fail(QS_ERR_OOM, "gathered half amplitudes");
       Timer tm(plan, ss[1], 3);
       if (ne > 0) {
-        const size_t nr = (size_t)NL + (1u << ne) + 1;  // rows, then group starts
-        uint32_t* dr = (uint32_t*)plan->pool.get(nr * sizeof(uint32_t), ss[1]);
-        if (!dr) return fail(QS_ERR_OOM, "row order");
-        HIPCHECK(hipMemcpyAsync(dr, prs[1]->dev + prs[1]->o_rows, nr * sizeof(uint32_t),
-                                hipMemcpyDeviceToDevice, ss[1]));
         HIPCHECK(launch_gather_rows_cols(br.X[1], XL, dr, bmap.d_colsel, NL, (int)K0, (int)K0,
                                          ss[1]));
         br.d_rows = dr;
@@ -2060,12 +2070,12 @@ qs_status qs_chain_amplitudes_device(qs_mplan* mp, float* d_out_c64, double* d_o
     release(U, u_part);
   }
   const size_t m = mp->bits.size();
-  HIPCHECK(launch_gather_amps(G, (int)Rr, mp->d_iu, mp->d_il, m, (float2*)d_out_c64,
-                              make_float2((float)ph_re, (float)ph_im), st));
   const int nb = prob_partial_blocks(m);
   double* part = (double*)mp->pool.get((2 * (size_t)nb + 2) * sizeof(double), st);
   if (!part) return fail(QS_ERR_OOM, "probability sums");
-  HIPCHECK(launch_prob_sums((const float2*)d_out_c64, m, part, d_out_sums ? d_out_sums : part + 2 * nb, st));
+  HIPCHECK(launch_gather_prob_sums(G, (int)Rr, mp->d_iu, mp->d_il, m, (float2*)d_out_c64,
+                                   make_float2((float)ph_re, (float)ph_im), part,
+                                   d_out_sums ? d_out_sums : part + 2 * nb, st));
   mp->pool.put(part, st);
   mp->pool.put(G, st);
   return QS_OK;

@@ -93,6 +93,11 @@ hipError_t launch_gather_amps(const float2* C, int ldc, const int* iu, const int
 // FP64 sums over m amplitudes: out[0] = sum |a|^2, out[1] = sum |a|^4.
 // `partial` must hold 2 * prob_partial_blocks(m) doubles.
 int prob_partial_blocks(size_t m);
+// launch_gather_amps followed by launch_prob_sums, with the gather and the
+// partial sums in one kernel (same results).
+hipError_t launch_gather_prob_sums(const float2* C, int ldc, const int* iu, const int* il,
+                                   size_t m, float2* amps, float2 phi, double* partial,
+                                   double* out, hipStream_t st);
 hipError_t launch_prob_sums(const float2* amps, size_t m, double* partial, double* out,
                             hipStream_t st);
 

@@ -2816,6 +2816,54 @@ k_prob_final(const double* __restrict__ partial, int nb, double* __restrict__ ou
   }
 }
 
+// k_gather_amps and k_prob_partial in one pass: each workgroup gathers its
+// kProbPerBlock amplitudes, writes them, and sums them in the same order as
+// k_prob_partial (the sums are bit-identical to the two-kernel form).
+__global__ void __launch_bounds__(kProbThreads)
+k_gather_prob_partial(const float2* __restrict__ C, int ldc, const int* __restrict__ iu,
+                      const int* __restrict__ il, size_t m, float2* __restrict__ amps, float2 phi,
+                      double* __restrict__ partial) {
+  __shared__ double s1[kProbThreads], s2[kProbThreads];
+  const size_t base = (size_t)blockIdx.x * kProbPerBlock;
+  double a1 = 0, a2 = 0;
+  for (int i = threadIdx.x; i < kProbPerBlock; i += kProbThreads) {
+    const size_t t = base + i;
+    if (t < m) {
+      const float2 a = cmul(C[(size_t)iu[t] * ldc + il[t]], phi);
+      amps[t] = a;
+      const double re = a.x, im = a.y;
+      const double p = re * re + im * im;
+      a1 += p;
+      a2 += p * p;
+    }
+  }
+  s1[threadIdx.x] = a1;
+  s2[threadIdx.x] = a2;
+  __syncthreads();
+  for (int w = kProbThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = s1[0];
+    partial[2 * blockIdx.x + 1] = s2[0];
+  }
+}
+
+hipError_t launch_gather_prob_sums(const float2* C, int ldc, const int* iu, const int* il,
+                                   size_t m, float2* amps, float2 phi, double* partial,
+                                   double* out, hipStream_t st) {
+  const int nb = prob_partial_blocks(m);
+  if (nb == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gather_prob_partial, dim3(nb), dim3(kProbThreads), 0, st, C, ldc, iu, il,
+                     m, amps, phi, partial);
+  hipLaunchKernelGGL(k_prob_final, dim3(1), dim3(kProbThreads), 0, st, partial, nb, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_prob_sums(const float2* amps, size_t m, double* partial, double* out,
                             hipStream_t st) {
   const int nb = prob_partial_blocks(m);

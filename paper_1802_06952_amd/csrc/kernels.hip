@@ -369,11 +369,13 @@ __device__ __forceinline__ void diag_offsets(uint32_t (&off)[1 << NB], const Dev
   constexpr int E = 1 << NB;
   // every field of the op is the same in all lanes: read into scalar registers
   const auto su = [](uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane(x); };
-  int eF = __popc(F & su((uint32_t)op.t0)) + 2 * __popc(F & su((uint32_t)op.t1)) +
-           4 * __popc(F & su((uint32_t)op.t2));
+  // (the masks used once per op stay in vector registers: moving each into a
+  // scalar register would cost one more vector instruction than it saves)
+  int eF = __popc(F & (uint32_t)op.t0) + 2 * __popc(F & (uint32_t)op.t1) +
+           4 * __popc(F & (uint32_t)op.t2);
   const int nd = __builtin_amdgcn_readfirstlane(op.nd);
   for (int i = 0; i < nd; ++i)
-    eF += 4 * __popc(F & (F >> su((uint32_t)op.d[i])) & su((uint32_t)op.M[i]));
+    eF += 4 * __popc(F & (F >> (uint32_t)op.d[i]) & (uint32_t)op.M[i]);
   int ex[E];
   ex[0] = eF << 3;
   if constexpr (NB > 0) {
@@ -381,7 +383,7 @@ __device__ __forceinline__ void diag_offsets(uint32_t (&off)[1 << NB], const Dev
     uint32_t rr[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-      wk[k] = ((int)su((uint32_t)op.wl[k]) + 4 * __popc(F & su(op.cross[k]))) << 3;
+      wk[k] = (op.wl[k] + 4 * __popc(F & op.cross[k])) << 3;
       rr[k] = su(op.rr[k]);
     }
 #pragma unroll

@@ -237,6 +237,12 @@ def test_grid6x7_d20_values_past_the_first_round():
         say(f"case grid6x7_d20 block upper {ku} lower {kl}")
         sub, _ = run_plan(Q, w.circuit_text(), w.upper_mask, np.ascontiguousarray(B[ru, rl]).reshape(-1))
         assert_close(full[ru, rl].reshape(-1), sub, TOL[0], f"block {ku},{kl}")
+    # a ragged count: 300 x 260 values, so that some workgroups take two values
+    # and the others one
+    ru, rl = slice(700, 1000), slice(37, 297)
+    say("case grid6x7_d20 ragged 300 x 260")
+    sub, _ = run_plan(Q, w.circuit_text(), w.upper_mask, np.ascontiguousarray(B[ru, rl]).reshape(-1))
+    assert_close(full[ru, rl].reshape(-1), sub, TOL[0], "ragged block")
 
 
 def test_plain_form_and_device_outputs():

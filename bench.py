@@ -224,9 +224,11 @@ def error_stats(a, ref) -> dict:
             "n": int(a.size)}
 
 
-def time_workload(Q, w, prec, steps, warmup, stream, knobs=None, one_stream=False) -> dict:
+def time_workload(Q, w, prec, steps, warmup, stream, knobs=None, one_stream=False,
+                  graph=False) -> dict:
     """Amplitudes/s of one workload on its own: run_halves over its copy range
-    and the assembly per step, bitstrings registered and outputs in HBM."""
+    and the assembly per step, bitstrings registered and outputs in HBM; with
+    graph, also the same step replayed as one library-captured HIP graph."""
     import numpy as np
     import torch
     from workloads import product_bitstrings
@@ -254,10 +256,24 @@ def time_workload(Q, w, prec, steps, warmup, stream, knobs=None, one_stream=Fals
             step()
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1000.0 / steps
-        return {"value": round(m / (ms / 1000.0), 1), "unit": "amplitudes/s",
-                "ms_per_step": round(ms, 4), "bitstrings": m, "copies": k1 - k0,
-                "halves": [p.n_upper, p.n_lower], "cuts": p.n_cuts,
-                "amplitudes": d_out.cpu().numpy().view(np.complex64)}
+        r = {"value": round(m / (ms / 1000.0), 1), "unit": "amplitudes/s",
+             "ms_per_step": round(ms, 4), "bitstrings": m, "copies": k1 - k0,
+             "halves": [p.n_upper, p.n_lower], "cuts": p.n_cuts,
+             "amplitudes": d_out.cpu().numpy().view(np.complex64)}
+        if graph:
+            gs = torch.cuda.Stream()   # a graph cannot be captured on the null stream
+            p.run_graph(k0, k1, prec, d_out.data_ptr(), d_sums.data_ptr(), gs)
+            for _ in range(warmup):
+                p.run_graph(k0, k1, prec, d_out.data_ptr(), d_sums.data_ptr(), gs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                p.run_graph(k0, k1, prec, d_out.data_ptr(), d_sums.data_ptr(), gs)
+            torch.cuda.synchronize()
+            gms = (time.perf_counter() - t0) * 1000.0 / steps
+            r["graph"] = {"value": round(m / (gms / 1000.0), 1), "ms_per_step": round(gms, 4),
+                          "note": "the same step replayed as one HIP graph (qs_run_graph)"}
+        return r
     finally:
         p.close()
 
@@ -660,7 +676,8 @@ def main() -> int:
                              "grid8x8_d22_slice64"))
         # 36 qubits, 18+18 halves, all 4096 copies, 2^16 bitstrings: small enough that launch
         # latency, not bandwidth, sets its time
-        r = time_workload(Q, _wl("grid6x6_d16"), 0, a.steps, a.warmup, stream, tk.get("grid6x6_d16"))
+        r = time_workload(Q, _wl("grid6x6_d16"), 0, a.steps, a.warmup, stream, tk.get("grid6x6_d16"),
+                          graph=True)
         r["knobs"] = tk.get("grid6x6_d16") or "cost model defaults"
         r.pop("amplitudes")
         r["workload"] = "grid6x6_d16: 6x6 grid (36 qubits), depth 16, rows 0-2 | 3-5, FP32 assembly"

@@ -2077,20 +2077,26 @@ k_zgemm_nt_f32d(int M, int N, int K, int kper, const float2* __restrict__ A, int
 
 // C[i][j] = (accumulate ? C[i][j] : 0) + sum over splits of P[z][i][j], in split order.
 // (column j goes to C column cmap[j] when cmap is given)
+// Thread jj of column block x takes column jj of rows y, y + gridDim.y, ...
 __global__ void k_zgemm_reduce(int M, int N, int splits, const float2* __restrict__ P,
                                size_t split_stride, float2* __restrict__ C, int ldc, int accumulate,
                                const uint32_t* __restrict__ cmap) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (size_t)M * N) return;
-  const int i = (int)(t / N), jj = (int)(t % N);
+  const int jj = blockIdx.x * blockDim.x + threadIdx.x;
+  if (jj >= N) return;
   const int j = cmap ? (int)cmap[jj] : jj;
-  float2 acc = accumulate ? C[(size_t)i * ldc + j] : make_float2(0.f, 0.f);
-  for (int z = 0; z < splits; ++z) {
-    const float2 p = P[(size_t)z * split_stride + (size_t)i * N + jj];
-    acc.x += p.x;
-    acc.y += p.y;
+  for (int i = blockIdx.y; i < M; i += gridDim.y) {
+    float2 acc = accumulate ? C[(size_t)i * ldc + j] : make_float2(0.f, 0.f);
+    for (int z = 0; z < splits; ++z) {
+      const float2 p = P[(size_t)z * split_stride + (size_t)i * N + jj];
+      acc.x += p.x;
+      acc.y += p.y;
+    }
+    C[(size_t)i * ldc + j] = acc;
   }
-  C[(size_t)i * ldc + j] = acc;
+}
+
+static dim3 reduce_grid(int M, int N) {
+  return dim3((unsigned)((N + 255) / 256), (unsigned)std::max(1, std::min(M, 65535)));
 }
 
 // Split-BF16: each FP32 value a is split as hi = bf16(a) (round to nearest
@@ -2479,8 +2485,7 @@ hipError_t launch_zgemm_tn(int prec, int M, int N, int K, const float2* A, int l
       hipLaunchKernelGGL(k_zgemm_nt_bf16x3, grid, dim3(kBfThreads), 0, st, M, N, K, g.kper, A, lda,
                          B, ldb, P, N, ss, (const int*)nullptr, g.splits, 0);
   }
-  const size_t tot = ss;
-  hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, N,
+  hipLaunchKernelGGL(k_zgemm_reduce, reduce_grid(M, N), dim3(256), 0, st, M, N,
                      g.splits, P, ss, C, ldc, accumulate, cmap);
   return hipGetLastError();
 }
@@ -2529,7 +2534,7 @@ hipError_t launch_zgemm_grouped(int M, int Ntot, int maxn, int K, int ngroups, c
   else
     hipLaunchKernelGGL((k_zgemm_nt_f32d<4, kGroupTN>), grid, dim3(kGemmThreads), 0, st, M, Ntot, K,
                        g.kper, A, K, B, K, P, Ntot, ss, d_goff, g.splits, a_gstride);
-  hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((ss + 255) / 256)), dim3(256), 0, st, M, Ntot,
+  hipLaunchKernelGGL(k_zgemm_reduce, reduce_grid(M, Ntot), dim3(256), 0, st, M, Ntot,
                      g.splits, P, ss, C, ldc, accumulate, cmap);
   return hipGetLastError();
 }
@@ -2576,7 +2581,7 @@ hipError_t launch_zgemm_grouped_bf16(int M, int Ntot, int maxn, int K, int ngrou
   else
     hipLaunchKernelGGL(k_zgemm_nt_bf16x3, grid, dim3(kBfThreads), 0, st, M, Ntot, K, g.kper, A, K,
                        B, K, P, Ntot, ss, d_goff, g.splits, M);
-  hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((ss + 255) / 256)), dim3(256), 0, st, M, Ntot,
+  hipLaunchKernelGGL(k_zgemm_reduce, reduce_grid(M, Ntot), dim3(256), 0, st, M, Ntot,
                      g.splits, P, ss, C, ldc, accumulate, cmap);
   return hipGetLastError();
 }
@@ -2587,32 +2592,34 @@ hipError_t launch_zgemm_grouped_bf16(int M, int Ntot, int maxn, int K, int ngrou
 // half's copy order onto the upper half's.
 __global__ void k_permute_cols(const float2* __restrict__ in, float2* __restrict__ out,
                                const uint32_t* __restrict__ perm, int rows, int K) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (size_t)rows * K) return;
-  const size_t row = t / K;
-  const int j = (int)(t % K);
-  out[t] = in[row * K + perm[j]];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= K) return;
+  const uint32_t pj = perm[j];
+  for (int r = blockIdx.y; r < rows; r += gridDim.y)
+    out[(size_t)r * K + j] = in[(size_t)r * K + pj];
 }
 
 // out[r][j] = in[rowsel[r]][colsel[j]] (in: rows of Kin, out: rows of Kout).
+// Thread j of column block x takes column j of rows y, y + gridDim.y, ... (no
+// index division per element).
 __global__ void k_gather_rows_cols(const float2* __restrict__ in, float2* __restrict__ out,
                                    const uint32_t* __restrict__ rowsel,
                                    const uint32_t* __restrict__ colsel, int rows, int Kin,
                                    int Kout) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (size_t)rows * Kout) return;
-  const size_t r = t / Kout;
-  const int j = (int)(t % Kout);
-  out[t] = in[(size_t)rowsel[r] * Kin + colsel[j]];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Kout) return;
+  const uint32_t cj = colsel[j];
+  for (int r = blockIdx.y; r < rows; r += gridDim.y)
+    out[(size_t)r * Kout + j] = in[(size_t)rowsel[r] * Kin + cj];
 }
 
 hipError_t launch_gather_rows_cols(const float2* in, float2* out, const uint32_t* rowsel,
                                    const uint32_t* colsel, int rows, int Kin, int Kout,
                                    hipStream_t st) {
-  const size_t tot = (size_t)rows * Kout;
-  if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_rows_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
-                     in, out, rowsel, colsel, rows, Kin, Kout);
+  if (rows <= 0 || Kout <= 0) return hipSuccess;
+  const dim3 g((unsigned)((Kout + 255) / 256), (unsigned)std::min(rows, 65535));
+  hipLaunchKernelGGL(k_gather_rows_cols, g, dim3(256), 0, st, in, out, rowsel, colsel, rows, Kin,
+                     Kout);
   return hipGetLastError();
 }
 
@@ -2695,10 +2702,9 @@ hipError_t launch_end_wht(const float2* X, int rows, int K, int ne, const int* p
 
 hipError_t launch_permute_cols(const float2* in, float2* out, const uint32_t* perm, int rows,
                                int K, hipStream_t st) {
-  const size_t tot = (size_t)rows * K;
-  if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_permute_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, in, out,
-                     perm, rows, K);
+  if (rows <= 0 || K <= 0) return hipSuccess;
+  const dim3 g((unsigned)((K + 255) / 256), (unsigned)std::min(rows, 65535));
+  hipLaunchKernelGGL(k_permute_cols, g, dim3(256), 0, st, in, out, perm, rows, K);
   return hipGetLastError();
 }
 
@@ -2758,7 +2764,7 @@ hipError_t launch_gather_amps(const float2* C, int ldc, const int* iu, const int
 }
 
 constexpr int kProbThreads = 256;
-constexpr int kProbPerBlock = 4096;
+constexpr int kProbPerBlock = 1024;
 
 int prob_partial_blocks(size_t m) { return (int)((m + kProbPerBlock - 1) / kProbPerBlock); }
 

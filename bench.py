@@ -688,6 +688,9 @@ def main() -> int:
         # one GPU's slice of the 64-qubit circuit (32+32 halves, copies [0, 64) of 65536)
         c5 = {}
         for p_, name in ((0, "fp32"), (1, "split_bf16")):
+            # the plans take their memory budget from the free device memory:
+            # hand back what the caching allocator holds from the runs before
+            torch.cuda.empty_cache()
             r = time_workload(Q, _wl("grid8x8_d22_slice64"), p_, max(2, a.steps // 5), 1, stream,
                               tk.get("grid8x8_d22_slice64"))
             r.pop("amplitudes")

@@ -86,15 +86,11 @@ hipError_t launch_gathered_dot(int K, const float2* A, int lda, const float2* B,
                                const int* iu, const int* il, size_t m, float2* amps,
                                int accumulate, float2 phi, hipStream_t st);
 
-// amps[t] = phi * C[iu[t] * ldc + il[t]].
-hipError_t launch_gather_amps(const float2* C, int ldc, const int* iu, const int* il, size_t m,
-                              float2* amps, float2 phi, hipStream_t st);
-
 // FP64 sums over m amplitudes: out[0] = sum |a|^2, out[1] = sum |a|^4.
 // `partial` must hold 2 * prob_partial_blocks(m) doubles.
 int prob_partial_blocks(size_t m);
-// launch_gather_amps followed by launch_prob_sums, with the gather and the
-// partial sums in one kernel (same results).
+// amps[t] = phi * C[iu[t] * ldc + il[t]], then launch_prob_sums' sums of
+// them, with the gather and the partial sums in one kernel.
 hipError_t launch_gather_prob_sums(const float2* C, int ldc, const int* iu, const int* il,
                                    size_t m, float2* amps, float2 phi, double* partial,
                                    double* out, hipStream_t st);

@@ -2748,21 +2748,6 @@ hipError_t launch_gathered_dot(int K, const float2* A, int lda, const float2* B,
   return hipGetLastError();
 }
 
-__global__ void k_gather_amps(const float2* __restrict__ C, int ldc, const int* __restrict__ iu,
-                              const int* __restrict__ il, size_t m, float2* __restrict__ amps,
-                              float2 phi) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < m) amps[t] = cmul(C[(size_t)iu[t] * ldc + il[t]], phi);
-}
-
-hipError_t launch_gather_amps(const float2* C, int ldc, const int* iu, const int* il, size_t m,
-                              float2* amps, float2 phi, hipStream_t st) {
-  if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_amps, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, C, ldc,
-                     iu, il, m, amps, phi);
-  return hipGetLastError();
-}
-
 constexpr int kProbThreads = 256;
 constexpr int kProbPerBlock = 1024;
 
@@ -2824,9 +2809,10 @@ k_prob_final(const double* __restrict__ partial, int nb, double* __restrict__ ou
   }
 }
 
-// k_gather_amps and k_prob_partial in one pass: each workgroup gathers its
-// kProbPerBlock amplitudes, writes them, and sums them in the same order as
-// k_prob_partial (the sums are bit-identical to the two-kernel form).
+// The output amplitudes amps[t] = phi C[iu[t] ldc + il[t]] and their FP64
+// partial sums in one pass: each workgroup gathers its kProbPerBlock
+// amplitudes, writes them, and sums them in the same order as k_prob_partial
+// does over stored amplitudes.
 __global__ void __launch_bounds__(kProbThreads)
 k_gather_prob_partial(const float2* __restrict__ C, int ldc, const int* __restrict__ iu,
                       const int* __restrict__ il, size_t m, float2* __restrict__ amps, float2 phi,

@@ -167,6 +167,28 @@ def test_copy_slices_partial_sums():
     p.close()
 
 
+def test_folded_end_cuts_on_odd_copy_counts():
+    """The 42-qubit circuit's lower half has three end cuts, folded into the
+    assembly as 8 groups of K / 8 copies.  Copy ranges of 8 give one copy per
+    group (an odd count: the register-staged FP32 product), a range of 16 two
+    (the direct-to-LDS product); the partial sums of [0, 8) and [8, 16) add up
+    to [0, 16), in FP32 and in split-BF16."""
+    Q = _lib()
+    w = workload("grid6x7_d20")
+    bits, _, _ = product_bitstrings(w.n, w.upper_mask, 64, 64, w.seed_u, w.seed_l)
+    for prec in (0, 1):
+        part = {}
+        for a, b in [(0, 8), (8, 16), (0, 16)]:
+            say(f"case grid6x7_d20 copies [{a},{b}) prec={prec}")
+            p = Q.Plan(w.circuit_text(), w.upper_mask)
+            try:
+                p.run_halves(a, b, bits)
+                part[(a, b)], _ = p.amplitudes(bits, prec)
+            finally:
+                p.close()
+        assert_close(part[(0, 8)] + part[(8, 16)], part[(0, 16)], TOL[prec], f"prec {prec}")
+
+
 def test_argument_errors():
     Q = _lib()
     w = workload("grid4x4_d10")
